@@ -1,0 +1,163 @@
+/*
+ * kde.h -- C ABI of the MI355X (gfx950) binned FFT kernel density estimator
+ * with an unconstrained (full, symmetric positive definite) bandwidth matrix.
+ *
+ * Method: A. Gramacki and J. Gramacki, "FFT-Based Fast Computation of
+ * Multivariate Kernel Density Estimators with Unconstrained Bandwidth
+ * Matrices" (arXiv 1508.02766). The library computes the truncated binned
+ * estimate of Eq. (7),
+ *
+ *     f_j = sum_{|l_k| <= L_k} c_{j-l} k_l ,   k_l = n^-1 K_H(delta_1 l_1, ..., delta_d l_d)
+ *
+ * on an equally spaced grid (Eq. 3, 4) from linearly binned counts c
+ * (Section 2), with K the standard normal density and K_H as in Eq. (1), and
+ * L_k from Eq. (15). The kernel weights cover the whole signed lag box
+ * [-L, L]^d, which is the paper's correction of Wand's ordering (Section 4.2,
+ * Eq. 12-13); the convolution runs through zero-padded radix-16/8/4/2 FFTs
+ * (Eq. 10) written for gfx950.
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major with axis 1 slowest. X is n x d FP64, one sample
+ *     per row. Densities and counts are laid out as M_1 x ... x M_d and entry
+ *     j sits at g_j = lo + j * delta (0-based j).
+ *   - H is a host pointer to d x d FP64 (row-major). X, counts, lags,
+ *     densities, n_dropped and workspaces are device pointers owned by the
+ *     caller. The library allocates no device memory and never frees
+ *     caller memory.
+ *   - Work is enqueued on `stream` (0 = the null stream) and returns before
+ *     it finishes; no call synchronises the device. Host-side validation
+ *     happens before any enqueue, so a non-zero return means nothing ran.
+ *   - Return 0 (KDE_OK) or a negative kde_status; kde_strerror() names it.
+ *     No C++ exception crosses the ABI. Calls are thread-safe.
+ */
+#ifndef KDE_MI355X_H
+#define KDE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic type of the FFT convolution and of densities / lag weights. */
+enum kde_precision { KDE_F32 = 1, KDE_F64 = 2 };
+
+enum kde_status {
+    KDE_OK = 0,
+    KDE_ERR_ARG = -1,       /* null pointer, d not in {1,2,3}, M_k < 2, hi_k <= lo_k,
+                               non-finite box, n < 0 (n < 1 where the estimate divides by n),
+                               bad override, bad precision */
+    KDE_ERR_NOT_SPD = -2,   /* H not finite, not symmetric (|H - H'| > 1e-12 max|H|)
+                               or not positive definite (Cholesky fails) */
+    KDE_ERR_OVERFLOW = -3,  /* n * 2^(d Q) does not fit in uint64 */
+    KDE_ERR_WS = -4,        /* workspace or output buffer smaller than required */
+    KDE_ERR_SIZE = -5,      /* padded FFT length P_k > 4096 on some axis */
+    KDE_ERR_HIP = -6        /* a HIP launch or event call failed */
+};
+
+/* Equally spaced grid, Eq. (3)-(4): g_kj = lo[k] + j delta_k, j = 0..M[k]-1,
+ * delta_k = (hi[k] - lo[k]) / (M[k] - 1). Only the first d entries are read. */
+typedef struct kde_grid {
+    int32_t d;
+    int32_t reserved;
+    int64_t M[3];
+    double lo[3];
+    double hi[3];
+} kde_grid;
+
+/* Options; an all-zero struct (or a NULL pointer) means the defaults. */
+typedef struct kde_params {
+    double tau;               /* Eq. (15) constant; <= 0 selects 3.7 (Section 4.2) */
+    int32_t L[3];             /* > 0: use this L_k instead of Eq. (15) (must be <= M_k - 1);
+                                 0: Eq. (15) */
+    int32_t Q;                /* fixed-point bits of the binning weights; 0: floor(32 / d);
+                                 else 1 <= Q and d Q <= 62 */
+    int32_t prec;             /* KDE_F32 (also when 0) or KDE_F64 */
+    int32_t trace_capacity;   /* optional per-kernel timing, see below */
+    hipEvent_t* trace_events; /* if non-NULL: events[0] is recorded before the first kernel
+                                 and events[i] after the i-th kernel, on `stream`, up to
+                                 trace_capacity events */
+    int32_t* trace_count;     /* if non-NULL: receives the number of events recorded */
+    const char** trace_names; /* if non-NULL: receives a static name for kernel i
+                                 (trace_capacity - 1 entries) */
+} kde_params;
+
+/* Everything the host planner derives for one problem. */
+typedef struct kde_plan {
+    int32_t d;
+    int32_t Q;                /* fixed-point bits; counts are in units of 2^-(d Q) */
+    int32_t prec;
+    int32_t L[3];             /* truncation per axis, Eq. (15) or the override */
+    int32_t P[3];             /* padded FFT length per axis: smallest power of two
+                                 >= max(16, M_k + L_k) */
+    int32_t reserved;
+    double delta[3];          /* bin width, Eq. (4) */
+    double lambda_max;        /* largest eigenvalue of H */
+    double det_H;             /* |H| */
+    double norm;              /* n^-1 (2 pi)^-d/2 |H|^-1/2 = k_0 */
+    int64_t lag_count;        /* prod (2 L_k + 1) */
+    size_t lag_bytes;         /* lag_count * sizeof(real) */
+    size_t conv_ws_bytes;     /* workspace needed by kde_conv */
+    size_t eval_ws_bytes;     /* workspace needed by kde_eval (counts + conv workspace) */
+    size_t density_bytes;     /* prod M_k * sizeof(real) */
+} kde_plan;
+
+/* Plan one problem on the host (no device work, no HIP call).
+ * Validates H (Section 1: symmetric positive definite), the grid and the
+ * options; computes delta (Eq. 4), lambda_max and L (Eq. 15), the padded
+ * lengths P, |H|, the normalising constant k_0 (Eq. 6 with Eq. 1) and the
+ * workspace sizes. n is the sample count used in the 1/n of Eq. (1); it must
+ * be >= 1. `out` receives the plan. */
+int kde_plan_query(const double* H, int64_t n, const kde_grid* grid,
+                   const kde_params* params, kde_plan* out);
+
+/* Linear binning (Section 2, first step; the counts sum to n, Section 3
+ * footnote) of the n samples X (device, n x d FP64) onto the grid, in integer
+ * fixed point: for each axis u = (X_ik - lo_k) / delta_k (one FP64 subtract,
+ * one FP64 divide), j = min(floor u, M_k - 2), q = rint((u - j) 2^Q) with ties
+ * to even; corner b of the cell receives prod_k (b_k ? q_k : 2^Q - q_k).
+ * counts (device, prod M_k uint64) is overwritten, in units of 2^-(dQ); the
+ * result is independent of the order of the samples. Samples with u < 0,
+ * u > M_k - 1 or NaN on some axis are skipped; their number is written to
+ * *n_dropped (device, may be NULL). n = 0 gives all-zero counts.
+ * H is not used; n * 2^(dQ) must fit in uint64. */
+int kde_bin(const double* X, int64_t n, const kde_grid* grid, const kde_params* params,
+            uint64_t* counts, uint64_t* n_dropped, hipStream_t stream);
+
+/* Kernel weights on the signed lag box (Eq. 6 and Eq. 12):
+ * k_l = n^-1 (2 pi)^-d/2 |H|^-1/2 exp(-(delta l)' H^-1 (delta l) / 2) for
+ * l in [-L_1, L_1] x ... x [-L_d, L_d], written to lags (device,
+ * prod (2 L_k + 1) reals of the chosen precision) with entry
+ * [L_1 + l_1, ..., L_d + l_d] holding k_l. lags_bytes is the buffer size. */
+int kde_kernel_grid(const double* H, int64_t n, const kde_grid* grid, const kde_params* params,
+                    void* lags, size_t lags_bytes, hipStream_t stream);
+
+/* The convolution step (Section 2, third step; Eq. 7 via Eq. 10) from
+ * existing fixed-point counts (device, prod M_k uint64, as written by
+ * kde_bin): fills the lag box, transforms it, transforms the zero-padded
+ * counts, multiplies, transforms back and writes the M_1 x ... x M_d window
+ * (scaled by 2^-(dQ) / prod P_k) to density (device, reals of the chosen
+ * precision). n is the total sample count of Eq. (1). ws (device) must hold
+ * plan.conv_ws_bytes and be 256-byte aligned. */
+int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid* grid,
+             const kde_params* params, void* density, void* ws, size_t ws_bytes,
+             hipStream_t stream);
+
+/* The whole estimate: kde_bin into the workspace, then kde_conv.
+ * ws (device, 256-byte aligned) must hold plan.eval_ws_bytes; n_dropped may
+ * be NULL. n must be >= 1. */
+int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid,
+             const kde_params* params, void* density, void* ws, size_t ws_bytes,
+             uint64_t* n_dropped, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* kde_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDE_MI355X_H */

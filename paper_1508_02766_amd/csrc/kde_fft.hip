@@ -1,0 +1,665 @@
+// gfx950 kernels of the convolution step of the binned KDE (Gramacki &
+// Gramacki, arXiv 1508.02766, Section 2 third step, Eq. 7 through the
+// discrete convolution theorem of Eq. 10):
+//
+//   * kfill      lag-box weights k_l = n^-1 K_H(delta l) over [-L, L]^d (Eq. 6, Eq. 12)
+//   * rows_r2c   forward transform along the contiguous (last) axis of real rows,
+//                two rows per complex FFT; input either u64 counts (zero padded)
+//                or lag-box rows placed circularly (lag l at position l mod P)
+//   * cols       forward / fused forward x spectrum x inverse / inverse transforms
+//                along a strided axis; a workgroup owns B adjacent lines so each
+//                global access is a contiguous run of B complex values
+//   * rows_c2r   inverse transform along the contiguous axis back to real rows,
+//                with the 1/prod(P) and fixed-point scale, keeping the M window
+//
+// Every transform is one in-workgroup Stockham FFT of length P = 16..4096:
+// 16 points per thread in registers, a radix-16 stage first, then radix-16 and
+// a final radix-8/4/2 stage, exchanging through padded LDS between stages.
+// Twiddles come from a table of exp(-2 pi i k / 4096) built at compile time in
+// FP64 (rounded once to FP32 for the single-precision kernels).
+//
+// Layout used by the host (row-major, axis 1 slowest, H_d = P_d/2 + 1):
+// the lag box sits circularly in the padded array (negative lags at P - |l|),
+// the counts sit at the origin, so with P_k >= M_k + L_k the circular
+// convolution equals Eq. (7) on the window [0, M_k) of every axis.
+
+#include "kde_internal.h"
+
+namespace kde {
+namespace {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+
+template <typename R>
+struct cpx {
+    R re, im;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> scal(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> conj(cpx<R> a) { return {a.re, -a.im}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> mul_minus_i(cpx<R> a) { return {a.im, -a.re}; }
+
+// ---------------------------------------------------------------------------
+// compile-time twiddle table: exp(-2 pi i k / 4096), k = 0..4095
+// ---------------------------------------------------------------------------
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// Taylor series on [0, pi/4]; 14 terms leave a truncation error far below
+// one FP64 ulp there.
+constexpr double sin_series(double x) {
+    double x2 = x * x, term = x, s = x;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+        s += term;
+    }
+    return s;
+}
+constexpr double cos_series(double x) {
+    double x2 = x * x, term = 1.0, s = 1.0;
+    for (int k = 1; k < 14; ++k) {
+        term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+        s += term;
+    }
+    return s;
+}
+
+struct SinCos {
+    double s, c;
+};
+
+// sin and cos of 2 pi k / N with the argument reduced exactly in integers
+// (quadrant, then reflection about pi/4), N divisible by 8.
+constexpr SinCos sincos_turn(long k, long N) {
+    k %= N;
+    if (k < 0) k += N;
+    const long quarter = N / 4;
+    const long quad = k / quarter, r = k % quarter;
+    double s = 0.0, c = 0.0;
+    if (2 * r <= quarter) {
+        const double x = 2.0 * kPi * static_cast<double>(r) / static_cast<double>(N);
+        s = sin_series(x);
+        c = cos_series(x);
+    } else {
+        const double x = 2.0 * kPi * static_cast<double>(quarter - r) / static_cast<double>(N);
+        s = cos_series(x);
+        c = sin_series(x);
+    }
+    switch (quad) {
+        case 0: return {s, c};
+        case 1: return {c, -s};
+        case 2: return {-s, -c};
+        default: return {-c, s};
+    }
+}
+
+template <typename R>
+struct TwiddleTable {
+    cpx<R> w[kMaxP];
+};
+
+template <typename R>
+constexpr TwiddleTable<R> make_twiddles() {
+    TwiddleTable<R> t{};
+    for (int k = 0; k < kMaxP; ++k) {
+        const SinCos v = sincos_turn(k, kMaxP);
+        t.w[k] = cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
+    }
+    return t;
+}
+
+__device__ constexpr TwiddleTable<float> g_tw32 = make_twiddles<float>();
+__device__ constexpr TwiddleTable<double> g_tw64 = make_twiddles<double>();
+
+template <typename R>
+__device__ __forceinline__ cpx<R> twiddle(int k);
+template <>
+__device__ __forceinline__ cpx<float> twiddle<float>(int k) { return g_tw32.w[k]; }
+template <>
+__device__ __forceinline__ cpx<double> twiddle<double>(int k) { return g_tw64.w[k]; }
+
+// multiply by the compile-time constant exp(-2 pi i m / 16)
+template <int m, typename R>
+__device__ __forceinline__ cpx<R> rot16(cpx<R> a) {
+    constexpr int mm = ((m % 16) + 16) % 16;
+    if constexpr (mm == 0) {
+        return a;
+    } else if constexpr (mm == 4) {
+        return mul_minus_i(a);
+    } else if constexpr (mm == 8) {
+        return cpx<R>{-a.re, -a.im};
+    } else if constexpr (mm == 12) {
+        return cpx<R>{-a.im, a.re};
+    } else {
+        constexpr SinCos v = sincos_turn(mm, 16);
+        return a * cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// register DFTs, forward sign, natural order in and out
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__device__ __forceinline__ void dft4(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {
+    const cpx<R> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_minus_i(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+template <int RAD, typename R>
+__device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
+    if constexpr (RAD == 2) {
+        const cpx<R> t = a[0] - a[1];
+        a[0] = a[0] + a[1];
+        a[1] = t;
+    } else if constexpr (RAD == 4) {
+        dft4(a[0], a[1], a[2], a[3]);
+    } else if constexpr (RAD == 8) {
+        // even and odd halves, then the radix-2 combination with exp(-2 pi i k / 8)
+        dft4(a[0], a[2], a[4], a[6]);
+        dft4(a[1], a[3], a[5], a[7]);
+        const cpx<R> o1 = rot16<2>(a[3]), o2 = rot16<4>(a[5]), o3 = rot16<6>(a[7]);
+        const cpx<R> y0 = a[0] + a[1], y4 = a[0] - a[1];
+        const cpx<R> y1 = a[2] + o1, y5 = a[2] - o1;
+        const cpx<R> y2 = a[4] + o2, y6 = a[4] - o2;
+        const cpx<R> y3 = a[6] + o3, y7 = a[6] - o3;
+        a[0] = y0; a[1] = y1; a[2] = y2; a[3] = y3;
+        a[4] = y4; a[5] = y5; a[6] = y6; a[7] = y7;
+    } else if constexpr (RAD == 16) {
+        // 16 = 4 x 4: length-4 DFTs over n1 (input n = 4 n1 + n2), twiddle
+        // exp(-2 pi i n2 k1 / 16), length-4 DFTs over n2; output k = k1 + 4 k2.
+        dft4(a[0], a[4], a[8], a[12]);
+        dft4(a[1], a[5], a[9], a[13]);
+        dft4(a[2], a[6], a[10], a[14]);
+        dft4(a[3], a[7], a[11], a[15]);
+        // a[n2 + 4 k1] now holds the inner result for (n2, k1)
+        a[5] = rot16<1>(a[5]);
+        a[6] = rot16<2>(a[6]);
+        a[7] = rot16<3>(a[7]);
+        a[9] = rot16<2>(a[9]);
+        a[10] = rot16<4>(a[10]);
+        a[11] = rot16<6>(a[11]);
+        a[13] = rot16<3>(a[13]);
+        a[14] = rot16<6>(a[14]);
+        a[15] = rot16<9>(a[15]);
+        dft4(a[0], a[1], a[2], a[3]);
+        dft4(a[4], a[5], a[6], a[7]);
+        dft4(a[8], a[9], a[10], a[11]);
+        dft4(a[12], a[13], a[14], a[15]);
+        // a[4 k1 + k2] holds output k1 + 4 k2: transpose the 4 x 4 block
+        cpx<R> y[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) y[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = y[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// in-workgroup Stockham FFT of one line of length P
+// ---------------------------------------------------------------------------
+
+// LDS index of line element p: one padding slot after every 16 elements keeps
+// the stride-16 stores of the first stage off a single bank.
+__device__ __forceinline__ int padi(int p) { return p + (p >> 4); }
+
+template <int P>
+struct LineShape {
+    static constexpr int T = P / 16;          // threads per line
+    static constexpr int LDS = P + P / 16;    // padded LDS elements per line
+};
+
+// One radix-RAD pass with NS = product of the earlier radices. Thread t owns
+// the butterflies j = t + T u, u < 16/RAD; butterfly j reads elements
+// j + r P/RAD and writes (j / NS) NS RAD + j % NS + r NS. Element
+// t + T m always lives in register slot m.
+template <typename R, int P, int LS, int RAD, int NS>
+__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t) {
+    constexpr int T = LineShape<P>::T;
+    constexpr int NB = 16 / RAD;
+    constexpr bool kFirst = (NS == 1);
+    constexpr bool kLast = (NS * RAD == P);
+    if constexpr (!kFirst) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = lds[padi(t + T * m) * LS];
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        cpx<R> a[RAD];
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) a[r] = v[u + r * NB];
+        if constexpr (NS > 1) {
+            const int jm = (t + T * u) & (NS - 1);
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) a[r] = a[r] * twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+        }
+        dft<RAD>(a);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[u + r * NB] = a[r];
+    }
+    if constexpr (!kLast) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = t + T * u;
+            const int base = (j / NS) * (NS * RAD) + (j & (NS - 1));
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) lds[padi(base + r * NS) * LS] = v[u + r * NB];
+        }
+    }
+}
+
+// Forward DFT (sign -1) of the line whose element t + T m is in v[m]; on
+// return v[m] holds output t + T m. Every thread of the workgroup must call
+// it (it contains barriers). LS is the LDS distance between padded elements.
+template <typename R, int P, int LS>
+__device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
+    static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
+    fft_stage<R, P, LS, 16, 1>(v, lds, t);
+    if constexpr (P > 16) {
+        constexpr int R1 = (P / 16 >= 16) ? 16 : P / 16;
+        fft_stage<R, P, LS, R1, 16>(v, lds, t);
+        if constexpr (P > 256) fft_stage<R, P, LS, P / 256, 256>(v, lds, t);
+    }
+}
+
+// Unnormalised inverse DFT (sign +1) through conj(F(conj(x))).
+template <typename R, int P, int LS>
+__device__ __forceinline__ void ifft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
+    fft_line<R, P, LS>(v, lds, t);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
+}
+
+template <typename R>
+__device__ __forceinline__ R to_real(uint64_t x) { return static_cast<R>(x); }
+
+template <typename R>
+__device__ __forceinline__ R fexp(R x);
+template <>
+__device__ __forceinline__ float fexp<float>(float x) { return expf(x); }
+template <>
+__device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
+
+// ---------------------------------------------------------------------------
+// kfill: k_l = norm exp(-0.5 l'Al), A_ab = delta_a delta_b (H^-1)_ab (Eq. 6, Eq. 1)
+// ---------------------------------------------------------------------------
+
+template <typename R, int D>
+__global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_t count, int L0, int L1,
+                                                    int L2, R a00, R a01, R a02, R a11, R a12, R a22,
+                                                    R norm) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int64_t rem = i;
+    R l0 = 0, l1 = 0, l2 = 0;
+    if constexpr (D == 3) {
+        const int64_t n2 = 2 * L2 + 1, n1 = 2 * L1 + 1;
+        l2 = static_cast<R>(rem % n2 - L2);
+        rem /= n2;
+        l1 = static_cast<R>(rem % n1 - L1);
+        rem /= n1;
+        l0 = static_cast<R>(rem - L0);
+    } else if constexpr (D == 2) {
+        const int64_t n1 = 2 * L1 + 1;
+        l1 = static_cast<R>(rem % n1 - L1);
+        rem /= n1;
+        l0 = static_cast<R>(rem - L0);
+    } else {
+        l0 = static_cast<R>(rem - L0);
+    }
+    R q = a00 * l0 * l0;
+    if constexpr (D >= 2) q += a11 * l1 * l1 + R(2) * a01 * l0 * l1;
+    if constexpr (D == 3) q += a22 * l2 * l2 + R(2) * (a02 * l0 * l2 + a12 * l1 * l2);
+    lags[i] = norm * fexp<R>(R(-0.5) * q);
+}
+
+// ---------------------------------------------------------------------------
+// rows_r2c: real rows along the contiguous axis -> half spectra (P/2 + 1 bins)
+// ---------------------------------------------------------------------------
+
+template <int P>
+struct RowShape {
+    static constexpr int T = P / 16;
+    static constexpr int B = (256 / T) >= 1 ? 256 / T : 1;   // lines (row pairs) per workgroup
+};
+
+template <typename R, int P, int IN_KIND, bool OUT_REAL>
+__global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ in_, int64_t nrows,
+                                                       int64_t in_ld, int len, void* __restrict__ out_,
+                                                       int64_t out_ld) {
+    using C = cpx<R>;
+    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
+    __shared__ C lds[B * LINE];
+    const int b = threadIdx.x / T, t = threadIdx.x - b * T;
+    const int64_t r0 = 2 * (static_cast<int64_t>(blockIdx.x) * B + b), r1 = r0 + 1;
+    const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
+    C v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int p = t + T * m;
+        R x = 0, y = 0;
+        if constexpr (IN_KIND == kRowCountsU64) {
+            const uint64_t* in = static_cast<const uint64_t*>(in_);
+            if (p < len) {
+                if (ok0) x = to_real<R>(in[r0 * in_ld + p]);
+                if (ok1) y = to_real<R>(in[r1 * in_ld + p]);
+            }
+        } else {
+            const R* in = static_cast<const R*>(in_);
+            const int idx = p <= len ? p + len : (p >= P - len ? p - P + len : -1);
+            if (idx >= 0) {
+                if (ok0) x = in[r0 * in_ld + idx];
+                if (ok1) y = in[r1 * in_ld + idx];
+            }
+        }
+        v[m] = C{x, y};
+    }
+    C* line = lds + b * LINE;
+    fft_line<R, P, 1>(v, line, t);
+    // split Z = X + iY of two real rows: X_k = (Z_k + conj Z_-k)/2, Y_k = (Z_k - conj Z_-k)/(2i)
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) line[padi(t + T * m)] = v[m];
+    __syncthreads();
+    const R h = R(0.5);
+    for (int k = t; k <= P / 2; k += T) {
+        const C zk = line[padi(k)], zn = line[padi((P - k) & (P - 1))];
+        const C X{(zk.re + zn.re) * h, (zk.im - zn.im) * h};
+        const C Y{(zk.im + zn.im) * h, (zn.re - zk.re) * h};
+        if constexpr (OUT_REAL) {
+            R* out = static_cast<R*>(out_);
+            if (ok0) out[r0 * out_ld + k] = X.re;
+            if (ok1) out[r1 * out_ld + k] = Y.re;
+        } else {
+            C* out = static_cast<C*>(out_);
+            if (ok0) out[r0 * out_ld + k] = X;
+            if (ok1) out[r1 * out_ld + k] = Y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rows_c2r: half spectra -> real rows, scaled, window [0, mout)
+// ---------------------------------------------------------------------------
+
+template <typename R, int P, bool MULT>
+__global__ __launch_bounds__(256) void rows_c2r_kernel(const cpx<R>* __restrict__ in, int64_t nrows,
+                                                       int64_t in_ld, const R* __restrict__ mult,
+                                                       R* __restrict__ out, int64_t out_ld, int mout,
+                                                       R scale) {
+    using C = cpx<R>;
+    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
+    __shared__ C lds[B * LINE];
+    const int b = threadIdx.x / T, t = threadIdx.x - b * T;
+    const int64_t r0 = 2 * (static_cast<int64_t>(blockIdx.x) * B + b), r1 = r0 + 1;
+    const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
+    C v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int p = t + T * m;
+        const bool upper = p > P / 2;
+        const int src = upper ? P - p : p;
+        C X{0, 0}, Y{0, 0};
+        if (ok0) X = in[r0 * in_ld + src];
+        if (ok1) Y = in[r1 * in_ld + src];
+        if (upper) {
+            X = conj(X);
+            Y = conj(Y);
+        }
+        if constexpr (MULT) {
+            const R kk = mult[src];
+            X = scal(X, kk);
+            Y = scal(Y, kk);
+        }
+        v[m] = C{X.re - Y.im, X.im + Y.re};   // Z = X + iY
+    }
+    ifft_line<R, P, 1>(v, lds + b * LINE, t);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int p = t + T * m;
+        if (p < mout) {
+            if (ok0) out[r0 * out_ld + p] = v[m].re * scale;
+            if (ok1) out[r1 * out_ld + p] = v[m].im * scale;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cols: transforms along a strided axis, B adjacent lines per workgroup
+// ---------------------------------------------------------------------------
+
+template <typename R, int P>
+struct ColShape {
+    static constexpr int T = P / 16;
+    static constexpr int kLineBytes = LineShape<P>::LDS * static_cast<int>(sizeof(cpx<R>));
+    static constexpr int kCap = 73728 / kLineBytes;                 // at most 72 KiB of LDS
+    static constexpr int kThr = 1024 / T;
+    static constexpr int kRaw = kCap < kThr ? (kCap < 16 ? kCap : 16) : (kThr < 16 ? kThr : 16);
+    static constexpr int B = kRaw >= 16 ? 16 : kRaw >= 8 ? 8 : kRaw >= 4 ? 4 : kRaw >= 2 ? 2 : 1;
+    static constexpr int THREADS = T * B;
+};
+
+template <typename R, int P, int MODE>
+__global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs a) {
+    using C = cpx<R>;
+    constexpr int T = ColShape<R, P>::T, B = ColShape<R, P>::B;
+    __shared__ C lds[B * LineShape<P>::LDS];
+    const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * B + b;
+    const int64_t o = blockIdx.y;
+    const bool act = w < a.W;
+    const C* in = static_cast<const C*>(a.in) + o * a.in_os + w;
+    C v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int p = t + T * m;
+        C x{0, 0};
+        if constexpr (MODE == kColFwdPrefix || MODE == kColConv) {
+            if (act && p < a.len) x = in[p * a.in_ps];
+        } else if constexpr (MODE == kColFwdCirc || MODE == kColFwdCircReal) {
+            const int idx = p <= a.len ? p + a.len : (p >= P - a.len ? p - P + a.len : -1);
+            if (act && idx >= 0) x = in[idx * a.in_ps];
+        } else {   // kColInvPrefix
+            if (act) x = in[p * a.in_ps];
+        }
+        v[m] = x;
+    }
+    if constexpr (MODE == kColInvPrefix) {
+        ifft_line<R, P, B>(v, lds + b, t);
+    } else {
+        fft_line<R, P, B>(v, lds + b, t);
+    }
+    if constexpr (MODE == kColConv) {
+        const R* kh = static_cast<const R*>(a.khat) + w;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int p = t + T * m;
+            const R kk = act ? kh[p * a.k_ps] : R(0);
+            v[m] = scal(v[m], kk);
+        }
+        ifft_line<R, P, B>(v, lds + b, t);
+    }
+    if (!act) return;
+    if constexpr (MODE == kColFwdCircReal) {
+        R* out = static_cast<R*>(a.out) + o * a.out_os + w;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m].re;
+    } else if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
+        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m];
+    } else {   // kColConv (in place) and kColInvPrefix: keep [0, mout)
+        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int p = t + T * m;
+            if (p < a.mout) out[p * a.out_ps] = v[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename R, int D>
+hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* lags, hipStream_t s) {
+    int64_t count = 1;
+    for (int k = 0; k < D; ++k) count *= 2 * L[k] + 1;
+    const int64_t blocks = ceil_div(count, 256);
+    hipLaunchKernelGGL((kfill_kernel<R, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       static_cast<R*>(lags), count, L[0], D > 1 ? L[1] : 0, D > 2 ? L[2] : 0,
+                       static_cast<R>(A[0]), static_cast<R>(A[1]), static_cast<R>(A[2]),
+                       static_cast<R>(A[4]), static_cast<R>(A[5]), static_cast<R>(A[8]),
+                       static_cast<R>(norm));
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t rows_r2c_launch(int kind, const void* in, int64_t nrows, int64_t in_ld, int len, void* out,
+                           int64_t out_ld, bool out_real, hipStream_t s) {
+    const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
+    const dim3 g(static_cast<unsigned>(blocks)), blk(256);
+    if (kind == kRowCountsU64) {
+        if (out_real)
+            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, true>), g, blk, 0, s, in, nrows, in_ld,
+                               len, out, out_ld);
+        else
+            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false>), g, blk, 0, s, in, nrows, in_ld,
+                               len, out, out_ld);
+    } else {
+        if (out_real)
+            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowLagsCirc, true>), g, blk, 0, s, in, nrows, in_ld,
+                               len, out, out_ld);
+        else
+            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowLagsCirc, false>), g, blk, 0, s, in, nrows, in_ld,
+                               len, out, out_ld);
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t rows_c2r_launch(const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
+                           int64_t out_ld, int mout, double scale, hipStream_t s) {
+    const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
+    const dim3 g(static_cast<unsigned>(blocks)), blk(256);
+    if (mult)
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, static_cast<const cpx<R>*>(in), nrows,
+                           in_ld, static_cast<const R*>(mult), static_cast<R*>(out), out_ld, mout,
+                           static_cast<R>(scale));
+    else
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false>), g, blk, 0, s, static_cast<const cpx<R>*>(in), nrows,
+                           in_ld, static_cast<const R*>(nullptr), static_cast<R*>(out), out_ld, mout,
+                           static_cast<R>(scale));
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
+    constexpr int B = ColShape<R, P>::B;
+    const dim3 g(static_cast<unsigned>(ceil_div(a.W, B)), static_cast<unsigned>(a.outer));
+    const dim3 blk(ColShape<R, P>::THREADS);
+    switch (mode) {
+        case kColFwdPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdPrefix>), g, blk, 0, s, a); break;
+        case kColFwdCirc: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCirc>), g, blk, 0, s, a); break;
+        case kColFwdCircReal: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCircReal>), g, blk, 0, s, a); break;
+        case kColConv: hipLaunchKernelGGL((cols_kernel<R, P, kColConv>), g, blk, 0, s, a); break;
+        case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix>), g, blk, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+#define KDE_FOR_EACH_P(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+template <typename R>
+hipError_t rows_r2c_any(int P, int kind, const void* in, int64_t nrows, int64_t in_ld, int len, void* out,
+                        int64_t out_ld, bool out_real, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return rows_r2c_launch<R, PP>(kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t rows_c2r_any(int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
+                        int64_t out_ld, int mout, double scale, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return rows_c2r_launch<R, PP>(in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t cols_any(int P, int mode, const ColArgs& a, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return cols_launch<R, PP>(mode, a, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], double norm, void* lags,
+                        hipStream_t s) {
+    if (prec == 2) {
+        if (d == 1) return kfill_launch<double, 1>(L, A, norm, lags, s);
+        if (d == 2) return kfill_launch<double, 2>(L, A, norm, lags, s);
+        return kfill_launch<double, 3>(L, A, norm, lags, s);
+    }
+    if (d == 1) return kfill_launch<float, 1>(L, A, norm, lags, s);
+    if (d == 2) return kfill_launch<float, 2>(L, A, norm, lags, s);
+    return kfill_launch<float, 3>(L, A, norm, lags, s);
+}
+
+hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, int64_t nrows, int64_t in_ld,
+                           int len, void* out, int64_t out_ld, bool out_real, hipStream_t s) {
+    if (prec == 2) return rows_r2c_any<double>(P, input_kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
+    return rows_r2c_any<float>(P, input_kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
+}
+
+hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult,
+                           void* out, int64_t out_ld, int mout, double scale, hipStream_t s) {
+    if (prec == 2) return rows_c2r_any<double>(P, in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+    return rows_c2r_any<float>(P, in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+}
+
+hipError_t launch_cols(int prec, int P, int mode, const ColArgs& a, hipStream_t s) {
+    if (prec == 2) return cols_any<double>(P, mode, a, s);
+    return cols_any<float>(P, mode, a, s);
+}
+
+}  // namespace kde

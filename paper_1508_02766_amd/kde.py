@@ -1,0 +1,331 @@
+"""ctypes binding of libkde.so, the gfx950 binned FFT KDE library.
+
+Argument marshalling only: every step of the estimate runs in the library's
+HIP kernels. PyTorch supplies device memory (tensors) and the current stream.
+The names and semantics follow include/kde.h:
+
+    kde_plan_query(H, n, grid, **opts)          -> dict (host planner, no device work)
+    kde_bin(X, grid, **opts)                    -> (counts, n_dropped)
+    kde_kernel_grid(H, n, grid, **opts)         -> lag-box weights
+    kde_conv(counts, n, H, grid, **opts)        -> density from counts
+    kde_eval(X, H, grid, **opts)                -> (density, n_dropped)
+    kde_strerror(code)                          -> str
+
+``grid`` is ``(lo, hi, M)`` (per-axis sequences) or a ``KdeGrid``. Options:
+``prec`` ("f32" default, or "f64"), ``tau``, ``L`` (per-axis override),
+``Q`` (fixed-point bits), ``trace_events`` (list of raw hipEvent_t handles
+as ints) with ``trace`` (a dict that receives ``count`` and ``names``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
+
+KDE_F32, KDE_F64 = 1, 2
+_PREC = {"f32": KDE_F32, "f64": KDE_F64, KDE_F32: KDE_F32, KDE_F64: KDE_F64, None: KDE_F32}
+_TDTYPE = {KDE_F32: torch.float32, KDE_F64: torch.float64}
+
+
+class KdeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {kde_strerror(code)} (status {code})")
+        self.code = code
+
+
+class KdeGrid(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("reserved", ctypes.c_int32), ("M", ctypes.c_int64 * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class KdeParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * 3), ("Q", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
+                ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
+                ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
+
+
+class KdePlan(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("Q", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("L", ctypes.c_int32 * 3), ("P", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
+                ("delta", ctypes.c_double * 3), ("lambda_max", ctypes.c_double), ("det_H", ctypes.c_double),
+                ("norm", ctypes.c_double), ("lag_count", ctypes.c_int64), ("lag_bytes", ctypes.c_size_t),
+                ("conv_ws_bytes", ctypes.c_size_t), ("eval_ws_bytes", ctypes.c_size_t),
+                ("density_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_strerror")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_1508_02766_amd.build` "
+                              "(there is no CPU fallback for the estimator)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+        G, Pp = ctypes.POINTER(KdeGrid), ctypes.POINTER(KdeParams)
+        L.kde_plan_query.argtypes = [vp, i64, G, Pp, ctypes.POINTER(KdePlan)]
+        L.kde_bin.argtypes = [vp, i64, G, Pp, vp, vp, vp]
+        L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
+        L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
+        L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
+        L.kde_strerror.argtypes = [ctypes.c_int]
+        L.kde_strerror.restype = ctypes.c_char_p
+        for name in EXPORTS[:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def kde_strerror(code: int) -> str:
+    return lib().kde_strerror(int(code)).decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def make_grid(lo, hi, M) -> KdeGrid:
+    lo = np.atleast_1d(np.asarray(lo, dtype=np.float64))
+    hi = np.atleast_1d(np.asarray(hi, dtype=np.float64))
+    M = np.atleast_1d(np.asarray(M, dtype=np.int64))
+    d = int(M.size)
+    if lo.size != d or hi.size != d or not 1 <= d <= 3:
+        raise ValueError("lo, hi and M need one entry per axis, 1 <= d <= 3")
+    g = KdeGrid()
+    g.d = d
+    for k in range(d):
+        g.M[k], g.lo[k], g.hi[k] = int(M[k]), float(lo[k]), float(hi[k])
+    return g
+
+
+def _grid(grid) -> KdeGrid:
+    return grid if isinstance(grid, KdeGrid) else make_grid(*grid)
+
+
+def _grid_shape(g: KdeGrid):
+    return tuple(int(g.M[k]) for k in range(g.d))
+
+
+def _params(prec=None, tau=None, L=None, Q=None, trace_events=None, trace=None):
+    p = KdeParams()
+    p.prec = _PREC.get(prec, prec)
+    if tau is not None:
+        p.tau = float(tau)
+    if L is not None:
+        for k, v in enumerate(L):
+            p.L[k] = int(v)
+    if Q is not None:
+        p.Q = int(Q)
+    keep = []
+    if trace_events:
+        arr = (ctypes.c_void_p * len(trace_events))(*[int(e) for e in trace_events])
+        cnt = ctypes.c_int32(0)
+        names = (ctypes.c_char_p * len(trace_events))()
+        p.trace_capacity = len(trace_events)
+        p.trace_events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+        p.trace_count = ctypes.pointer(cnt)
+        p.trace_names = ctypes.cast(names, ctypes.POINTER(ctypes.c_char_p))
+        keep = [arr, cnt, names, trace]
+    return p, keep
+
+
+def _finish_trace(keep):
+    if keep and keep[3] is not None:
+        arr, cnt, names, trace = keep
+        n = cnt.value
+        trace["count"] = n
+        trace["names"] = [names[i].decode() for i in range(max(n - 1, 0))]
+
+
+def _H(H, d: int):
+    Hn = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(d, d))
+    return Hn, Hn.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise KdeError(code, where)
+
+
+def _need_cuda(t: torch.Tensor, dtype, name: str):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def kde_plan_query(H, n: int, grid, **opts) -> dict:
+    g = _grid(grid)
+    p, _ = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    out = KdePlan()
+    _check(lib().kde_plan_query(Hp, int(n), ctypes.byref(g), ctypes.byref(p), ctypes.byref(out)), "kde_plan_query")
+    d = out.d
+    return {
+        "d": d, "Q": out.Q, "prec": out.prec, "L": tuple(out.L[:d]), "P": tuple(out.P[:d]),
+        "delta": tuple(out.delta[:d]), "lambda_max": out.lambda_max, "det_H": out.det_H, "norm": out.norm,
+        "lag_count": out.lag_count, "lag_bytes": out.lag_bytes, "conv_ws_bytes": out.conv_ws_bytes,
+        "eval_ws_bytes": out.eval_ws_bytes, "density_bytes": out.density_bytes,
+    }
+
+
+def _workspace(nbytes: int, device, ws=None) -> torch.Tensor:
+    if ws is None:
+        ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if ws.numel() < nbytes or ws.data_ptr() % 256:
+        raise ValueError("workspace too small or not 256-byte aligned")
+    return ws
+
+
+def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, **opts):
+    """Fixed-point counts (uint64 in units 2^-dQ, returned as a torch.uint64 tensor) and n_dropped."""
+    g = _grid(grid)
+    _need_cuda(X, torch.float64, "X")
+    if X.dim() != 2 or X.shape[1] != g.d:
+        raise ValueError("X must be (n, d)")
+    dev = X.device
+    if counts is None:
+        counts = torch.empty(_grid_shape(g), dtype=torch.uint64, device=dev)
+    if n_dropped is None:
+        n_dropped = torch.empty(1, dtype=torch.uint64, device=dev)
+    p, keep = _params(**opts)
+    _check(lib().kde_bin(_ptr(X), X.shape[0], ctypes.byref(g), ctypes.byref(p), _ptr(counts), _ptr(n_dropped),
+                         _stream(dev)), "kde_bin")
+    _finish_trace(keep)
+    return counts, n_dropped
+
+
+def kde_kernel_grid(H, n: int, grid, out=None, device="cuda", **opts) -> torch.Tensor:
+    g = _grid(grid)
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    shape = tuple(2 * L + 1 for L in plan["L"])
+    dt = _TDTYPE[plan["prec"]]
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=device)
+    _need_cuda(out, dt, "out")
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    _check(lib().kde_kernel_grid(Hp, int(n), ctypes.byref(g), ctypes.byref(p), _ptr(out),
+                                 out.numel() * out.element_size(), _stream(out.device)), "kde_kernel_grid")
+    _finish_trace(keep)
+    return out
+
+
+def kde_conv(counts: torch.Tensor, n: int, H, grid, out=None, ws=None, **opts) -> torch.Tensor:
+    g = _grid(grid)
+    if not (counts.is_cuda and counts.dtype in (torch.uint64, torch.int64) and counts.is_contiguous()):
+        raise TypeError("counts must be a contiguous uint64 CUDA tensor")
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    dt = _TDTYPE[plan["prec"]]
+    dev = counts.device
+    if out is None:
+        out = torch.empty(_grid_shape(g), dtype=dt, device=dev)
+    _need_cuda(out, dt, "out")
+    ws = _workspace(plan["conv_ws_bytes"], dev, ws)
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    _check(lib().kde_conv(_ptr(counts), int(n), Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws),
+                          ws.numel(), _stream(dev)), "kde_conv")
+    _finish_trace(keep)
+    return out
+
+
+def kde_eval(X: torch.Tensor, H, grid, out=None, ws=None, n_dropped=None, **opts):
+    """The binned estimate on the grid (Eq. 7) and the number of samples outside the grid box."""
+    g = _grid(grid)
+    _need_cuda(X, torch.float64, "X")
+    if X.dim() != 2 or X.shape[1] != g.d:
+        raise ValueError("X must be (n, d)")
+    n = X.shape[0]
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    dt = _TDTYPE[plan["prec"]]
+    dev = X.device
+    if out is None:
+        out = torch.empty(_grid_shape(g), dtype=dt, device=dev)
+    _need_cuda(out, dt, "out")
+    ws = _workspace(plan["eval_ws_bytes"], dev, ws)
+    if n_dropped is None:
+        n_dropped = torch.empty(1, dtype=torch.uint64, device=dev)
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    _check(lib().kde_eval(_ptr(X), n, Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(),
+                          _ptr(n_dropped), _stream(dev)), "kde_eval")
+    _finish_trace(keep)
+    return out, n_dropped
+
+
+class PreparedCall:
+    """A library call with every argument marshalled once, for repeated launches
+    (benchmarks, serving loops): ``call()`` enqueues the work on the stream that
+    was current when it was prepared and raises on a non-zero status."""
+
+    def __init__(self, fn, args, keep, name):
+        self._fn, self._args, self._keep, self._name = fn, args, keep, name
+
+    def __call__(self):
+        _check(self._fn(*self._args), self._name)
+
+    def trace(self) -> dict:
+        out = {}
+        if self._keep:
+            arr, cnt, names, _ = self._keep
+            _finish_trace([arr, cnt, names, out])
+        return out
+
+
+def prepare_eval(X: torch.Tensor, H, grid, out: torch.Tensor, ws: torch.Tensor, n_dropped=None,
+                 **opts) -> PreparedCall:
+    g = _grid(grid)
+    _need_cuda(X, torch.float64, "X")
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    args = (_ptr(X), X.shape[0], Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(),
+            _ptr(n_dropped), _stream(X.device))
+    return _Prepared(lib().kde_eval, args, keep, (g, p, Hn), "kde_eval")
+
+
+def prepare_conv(counts: torch.Tensor, n: int, H, grid, out: torch.Tensor, ws: torch.Tensor, **opts) -> PreparedCall:
+    g = _grid(grid)
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    args = (_ptr(counts), int(n), Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(),
+            _stream(counts.device))
+    return _Prepared(lib().kde_conv, args, keep, (g, p, Hn), "kde_conv")
+
+
+def prepare_bin(X: torch.Tensor, grid, counts: torch.Tensor, n_dropped=None, **opts) -> PreparedCall:
+    g = _grid(grid)
+    _need_cuda(X, torch.float64, "X")
+    p, keep = _params(**opts)
+    args = (_ptr(X), X.shape[0], ctypes.byref(g), ctypes.byref(p), _ptr(counts), _ptr(n_dropped),
+            _stream(X.device))
+    return _Prepared(lib().kde_bin, args, keep, (g, p), "kde_bin")
+
+
+class _Prepared(PreparedCall):
+    def __init__(self, fn, args, keep, owned, name):
+        super().__init__(fn, args, keep, name)
+        self._owned = owned          # keeps the ctypes structs and H alive

@@ -1,0 +1,278 @@
+"""Parity of the gfx950 path (through the C ABI) with the FP64 oracle.
+
+Bars: grid counts bit-exact (integer fixed point); lag weights within 2e-6 of
+k_0 in FP32 and 1e-14 in FP64; densities within 1e-5 of the grid maximum in
+FP32 and 1e-12 in FP64. Sizes span several FFT tiles with ragged tails; the
+full-size workloads are compared in full (2-D) or on sampled grid points the
+oracle evaluates one by one (3-D).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1508_02766_amd as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-12}
+DEV = "cuda:0"
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), device=DEV)
+
+
+def _counts(X, lo, hi, M, **opts):
+    c, nd = K.kde_bin(_dev(X), (lo, hi, M), **opts)
+    torch.cuda.synchronize()
+    return c.cpu().numpy(), int(nd.cpu().numpy()[0])
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+# --------------------------------------------------------------------------
+# binning: bit-exact
+# --------------------------------------------------------------------------
+
+def test_bin_hand_cases_bit_exact():
+    X = np.array([[1.0, 1.0], [1.5, 2.5], [3.0, 3.0], [0.25, 0.0], [0.1, 2.0], [1.0 + 3.0 / 2 ** 17, 0.0],
+                  [1.0 + 5.0 / 2 ** 17, 1.0], [-0.1, 1.0], [1.0, 3.0000000001], [np.nan, 1.0], [np.inf, 0.0],
+                  [0.0, 0.0], [2.9999999999999996, 0.5]])
+    ref, rnd = O.bin_fixed(X, [0.0, 0.0], [3.0, 3.0], (4, 4))
+    got, gnd = _counts(X, [0.0, 0.0], [3.0, 3.0], (4, 4))
+    assert gnd == rnd == 4
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", ["mix2d_small", "mix2d_512", "mix3d_128"])
+def test_bin_workloads_bit_exact(name):
+    w = W.WORKLOADS[name]()
+    ref, rnd = O.bin_fixed(w.X, w.lo, w.hi, w.M)
+    got, gnd = _counts(w.X, w.lo, w.hi, w.M)
+    assert gnd == rnd
+    assert got.dtype == np.uint64 and np.array_equal(got, ref)
+    assert int(got.sum(dtype=np.uint64)) == (w.n - gnd) * 2 ** (w.d * O.default_Q(w.d))
+
+
+@pytest.mark.parametrize("d,M,Q", [(1, (1000,), None), (1, (7,), 20), (2, (37, 50), None), (2, (2, 2), None),
+                                   (3, (5, 9, 17), None), (3, (40, 33, 2), 8), (2, (300, 3), 24)])
+def test_bin_ragged_bit_exact(d, M, Q):
+    rng = np.random.default_rng(100 + d)
+    n = 50_000
+    X = rng.normal(size=(n, d)) * 1.2
+    X[:50] = np.nan
+    lo, hi = np.full(d, -2.5), np.full(d, 2.5)
+    # samples exactly on nodes and on the box faces
+    g = O.grid_axes(lo, hi, M)
+    for i in range(200):
+        X[100 + i] = [g[k][rng.integers(0, M[k])] for k in range(d)]
+    X[400] = hi
+    X[401] = lo
+    ref, rnd = O.bin_fixed(X, lo, hi, M, Q)
+    got, gnd = _counts(X, lo, hi, M, Q=Q)
+    assert gnd == rnd
+    assert np.array_equal(got, ref)
+
+
+def test_bin_empty_and_order_independent():
+    got, gnd = _counts(np.zeros((0, 2)), [0.0, 0.0], [1.0, 1.0], (8, 8))
+    assert gnd == 0 and not got.any()
+    w = W.mix2d_small()
+    a, _ = _counts(w.X, w.lo, w.hi, w.M)
+    perm = np.random.default_rng(0).permutation(w.n)
+    b, _ = _counts(w.X[perm], w.lo, w.hi, w.M)
+    assert np.array_equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# lag weights (Eq. 6, Eq. 12)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("name", ["mix2d_small", "mix2d_512", "mix3d_128"])
+def test_kernel_grid(prec, name):
+    w = W.WORKLOADS[name]()
+    p = O.plan(w.H, w.lo, w.hi, w.M, w.n)
+    ref = O.lag_weights(w.H, p["delta"], p["L"], w.n)
+    got = K.kde_kernel_grid(w.H, w.n, (w.lo, w.hi, w.M), prec=prec, device=DEV)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert got.shape == ref.shape
+    tol = 2e-6 if prec == "f32" else 1e-14
+    assert np.max(np.abs(got - ref)) <= tol * ref.max()
+
+
+# --------------------------------------------------------------------------
+# convolution from exact counts (Eq. 7): isolates the FFT path
+# --------------------------------------------------------------------------
+
+CONV_CASES = [
+    # (d, M, seed, L override, H scale)
+    (1, (200,), 1, None, 1.0),
+    (1, (2000,), 2, None, 1.0),            # P = 4096 (largest length)
+    (1, (9,), 3, None, 1.0),               # P = 16 (smallest length)
+    (2, (64, 64), 4, None, 1.0),
+    (2, (37, 50), 5, None, 1.0),           # ragged, odd row count
+    (2, (129, 300), 6, None, 3.0),
+    (2, (2050, 12), 7, None, 0.5),         # P_1 = 4096
+    (2, (1000, 40), 12, None, 0.3),        # P_1 = 2048
+    (2, (24, 19), 8, (23, 18), 1.0),       # full lag box, L = M - 1
+    (3, (20, 17, 23), 9, None, 1.0),
+    (3, (33, 40, 31), 10, None, 2.0),
+    (3, (6, 5, 4), 11, (5, 4, 3), 1.0),
+]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("case", CONV_CASES, ids=[f"d{c[0]}-{'x'.join(map(str, c[1]))}" for c in CONV_CASES])
+def test_conv_from_counts(prec, case):
+    d, M, seed, Lovr, hs = case
+    w = W.small_mixture(seed=seed, d=d, n=4000, M=M, H_scale=hs)
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, L=Lovr)
+    counts = _dev(info["counts"])
+    got = K.kde_conv(counts, w.n, w.H, (w.lo, w.hi, w.M), prec=prec, L=Lovr)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert got.shape == f.shape
+    assert _rel(got, f) <= TOL[prec], (case, _rel(got, f))
+
+
+# --------------------------------------------------------------------------
+# the whole estimate
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_small_workload(prec):
+    w = W.mix2d_small()
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    assert int(nd.cpu().numpy()[0]) == 0
+    assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
+def test_eval_small_diagonal_and_full_differ():
+    w = W.mix2d_small()
+    Hd = np.diag(np.diag(w.H))
+    g = (w.lo, w.hi, w.M)
+    full = K.kde_eval(_dev(w.X), w.H, g, prec="f64")[0].cpu().numpy()
+    diag = K.kde_eval(_dev(w.X), Hd, g, prec="f64")[0].cpu().numpy()
+    fd, _ = O.kde_binned(w.X, Hd, w.lo, w.hi, w.M)
+    assert _rel(diag, fd) <= TOL["f64"]
+    assert _rel(full, diag) > 0.05
+
+
+@pytest.fixture(scope="module")
+def ref2d512():
+    w = W.mix2d_512()
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+    return w, f, info
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_2d_512_full(ref2d512, prec):
+    w, f, info = ref2d512
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    assert int(nd.cpu().numpy()[0]) == info["n_dropped"]
+    assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def ref3d128():
+    w = W.mix3d_128()
+    p = O.plan(w.H, w.lo, w.hi, w.M, w.n)
+    counts, nd = O.bin_fixed(w.X, w.lo, w.hi, w.M)
+    c = O.counts_to_c(counts, 3)
+    k = O.lag_weights(w.H, p["delta"], p["L"], w.n)
+    return w, p, counts, c, k
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_3d_128_sampled(ref3d128, prec):
+    w, p, counts, c, k = ref3d128
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    rng = np.random.default_rng(7)
+    pts = [tuple(int(v) for v in rng.integers(0, 128, size=3)) for _ in range(1500)]
+    imax = np.unravel_index(np.argmax(got), got.shape)
+    pts += [tuple(int(v) for v in imax), (0, 0, 0), (127, 127, 127), (0, 127, 64)]
+    # points near the mass: a box around the maximum
+    for dd in range(-3, 4):
+        pts.append(tuple(int(np.clip(imax[a] + dd * (a + 1), 0, 127)) for a in range(3)))
+    ref = O.conv_direct_at(c, k, p["L"], pts)
+    gmax = float(np.max(got))
+    err = np.max(np.abs(np.array([got[q] for q in pts]) - ref))
+    assert err <= TOL[prec] * gmax, err / gmax
+    # total mass: at most the normal tail beyond tau is lost
+    mass = got.sum(dtype=np.float64) * np.prod(p["delta"])
+    assert 0.99 <= mass <= 1.0 + 1e-4
+
+
+def test_eval_3d_128_bins_exact_inside_eval(ref3d128):
+    """kde_eval bins into its workspace with the same kernel: the counts it convolves are the oracle's."""
+    w, p, counts, c, k = ref3d128
+    plan = K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M))
+    ws = torch.empty(plan["eval_ws_bytes"], dtype=torch.uint8, device=DEV)
+    K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), ws=ws)
+    torch.cuda.synchronize()
+    ncell = int(np.prod(w.M))
+    got = ws[: ncell * 8].view(torch.uint64).cpu().numpy().reshape(w.M)
+    assert np.array_equal(got, counts)
+
+
+def test_eval_deterministic():
+    w = W.mix2d_512(n=200_000, M=256)
+    g = (w.lo, w.hi, w.M)
+    X = _dev(w.X)
+    a = K.kde_eval(X, w.H, g)[0].cpu().numpy()
+    b = K.kde_eval(X, w.H, g)[0].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_eval_single_sample_is_gaussian():
+    """n = 1 on a node gives exactly N(X_1, H) inside the lag box (closed form)."""
+    H = np.array([[0.09, 0.06], [0.06, 0.08]])
+    lo, hi, M = np.array([-2.0, -2.0]), np.array([2.0, 2.0]), (41, 41)
+    g = O.grid_axes(lo, hi, M)
+    X = np.array([[g[0][17], g[1][23]]])
+    f, info = O.kde_binned(X, H, lo, hi, M)
+    got = K.kde_eval(_dev(X), H, (lo, hi, M), prec="f64")[0].cpu().numpy()
+    assert _rel(got, f) <= 1e-12
+
+
+def test_eval_errors_on_gpu():
+    w = W.mix2d_small()
+    X = _dev(w.X)
+    with pytest.raises(ValueError):
+        K.kde_eval(X, w.H, (w.lo, w.hi, w.M), ws=torch.empty(64, dtype=torch.uint8, device=DEV))
+    with pytest.raises(K.KdeError) as e:
+        K.kde_eval(X, np.array([[0.09, 0.2], [0.2, 0.08]]), (w.lo, w.hi, w.M))
+    assert e.value.code == -2
+
+
+def test_trace_events_record_every_kernel():
+    import ctypes
+    hip = K.lib()          # hipEvent* resolved in the runtime the library links
+    evs = []
+    for _ in range(16):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e.value)
+    w = W.mix2d_small()
+    tr = {}
+    K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), trace_events=evs, trace=tr)
+    torch.cuda.synchronize()
+    assert tr["count"] == len(tr["names"]) + 1
+    assert tr["names"][:3] == ["zero_counts", "zero_dropped", "bin"] and tr["names"][-1] == "c2r"
+    for i in range(1, tr["count"]):
+        ms = ctypes.c_float()
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(evs[i - 1]), ctypes.c_void_p(evs[i])) == 0
+        assert ms.value >= 0.0
+    for e in evs:
+        hip.hipEventDestroy(ctypes.c_void_p(e))
