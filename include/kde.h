@@ -101,8 +101,10 @@ typedef struct kde_plan {
     int64_t lag_count;        /* prod (2 L_k + 1) */
     size_t lag_bytes;         /* lag_count * sizeof(real) */
     size_t conv_ws_bytes;     /* workspace needed by kde_conv */
-    size_t eval_ws_bytes;     /* workspace needed by kde_eval (counts + conv workspace) */
+    size_t eval_ws_bytes;     /* workspace needed by kde_eval (counts, binning and
+                                 convolution workspaces) */
     size_t density_bytes;     /* prod M_k * sizeof(real) */
+    size_t bin_ws_bytes;      /* workspace needed by kde_bin (0: none) */
 } kde_plan;
 
 /* Plan one problem on the host (no device work, no HIP call).
@@ -110,7 +112,8 @@ typedef struct kde_plan {
  * options; computes delta (Eq. 4), lambda_max and L (Eq. 15), the padded
  * lengths P, |H|, the normalising constant k_0 (Eq. 6 with Eq. 1) and the
  * workspace sizes. n is the sample count used in the 1/n of Eq. (1); it must
- * be >= 1. `out` receives the plan. */
+ * be >= 1. With H == NULL only the binning quantities (d, Q, delta,
+ * bin_ws_bytes) are filled and n >= 0 is accepted. `out` receives the plan. */
 int kde_plan_query(const double* H, int64_t n, const kde_grid* grid,
                    const kde_params* params, kde_plan* out);
 
@@ -123,9 +126,11 @@ int kde_plan_query(const double* H, int64_t n, const kde_grid* grid,
  * result is independent of the order of the samples. Samples with u < 0,
  * u > M_k - 1 or NaN on some axis are skipped; their number is written to
  * *n_dropped (device, may be NULL). n = 0 gives all-zero counts.
- * H is not used; n * 2^(dQ) must fit in uint64. */
+ * ws (device, 256-byte aligned, ws_bytes long) must hold plan.bin_ws_bytes
+ * (kde_plan_query with H == NULL); it may be NULL when that is 0.
+ * n * 2^(dQ) must fit in uint64. */
 int kde_bin(const double* X, int64_t n, const kde_grid* grid, const kde_params* params,
-            uint64_t* counts, uint64_t* n_dropped, hipStream_t stream);
+            uint64_t* counts, uint64_t* n_dropped, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Kernel weights on the signed lag box (Eq. 6 and Eq. 12):
  * k_l = n^-1 (2 pi)^-d/2 |H|^-1/2 exp(-(delta l)' H^-1 (delta l) / 2) for

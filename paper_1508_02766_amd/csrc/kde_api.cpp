@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/kde.h"
 #include "kde_internal.h"
@@ -34,13 +35,88 @@ struct Layout {
     size_t lags = 0, khat = 0, kt1 = 0, kt2 = 0, z1 = 0, z2 = 0, total = 0;
 };
 
+struct BinLayout {
+    // offsets into the binning workspace (tiled path)
+    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, seg_base = 0, seg_info = 0, nseg = 0, records = 0,
+           partial = 0, shared_tiles = 0, nshared = 0, total = 0;
+};
+
 struct Plan {
     kde_plan pub;
     double A[9];      // A_ab = delta_a delta_b (H^-1)_ab
     double tau;
     Layout lay;
     size_t counts_bytes;
+    bool tiled;       // tiled binning (else global atomics)
+    kde::TileGeom tg;
+    BinLayout blay;
 };
+
+// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 8 x 8 in 3-D,
+// 1024 in 1-D (clamped to the grid), widened until the tile count fits the
+// per-workgroup histogram. Returns false when the tiled path cannot be used:
+// too many cells per tile, records wider than 64 bits, or n 2^d >= 2^32.
+bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, kde::TileGeom* tg, BinLayout* bl) {
+    kde::TileGeom g{};
+    static const int base[3][3] = {{1024, 0, 0}, {32, 32, 0}, {8, 16, 16}};
+    for (int k = 0; k < d; ++k) {
+        int T = base[d - 1][k];
+        while (T > 1 && T / 2 >= M[k]) T /= 2;
+        g.T[k] = T;
+    }
+    for (;;) {
+        int64_t nt = 1;
+        int worst = 0;
+        for (int k = 0; k < d; ++k) {
+            g.nt[k] = static_cast<int>((M[k] + g.T[k] - 1) / g.T[k]);
+            nt *= g.nt[k];
+            if (g.nt[k] > g.nt[worst]) worst = k;
+        }
+        if (nt <= kde::kMaxTiles) {
+            g.ntiles = static_cast<int>(nt);
+            break;
+        }
+        g.T[worst] *= 2;
+    }
+    int64_t cells = 1;
+    int bits = 0;
+    g.qbits = Q + 1;
+    for (int k = 0; k < d; ++k) {
+        cells *= g.T[k];
+        int lg = 0;
+        while ((1 << lg) < g.T[k]) ++lg;
+        g.logT[k] = lg;
+        g.jbits[k] = lg + 1;
+        bits += g.jbits[k] + g.qbits;
+    }
+    if (cells > kde::kMaxTileCells || bits > 64) return false;
+    g.tile_cells = static_cast<int>(cells);
+    g.max_records = n << d;
+    if (n <= 0 || g.max_records >= (int64_t(1) << 32)) return false;
+    g.S = kde::kSegment;
+    g.nchunk = (n + kde::kBinChunk - 1) / kde::kBinChunk;
+    g.max_segments = g.ntiles + (g.max_records + g.S - 1) / g.S;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    bl->hist = take(static_cast<size_t>(g.nchunk) * g.ntiles * 4);
+    bl->tot = take(static_cast<size_t>(g.ntiles) * 4);
+    bl->drops = take(static_cast<size_t>(g.nchunk) * 4);
+    bl->tile_start = take(static_cast<size_t>(g.ntiles + 1) * 4);
+    bl->seg_base = take(static_cast<size_t>(g.ntiles + 1) * 4);
+    bl->seg_info = take(static_cast<size_t>(g.max_segments) * 16);
+    bl->nseg = take(4);
+    bl->records = take(static_cast<size_t>(g.max_records) * 8);
+    bl->partial = take(static_cast<size_t>(g.max_segments) * g.tile_cells * 8);
+    bl->shared_tiles = take(static_cast<size_t>(g.ntiles) * 4);
+    bl->nshared = take(4);
+    bl->total = off;
+    *tg = g;
+    return true;
+}
 
 // Validation and derived quantities. need_H: validate and factor H;
 // n_min: the smallest admissible sample count (1 where Eq. 1 divides by n).
@@ -89,6 +165,8 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     int64_t cells = 1;
     for (int k = 0; k < d; ++k) cells *= g->M[k];
     out->counts_bytes = static_cast<size_t>(cells) * sizeof(uint64_t);
+    out->tiled = plan_tiles(d, g->M, Q, n, &out->tg, &out->blay);
+    p.bin_ws_bytes = out->tiled ? out->blay.total : 0;
     if (!need_H) return KDE_OK;
 
     // H: finite, symmetric, positive definite
@@ -202,7 +280,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     // workspace layout of the convolution
     Layout& L = out->lay;
     const int64_t M0 = g->M[0], M1 = d > 1 ? g->M[1] : 1;
-    const int64_t P0 = p.P[0], P1 = d > 1 ? p.P[1] : 1;
+    const int64_t P1 = d > 1 ? p.P[1] : 1;
     const int64_t Hl = p.P[d - 1] / 2 + 1;   // bins kept along the last axis
     const int64_t n0 = 2 * p.L[0] + 1, n1 = d > 1 ? 2 * p.L[1] + 1 : 1;
     size_t off = 0;
@@ -211,16 +289,13 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         off = align_up(off + bytes);
         return at;
     };
-    L.lags = take(p.lag_bytes);
     if (d == 1) {
         L.khat = take(static_cast<size_t>(Hl) * rs);
         L.z1 = take(static_cast<size_t>(Hl) * cs);
     } else if (d == 2) {
-        L.khat = take(static_cast<size_t>(P0 * Hl) * rs);
         L.kt1 = take(static_cast<size_t>(n0 * Hl) * cs);
         L.z1 = take(static_cast<size_t>(M0 * Hl) * cs);
     } else {
-        L.khat = take(static_cast<size_t>(P0 * P1 * Hl) * rs);
         L.kt1 = take(static_cast<size_t>(n0 * n1 * Hl) * cs);
         L.kt2 = take(static_cast<size_t>(n0 * P1 * Hl) * cs);
         L.z1 = take(static_cast<size_t>(M0 * M1 * Hl) * cs);
@@ -228,7 +303,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     }
     L.total = off;
     p.conv_ws_bytes = L.total;
-    p.eval_ws_bytes = align_up(out->counts_bytes) + L.total;
+    p.eval_ws_bytes = align_up(out->counts_bytes) + align_up(p.bin_ws_bytes) + L.total;
     return KDE_OK;
 }
 
@@ -268,7 +343,7 @@ struct Tracer {
     } while (0)
 
 int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
-            hipStream_t s, Tracer& tr) {
+            char* ws, hipStream_t s, Tracer& tr) {
     const int d = pl.pub.d;
     kde::BinConsts c{};
     c.d = d;
@@ -284,80 +359,76 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
         c.delta[k] = pl.pub.delta[k];
         c.top[k] = static_cast<double>(g->M[k] - 1);
     }
+    if (pl.tiled && n > 0) {
+        const BinLayout& b = pl.blay;
+        kde::BinWork w{};
+        w.hist = reinterpret_cast<uint32_t*>(ws + b.hist);
+        w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
+        w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
+        w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
+        w.seg_base = reinterpret_cast<uint32_t*>(ws + b.seg_base);
+        w.seg_info = reinterpret_cast<uint4*>(ws + b.seg_info);
+        w.nseg_total = reinterpret_cast<uint32_t*>(ws + b.nseg);
+        w.records = reinterpret_cast<uint64_t*>(ws + b.records);
+        w.partial = reinterpret_cast<uint64_t*>(ws + b.partial);
+        w.shared_tiles = reinterpret_cast<uint32_t*>(ws + b.shared_tiles);
+        w.nshared = reinterpret_cast<uint32_t*>(ws + b.nshared);
+        KDE_LAUNCH(kde::launch_bin_hist(c, pl.tg, w, X, n, s), "bin_hist");
+        KDE_LAUNCH(kde::launch_bin_scan(pl.tg, w, n_dropped, s), "bin_scan");
+        KDE_LAUNCH(kde::launch_bin_scatter(c, pl.tg, w, X, n, s), "bin_scatter");
+        KDE_LAUNCH(kde::launch_bin_accum(c, pl.tg, w, counts, s), "bin_accum");
+        KDE_LAUNCH(kde::launch_bin_reduce(c, pl.tg, w, counts, s), "bin_reduce");
+        return KDE_OK;
+    }
     KDE_LAUNCH(kde::launch_zero_u64(counts, cells, s), "zero_counts");
     if (n_dropped) KDE_LAUNCH(kde::launch_zero_u64(n_dropped, 1, s), "zero_dropped");
     if (n > 0) KDE_LAUNCH(kde::launch_bin(c, X, n, counts, n_dropped, s), "bin");
     return KDE_OK;
 }
 
-int run_conv(const Plan& pl, const uint64_t* counts, const kde_grid* g, void* density, char* ws, hipStream_t s,
-             Tracer& tr) {
-    const kde_plan& p = pl.pub;
-    const Layout& L = pl.lay;
-    const int d = p.d, prec = p.prec;
-    void* lags = ws + L.lags;
-    void* khat = ws + L.khat;
-    void* kt1 = ws + L.kt1;
-    void* kt2 = ws + L.kt2;
-    void* z1 = ws + L.z1;
-    void* z2 = ws + L.z2;
-    double scale = std::ldexp(1.0, -d * p.Q);
-    for (int k = 0; k < d; ++k) scale /= static_cast<double>(p.P[k]);
+// Stage views of the convolution workspace.
+struct ConvBufs {
+    void *khat, *kt1, *kt2, *z1, *z2;
+};
 
-    KDE_LAUNCH(kde::launch_kfill(prec, d, p.L, pl.A, p.norm, lags, s), "kfill");
+ConvBufs conv_bufs(const Plan& pl, char* ws) {
+    const Layout& L = pl.lay;
+    return {ws + L.khat, ws + L.kt1, ws + L.kt2, ws + L.z1, ws + L.z2};
+}
+
+// Kernel spectrum: lag-box weights computed in place (Eq. 6 over the signed
+// box of Eq. 12), transformed along every axis; real because the box is
+// centrally symmetric and placed circularly.
+int run_kspec(const Plan& pl, const kde_grid* g, char* ws, hipStream_t s, Tracer& tr) {
+    const kde_plan& p = pl.pub;
+    const int d = p.d, prec = p.prec;
+    const ConvBufs b = conv_bufs(pl, ws);
+    kde::GaussLag gl{};
+    for (int i = 0; i < 9; ++i) gl.A[i] = pl.A[i];
+    gl.norm = p.norm;
+    gl.d = d;
+    for (int k = 0; k < 3; ++k) gl.L[k] = k < d ? p.L[k] : 0;
+    (void)g;
     if (d == 1) {
         const int P0 = p.P[0];
-        const int64_t H0 = P0 / 2 + 1, M0 = g->M[0];
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P0, kde::kRowLagsCirc, lags, 1, 2 * p.L[0] + 1, p.L[0], khat, H0,
+        KDE_LAUNCH(kde::launch_rows_r2c(prec, P0, kde::kRowGaussCirc, nullptr, &gl, 1, 0, p.L[0], b.khat, P0 / 2 + 1,
                                         true, s), "kspec_r2c");
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P0, kde::kRowCountsU64, counts, 1, M0, static_cast<int>(M0), z1, H0,
-                                        false, s), "counts_r2c");
-        KDE_LAUNCH(kde::launch_rows_c2r(prec, P0, z1, 1, H0, khat, density, M0, static_cast<int>(M0), scale, s),
-                   "product_c2r");
         return KDE_OK;
     }
     if (d == 2) {
-        const int P0 = p.P[0], P1 = p.P[1];
-        const int64_t H1 = P1 / 2 + 1, M0 = g->M[0], M1 = g->M[1];
-        const int64_t n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowLagsCirc, lags, n0, n1, p.L[1], kt1, H1, false, s),
-                   "kspec_r2c");
-        kde::ColArgs ka{};
-        ka.in = kt1;
-        ka.out = khat;
-        ka.W = H1;
-        ka.outer = 1;
-        ka.in_ps = H1;
-        ka.out_ps = H1;
-        ka.len = p.L[0];
-        KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColFwdCircReal, ka, s), "kspec_col");
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowCountsU64, counts, M0, M1, static_cast<int>(M1), z1, H1,
-                                        false, s), "counts_r2c");
-        kde::ColArgs ca{};
-        ca.in = z1;
-        ca.out = z1;
-        ca.khat = khat;
-        ca.W = H1;
-        ca.outer = 1;
-        ca.in_ps = H1;
-        ca.out_ps = H1;
-        ca.k_ps = H1;
-        ca.len = static_cast<int>(M0);
-        ca.mout = static_cast<int>(M0);
-        KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConv, ca, s), "conv_col");
-        KDE_LAUNCH(kde::launch_rows_c2r(prec, P1, z1, M0, H1, nullptr, density, M1, static_cast<int>(M1), scale, s),
-                   "c2r");
+        const int P1 = p.P[1];
+        const int64_t H1 = P1 / 2 + 1, n0 = 2 * p.L[0] + 1;
+        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, H1, false,
+                                        s), "kspec_r2c");
         return KDE_OK;
     }
-    // d == 3
-    const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2];
-    const int64_t H2 = P2 / 2 + 1, M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
-    const int64_t n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1, n2 = 2 * p.L[2] + 1;
-    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowLagsCirc, lags, n0 * n1, n2, p.L[2], kt1, H2, false, s),
-               "kspec_r2c");
+    const int P1 = p.P[1], P2 = p.P[2];
+    const int64_t H2 = P2 / 2 + 1, n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
+    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowGaussCirc, nullptr, &gl, n0 * n1, 0, p.L[2], b.kt1, H2, false,
+                                    s), "kspec_r2c");
     kde::ColArgs k1{};
-    k1.in = kt1;
-    k1.out = kt2;
+    k1.in = b.kt1;
+    k1.out = b.kt2;
     k1.W = H2;
     k1.outer = n0;
     k1.in_os = n1 * H2;
@@ -366,43 +437,92 @@ int run_conv(const Plan& pl, const uint64_t* counts, const kde_grid* g, void* de
     k1.out_ps = H2;
     k1.len = p.L[1];
     KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdCirc, k1, s), "kspec_col2");
-    kde::ColArgs k0{};
-    k0.in = kt2;
-    k0.out = khat;
-    k0.W = static_cast<int64_t>(P1) * H2;
-    k0.outer = 1;
-    k0.in_ps = k0.W;
-    k0.out_ps = k0.W;
-    k0.len = p.L[0];
-    KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColFwdCircReal, k0, s), "kspec_col1");
-    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowCountsU64, counts, M0 * M1, M2, static_cast<int>(M2), z1, H2,
-                                    false, s), "counts_r2c");
-    kde::ColArgs f1{};
-    f1.in = z1;
-    f1.out = z2;
-    f1.W = H2;
-    f1.outer = M0;
-    f1.in_os = M1 * H2;
-    f1.in_ps = H2;
-    f1.out_os = static_cast<int64_t>(P1) * H2;
-    f1.out_ps = H2;
-    f1.len = static_cast<int>(M1);
-    KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdPrefix, f1, s), "counts_col2");
+    return KDE_OK;
+}
+
+// Forward transforms of the zero-padded counts that do not need the spectrum.
+int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, char* ws, hipStream_t s, Tracer& tr) {
+    const kde_plan& p = pl.pub;
+    const int d = p.d, prec = p.prec;
+    const ConvBufs b = conv_bufs(pl, ws);
+    const int Pl = p.P[d - 1];
+    const int64_t Hl = Pl / 2 + 1;
+    const int64_t Ml = g->M[d - 1];
+    int64_t rows = 1;
+    for (int k = 0; k < d - 1; ++k) rows *= g->M[k];
+    KDE_LAUNCH(kde::launch_rows_r2c(prec, Pl, kde::kRowCountsU64, counts, nullptr, rows, Ml, static_cast<int>(Ml), b.z1,
+                                    Hl, false, s), "counts_r2c");
+    if (d == 3) {
+        const int P1 = p.P[1];
+        const int64_t M0 = g->M[0], M1 = g->M[1];
+        kde::ColArgs f1{};
+        f1.in = b.z1;
+        f1.out = b.z2;
+        f1.W = Hl;
+        f1.outer = M0;
+        f1.in_os = M1 * Hl;
+        f1.in_ps = Hl;
+        f1.out_os = static_cast<int64_t>(P1) * Hl;
+        f1.out_ps = Hl;
+        f1.len = static_cast<int>(M1);
+        KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdPrefix, f1, s), "counts_col2");
+    }
+    return KDE_OK;
+}
+
+// Product with the spectrum, inverse transforms, window [0, M_k) and the
+// 2^-(dQ) / prod P_k scale.
+int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, hipStream_t s, Tracer& tr) {
+    const kde_plan& p = pl.pub;
+    const int d = p.d, prec = p.prec;
+    const ConvBufs b = conv_bufs(pl, ws);
+    double scale = std::ldexp(1.0, -d * p.Q);
+    for (int k = 0; k < d; ++k) scale /= static_cast<double>(p.P[k]);
+    if (d == 1) {
+        const int P0 = p.P[0];
+        const int64_t H0 = P0 / 2 + 1, M0 = g->M[0];
+        KDE_LAUNCH(kde::launch_rows_c2r(prec, P0, b.z1, 1, H0, b.khat, density, M0, static_cast<int>(M0), scale, s),
+                   "product_c2r");
+        return KDE_OK;
+    }
+    if (d == 2) {
+        const int P0 = p.P[0], P1 = p.P[1];
+        const int64_t H1 = P1 / 2 + 1, M0 = g->M[0], M1 = g->M[1];
+        kde::ColArgs ca{};
+        ca.in = b.z1;
+        ca.out = b.z1;
+        ca.kt = b.kt1;
+        ca.kt_ps = H1;
+        ca.kt_len = p.L[0];
+        ca.W = H1;
+        ca.outer = 1;
+        ca.in_ps = H1;
+        ca.out_ps = H1;
+        ca.len = static_cast<int>(M0);
+        ca.mout = static_cast<int>(M0);
+        KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, ca, s), "conv_col");
+        KDE_LAUNCH(kde::launch_rows_c2r(prec, P1, b.z1, M0, H1, nullptr, density, M1, static_cast<int>(M1), scale, s),
+                   "c2r");
+        return KDE_OK;
+    }
+    const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2];
+    const int64_t H2 = P2 / 2 + 1, M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
     kde::ColArgs cv{};
-    cv.in = z2;
-    cv.out = z2;
-    cv.khat = khat;
+    cv.in = b.z2;
+    cv.out = b.z2;
+    cv.kt = b.kt2;
     cv.W = static_cast<int64_t>(P1) * H2;
+    cv.kt_ps = cv.W;
+    cv.kt_len = p.L[0];
     cv.outer = 1;
     cv.in_ps = cv.W;
     cv.out_ps = cv.W;
-    cv.k_ps = cv.W;
     cv.len = static_cast<int>(M0);
     cv.mout = static_cast<int>(M0);
-    KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConv, cv, s), "conv_col1");
+    KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, cv, s), "conv_col1");
     kde::ColArgs i1{};
-    i1.in = z2;
-    i1.out = z1;
+    i1.in = b.z2;
+    i1.out = b.z1;
     i1.W = H2;
     i1.outer = M0;
     i1.in_os = static_cast<int64_t>(P1) * H2;
@@ -411,9 +531,70 @@ int run_conv(const Plan& pl, const uint64_t* counts, const kde_grid* g, void* de
     i1.out_ps = H2;
     i1.mout = static_cast<int>(M1);
     KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColInvPrefix, i1, s), "inv_col2");
-    KDE_LAUNCH(kde::launch_rows_c2r(prec, P2, z1, M0 * M1, H2, nullptr, density, M2, static_cast<int>(M2), scale, s),
+    KDE_LAUNCH(kde::launch_rows_c2r(prec, P2, b.z1, M0 * M1, H2, nullptr, density, M2, static_cast<int>(M2), scale, s),
                "c2r");
     return KDE_OK;
+}
+
+// A second stream per device on which the kernel spectrum is computed while
+// the caller's stream bins and transforms the counts. Created once (default
+// priority, non-blocking) and kept for the life of the process; the fork /
+// join events order it with the caller's stream, so the work stays capturable
+// in a HIP graph. The mutex keeps concurrent callers from interleaving their
+// event records.
+struct Aux {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool ready = false;
+};
+std::mutex g_aux_mu;
+Aux g_aux[64];
+
+Aux* aux_for(hipStream_t s) {
+    int dev = 0;
+    if (hipStreamGetDevice(s, &dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    Aux& a = g_aux[dev];
+    if (a.ready) return &a;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+    bool ok = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&a.fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&a.join, hipEventDisableTiming) == hipSuccess;
+    if (cur != dev && hipSetDevice(cur) != hipSuccess) ok = false;
+    if (!ok) return nullptr;
+    a.ready = true;
+    return &a;
+}
+
+// The convolution of counts (already on / being computed on stream s), with
+// the spectrum on the auxiliary stream unless per-kernel tracing asks for one
+// serial stream. `pre` enqueues the work that produces the counts (binning)
+// or nothing.
+template <typename Pre>
+int run_pipeline(const Plan& pl, const kde_grid* g, const uint64_t* counts, void* density, char* conv_ws, hipStream_t s,
+                 Tracer& tr, Pre&& pre) {
+    if (!tr.on) {
+        std::lock_guard<std::mutex> lock(g_aux_mu);
+        Aux* a = aux_for(s);
+        if (a) {
+            KDE_TRY(hipEventRecord(a->fork, s));
+            KDE_TRY(hipStreamWaitEvent(a->stream, a->fork, 0));
+            int r = run_kspec(pl, g, conv_ws, a->stream, tr);
+            if (r != KDE_OK) return r;
+            KDE_TRY(hipEventRecord(a->join, a->stream));
+            r = pre();
+            if (r == KDE_OK) r = run_counts_fwd(pl, counts, g, conv_ws, s, tr);
+            if (r != KDE_OK) return r;
+            KDE_TRY(hipStreamWaitEvent(s, a->join, 0));
+            return run_product_inv(pl, g, density, conv_ws, s, tr);
+        }
+    }
+    int r = pre();
+    if (r == KDE_OK) r = run_kspec(pl, g, conv_ws, s, tr);
+    if (r == KDE_OK) r = run_counts_fwd(pl, counts, g, conv_ws, s, tr);
+    if (r == KDE_OK) r = run_product_inv(pl, g, density, conv_ws, s, tr);
+    return r;
 }
 
 }  // namespace
@@ -423,21 +604,25 @@ extern "C" {
 int kde_plan_query(const double* H, int64_t n, const kde_grid* grid, const kde_params* params, kde_plan* out) {
     if (!out) return KDE_ERR_ARG;
     Plan pl;
-    const int rc = make_plan(H, n, 1, true, grid, params, &pl);
+    const int rc = H ? make_plan(H, n, 1, true, grid, params, &pl) : make_plan(nullptr, n, 0, false, grid, params, &pl);
     if (rc != KDE_OK) return rc;
     *out = pl.pub;
     return KDE_OK;
 }
 
 int kde_bin(const double* X, int64_t n, const kde_grid* grid, const kde_params* params, uint64_t* counts,
-            uint64_t* n_dropped, hipStream_t stream) {
+            uint64_t* n_dropped, void* ws, size_t ws_bytes, hipStream_t stream) {
     Plan pl;
     const int rc = make_plan(nullptr, n, 0, false, grid, params, &pl);
     if (rc != KDE_OK) return rc;
     if (!counts || (n > 0 && !X)) return KDE_ERR_ARG;
+    if (pl.pub.bin_ws_bytes > 0) {
+        if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
+        if (ws_bytes < pl.pub.bin_ws_bytes) return KDE_ERR_WS;
+    }
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    const int r = run_bin(pl, X, n, grid, counts, n_dropped, stream, tr);
+    const int r = run_bin(pl, X, n, grid, counts, n_dropped, static_cast<char*>(ws), stream, tr);
     tr.finish();
     return r;
 }
@@ -466,7 +651,7 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     if (ws_bytes < pl.pub.conv_ws_bytes) return KDE_ERR_WS;
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    const int r = run_conv(pl, counts, grid, density, static_cast<char*>(ws), stream, tr);
+    const int r = run_pipeline(pl, grid, counts, density, static_cast<char*>(ws), stream, tr, [] { return KDE_OK; });
     tr.finish();
     return r;
 }
@@ -480,11 +665,12 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
     if (ws_bytes < pl.pub.eval_ws_bytes) return KDE_ERR_WS;
     auto* counts = static_cast<uint64_t*>(ws);
-    char* conv_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
+    char* bin_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
+    char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    int r = run_bin(pl, X, n, grid, counts, n_dropped, stream, tr);
-    if (r == KDE_OK) r = run_conv(pl, counts, grid, density, conv_ws, stream, tr);
+    const int r = run_pipeline(pl, grid, counts, density, conv_ws, stream, tr,
+                               [&] { return run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, stream, tr); });
     tr.finish();
     return r;
 }

@@ -7,13 +7,429 @@
 // -ffp-contract=off and without fast-math so nothing is fused or
 // approximated), j = min(floor u, M - 2), q = rint((u - j) 2^Q) (ties to
 // even). Corner b of the cell receives prod_k (b_k ? q_k : 2^Q - q_k), an
-// exact uint64, added with integer atomics, so the result does not depend on
-// the order in which samples are processed.
+// exact uint64; integer addition makes the result independent of order.
+//
+// Two implementations with identical results:
+//
+// * tiled (default): a counting sort of packed (sample, tile) records into
+//   per-tile buckets, then one workgroup per segment of a bucket sums its
+//   records in LDS and stores whole tiles with plain writes. Five launches:
+//     hist     per-chunk histogram of records per tile (LDS atomics)
+//     scan     per-tile exclusive scan over chunks (one wavefront per tile)
+//     scatter  block scan of the tile totals, packed records into buckets
+//     accum    LDS sum of one segment (<= S records) of one tile; a tile with
+//              one segment is stored directly, others as partial sub-grids
+//     reduce   sum of the partial sub-grids of tiles with several segments
+//   A sample whose corners straddle a tile edge gets one record per tile it
+//   touches, so every cell is owned by exactly one tile and no global atomic
+//   is needed anywhere.
+// * atomic (fallback when a record does not fit in 64 bits or the grid needs
+//   more tiles than one workgroup can histogram): zero fill, then 2^d global
+//   64-bit atomic adds per sample.
 
 #include "kde_internal.h"
 
 namespace kde {
 namespace {
+
+// Classification of a sample with coordinates x: false when it lies outside
+// the closed grid box (or is NaN) on some axis; otherwise the lower-corner
+// node j and the fractions q.
+template <int D>
+__device__ __forceinline__ bool classify_x(const double (&x)[D], const BinConsts& c, int64_t (&j)[D],
+                                           uint64_t (&q)[D]) {
+    const double scale = static_cast<double>(1ull << c.Q);   // exact power of two
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const double u = (x[k] - c.lo[k]) / c.delta[k];
+        const bool in = (u >= 0.0) && (u <= c.top[k]);   // false for NaN
+        ok = ok && in;
+        double jf = floor(u);
+        jf = jf < c.top[k] - 1.0 ? jf : c.top[k] - 1.0;  // a sample on the last node
+        const double t = u - jf;                           // exact
+        q[k] = in ? static_cast<uint64_t>(rint(t * scale)) : 0;
+        j[k] = in ? static_cast<int64_t>(jf) : 0;
+    }
+    return ok;
+}
+
+template <int D>
+__device__ __forceinline__ bool classify(const double* __restrict__ X, int64_t i, const BinConsts& c,
+                                         int64_t (&j)[D], uint64_t (&q)[D]) {
+    double x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = X[i * D + k];
+    return classify_x<D>(x, c, j, q);
+}
+
+constexpr int kPer = kBinChunk / kBinThreads;   // samples per thread in hist / scatter
+
+// Loads this thread's kPer samples of chunk `blk` up front so that all their
+// loads are in flight together; rows past n are marked invalid.
+template <int D>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ X, int64_t n, int64_t blk, double (&x)[kPer][D],
+                                           bool (&valid)[kPer]) {
+    const int64_t base = blk * kBinChunk + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = base + static_cast<int64_t>(k) * kBinThreads;
+        valid[k] = i < n;
+        const int64_t ii = valid[k] ? i : 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[k][a] = X[ii * D + a];
+    }
+}
+
+// Calls f(tile, record) for every tile the corners j..j+1 touch.
+template <int D, typename F>
+__device__ __forceinline__ void for_each_tile(const TileGeom& g, const int64_t (&j)[D], const uint64_t (&q)[D], F&& f) {
+    int64_t tlo[D];
+    int span[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        tlo[k] = j[k] >> g.logT[k];
+        span[k] = static_cast<int>(((j[k] + 1) >> g.logT[k]) != tlo[k]);
+    }
+    uint64_t qpart = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) qpart |= q[k] << (k * g.qbits);
+#pragma unroll
+    for (int b = 0; b < (1 << D); ++b) {
+        bool use = true;
+        int64_t tile = 0;
+        uint64_t rec = qpart;
+        int shift = D * g.qbits;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const int bk = (b >> k) & 1;
+            use = use && (bk <= span[k]);
+            const int64_t tk = tlo[k] + bk;
+            tile = tile * g.nt[k] + tk;
+            const uint64_t jl = static_cast<uint64_t>(j[k] - (tk << g.logT[k]) + 1);   // in [0, T_k]
+            rec |= jl << shift;
+            shift += g.jbits[k];
+        }
+        if (use) f(static_cast<uint32_t>(tile), rec);
+    }
+}
+
+// Exclusive scan of a[0..n) in LDS by a 256-thread block; returns the total.
+__device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* wave_sums) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int per = (n + kBinThreads - 1) / kBinThreads;
+    const int b0 = tid * per < n ? tid * per : n;
+    const int b1 = b0 + per < n ? b0 + per : n;
+    uint32_t s = 0;
+    for (int i = b0; i < b1; ++i) s += a[i];
+    uint32_t x = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sums[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBinThreads / 64; ++w) {
+        if (w < wave) before += wave_sums[w];
+        total += wave_sums[w];
+    }
+    uint32_t run = before + x - s;
+    for (int i = b0; i < b1; ++i) {
+        const uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// tiled path
+// ---------------------------------------------------------------------------
+
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
+                                                               TileGeom g, uint32_t* __restrict__ hist,
+                                                               uint32_t* __restrict__ drops) {
+    __shared__ uint32_t h[kMaxTiles];
+    __shared__ uint32_t nd;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) h[t] = 0;
+    if (tid == 0) nd = 0;
+    __syncthreads();
+    double x[kPer][D];
+    bool valid[kPer];
+    load_chunk<D>(X, n, blockIdx.x, x, valid);
+    uint32_t dropped = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (!valid[k]) continue;
+        int64_t j[D];
+        uint64_t q[D];
+        if (!classify_x<D>(x[k], c, j, q)) {
+            ++dropped;
+            continue;
+        }
+        for_each_tile<D>(g, j, q, [&](uint32_t tile, uint64_t) { atomicAdd(&h[tile], 1u); });
+    }
+    if (dropped) atomicAdd(&nd, dropped);
+    __syncthreads();
+    uint32_t* row = hist + static_cast<int64_t>(blockIdx.x) * g.ntiles;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) row[t] = h[t];
+    if (tid == 0) drops[blockIdx.x] = nd;
+}
+
+// One wavefront per tile: exclusive scan of hist[., tile] over the chunks,
+// tot[tile] = the tile's record count. Block 0 also totals the dropped samples.
+__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(TileGeom g, uint32_t* __restrict__ hist,
+                                                               uint32_t* __restrict__ tot,
+                                                               const uint32_t* __restrict__ drops,
+                                                               unsigned long long* __restrict__ n_dropped) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = blockIdx.x * (kBinThreads / 64) + wave;
+    const int64_t nch = g.nchunk;
+    if (tile < g.ntiles) {
+        const int64_t per = (nch + 63) / 64;
+        const int64_t c0 = lane * per < nch ? lane * per : nch;
+        const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+        uint32_t s = 0;
+        for (int64_t ch = c0; ch < c1; ++ch) s += hist[ch * g.ntiles + tile];
+        uint32_t x = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t run = x - s;
+        for (int64_t ch = c0; ch < c1; ++ch) {
+            const uint32_t v = hist[ch * g.ntiles + tile];
+            hist[ch * g.ntiles + tile] = run;
+            run += v;
+        }
+        if (lane == 63) tot[tile] = x;
+    }
+    if (blockIdx.x == 0 && n_dropped) {
+        __shared__ unsigned long long acc;
+        if (tid == 0) acc = 0;
+        __syncthreads();
+        unsigned long long s = 0;
+        for (int64_t ch = tid; ch < nch; ch += kBinThreads) s += drops[ch];
+        if (s) atomicAdd(&acc, s);
+        __syncthreads();
+        if (tid == 0) n_dropped[0] = acc;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
+                                                                  TileGeom g, BinWork w) {
+    __shared__ uint32_t cur[kMaxTiles];
+    __shared__ uint32_t wave_sums[kBinThreads / 64];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] = w.tot[t];
+    __syncthreads();
+    const uint32_t total = block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
+    if (blockIdx.x == 0) {
+        // publish tile starts and the segment -> tile map for the accumulation pass
+        for (int t = tid; t < g.ntiles; t += kBinThreads) w.tile_start[t] = cur[t];
+        if (tid == 0) w.tile_start[g.ntiles] = total;
+        __shared__ uint32_t nseg[kMaxTiles];
+        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+            const uint32_t cnt = w.tot[t];
+            const uint32_t ns = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+            nseg[t] = ns;
+        }
+        __syncthreads();
+        const uint32_t nsegs = block_exclusive_scan(nseg, g.ntiles, wave_sums);
+        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+            const uint32_t b = nseg[t];
+            w.seg_base[t] = b;
+            const uint32_t e = t + 1 < g.ntiles ? nseg[t + 1] : nsegs;
+            const uint32_t start = cur[t];
+            const uint32_t end = start + w.tot[t];
+            for (uint32_t s2 = b; s2 < e; ++s2) {
+                const uint32_t r0 = start + (s2 - b) * static_cast<uint32_t>(g.S);
+                const uint32_t r1 = r0 + static_cast<uint32_t>(g.S) < end ? r0 + static_cast<uint32_t>(g.S) : end;
+                w.seg_info[s2] = make_uint4(static_cast<uint32_t>(t), r0, r1, e - b > 1 ? 1u : 0u);
+            }
+        }
+        if (tid == 0) {
+            w.seg_base[g.ntiles] = nsegs;
+            w.nseg_total[0] = nsegs;
+        }
+        __syncthreads();
+        // compact list of the tiles with several segments (summed by the reduce pass)
+        for (int t = tid; t < g.ntiles; t += kBinThreads) nseg[t] = w.tot[t] > static_cast<uint32_t>(g.S) ? 1u : 0u;
+        __syncthreads();
+        const uint32_t nshared = block_exclusive_scan(nseg, g.ntiles, wave_sums);
+        for (int t = tid; t < g.ntiles; t += kBinThreads)
+            if (w.tot[t] > static_cast<uint32_t>(g.S)) w.shared_tiles[nseg[t]] = static_cast<uint32_t>(t);
+        if (tid == 0) w.nshared[0] = nshared;
+        __syncthreads();
+    }
+    const uint32_t* off = w.hist + static_cast<int64_t>(blockIdx.x) * g.ntiles;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += off[t];
+    __syncthreads();
+    double x[kPer][D];
+    bool valid[kPer];
+    load_chunk<D>(X, n, blockIdx.x, x, valid);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (!valid[k]) continue;
+        int64_t j[D];
+        uint64_t q[D];
+        if (!classify_x<D>(x[k], c, j, q)) continue;
+        for_each_tile<D>(g, j, q, [&](uint32_t tile, uint64_t rec) {
+            const uint32_t pos = atomicAdd(&cur[tile], 1u);
+            w.records[pos] = rec;
+        });
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void tile_frame(const BinConsts& c, const TileGeom& g, uint32_t tile, int64_t (&org)[D],
+                                           int (&ext)[D]) {
+    uint32_t rem = tile;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+        const uint32_t ta = rem % static_cast<uint32_t>(g.nt[a]);
+        rem /= static_cast<uint32_t>(g.nt[a]);
+        org[a] = static_cast<int64_t>(ta) << g.logT[a];
+        const int64_t left = c.M[a] - org[a];
+        ext[a] = left < g.T[a] ? static_cast<int>(left) : g.T[a];
+    }
+}
+
+// Counts index of tile-local cell i (row-major over T), or -1 outside the grid.
+template <int D>
+__device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const TileGeom& g, const int64_t (&org)[D],
+                                                   const int (&ext)[D], int i) {
+    int64_t idx = 0;
+    bool inside = true;
+    int rem = i;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+        const int ca = rem & (g.T[a] - 1);
+        rem >>= g.logT[a];
+        inside = inside && ca < ext[a];
+        idx += (org[a] + ca) * c.stride[a];
+    }
+    return inside ? idx : -1;
+}
+
+// One workgroup per segment (<= S records of one tile): sum the records'
+// corner weights in LDS, then store the tile (sole segment) or its partial.
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinConsts c, TileGeom g, BinWork w,
+                                                                uint64_t* __restrict__ counts) {
+    __shared__ unsigned long long grid[kMaxTileCells];
+    const int tid = threadIdx.x;
+    const uint32_t s = blockIdx.x;
+    if (s >= w.nseg_total[0]) return;
+    const uint4 info = w.seg_info[s];
+    const uint32_t tile = info.x, r0 = info.y, r1 = info.z;
+    const bool shared_tile = info.w != 0;
+    // this thread's records, loaded together
+    constexpr int kRec = kSegment / kBinThreads;
+    uint64_t recs[kRec];
+#pragma unroll
+    for (int m = 0; m < kRec; ++m) {
+        const uint32_t r = r0 + tid + m * kBinThreads;
+        recs[m] = r < r1 ? w.records[r] : 0;
+    }
+    int64_t org[D];
+    int ext[D];
+    tile_frame<D>(c, g, tile, org, ext);
+    for (int i = tid; i < g.tile_cells; i += kBinThreads) grid[i] = 0;
+    __syncthreads();
+    const uint64_t one = 1ull << c.Q;
+    const uint64_t qmask = (1ull << g.qbits) - 1;
+#pragma unroll
+    for (int m = 0; m < kRec; ++m) {
+        if (r0 + tid + m * kBinThreads >= r1) break;
+        const uint64_t rec = recs[m];
+        uint64_t q[D];
+        int jl[D];
+        int shift = D * g.qbits;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            q[a] = (rec >> (a * g.qbits)) & qmask;
+            jl[a] = static_cast<int>((rec >> shift) & ((1ull << g.jbits[a]) - 1)) - 1;
+            shift += g.jbits[a];
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << D); ++b) {
+            bool inside = true;
+            int cell = 0;
+            uint64_t wgt = 1;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int bit = (b >> (D - 1 - a)) & 1;
+                const int ca = jl[a] + bit;
+                inside = inside && ca >= 0 && ca < ext[a];
+                cell = (cell << g.logT[a]) + ca;
+                wgt *= bit ? q[a] : one - q[a];
+            }
+            if (inside && wgt) atomicAdd(&grid[cell], static_cast<unsigned long long>(wgt));
+        }
+    }
+    __syncthreads();
+    if (!shared_tile) {
+        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
+            const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
+            if (idx >= 0) counts[idx] = grid[i];
+        }
+    } else {
+        uint64_t* part = w.partial + static_cast<int64_t>(s) * g.tile_cells;
+        for (int i = tid; i < g.tile_cells; i += kBinThreads) part[i] = grid[i];
+    }
+}
+
+// Tiles with several segments: sum their partial sub-grids into the counts
+// (the kernel boundary orders these reads after every partial store). Work
+// items are (shared tile, block of 64 cells); the 4 wavefronts of a workgroup
+// sum interleaved segments of the same 64 cells and combine through LDS.
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinConsts c, TileGeom g, BinWork w,
+                                                                 uint64_t* __restrict__ counts) {
+    __shared__ uint64_t part_sum[kBinThreads];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int blocks_per_tile = (g.tile_cells + 63) / 64;
+    const uint32_t items = w.nshared[0] * static_cast<uint32_t>(blocks_per_tile);
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const uint32_t tile = w.shared_tiles[it / blocks_per_tile];
+        const int i = static_cast<int>(it % blocks_per_tile) * 64 + lane;
+        const uint32_t sb = w.seg_base[tile], nseg = w.seg_base[tile + 1] - sb;
+        const uint64_t* base = w.partial + static_cast<int64_t>(sb) * g.tile_cells;
+        uint64_t acc[4] = {0, 0, 0, 0};
+        if (i < g.tile_cells) {
+            uint32_t k = wave;
+            for (; k + 12 < nseg; k += 16) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] += base[static_cast<int64_t>(k + 4 * u) * g.tile_cells + i];
+            }
+            for (; k < nseg; k += 4) acc[0] += base[static_cast<int64_t>(k) * g.tile_cells + i];
+        }
+        part_sum[tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        __syncthreads();
+        if (wave == 0 && i < g.tile_cells) {
+            int64_t org[D];
+            int ext[D];
+            tile_frame<D>(c, g, tile, org, ext);
+            const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
+            if (idx >= 0)
+                counts[idx] = (part_sum[lane] + part_sum[64 + lane]) + (part_sum[128 + lane] + part_sum[192 + lane]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// atomic path
+// ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void zero_u64_kernel(uint64_t* __restrict__ p, int64_t count) {
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -24,26 +440,13 @@ template <int D>
 __global__ __launch_bounds__(256) void bin_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
                                                   unsigned long long* __restrict__ counts,
                                                   unsigned long long* __restrict__ n_dropped) {
-    const double scale = static_cast<double>(1ull << c.Q);   // exact power of two
     const uint64_t one = 1ull << c.Q;
     unsigned long long dropped = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
         int64_t j[D];
         uint64_t q[D];
-        bool ok = true;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const double u = (X[i * D + k] - c.lo[k]) / c.delta[k];
-            const bool in = (u >= 0.0) && (u <= c.top[k]);   // false for NaN
-            ok = ok && in;
-            double jf = floor(u);
-            jf = jf < c.top[k] - 1.0 ? jf : c.top[k] - 1.0;  // a sample on the last node
-            const double t = u - jf;                           // exact
-            q[k] = in ? static_cast<uint64_t>(rint(t * scale)) : 0;
-            j[k] = in ? static_cast<int64_t>(jf) : 0;
-        }
-        if (!ok) {
+        if (!classify<D>(X, i, c, j, q)) {
             ++dropped;
             continue;
         }
@@ -87,6 +490,62 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
         hipLaunchKernelGGL((bin_kernel<2>), g, blk, 0, s, X, n, c, cc, nd);
     else
         hipLaunchKernelGGL((bin_kernel<3>), g, blk, 0, s, X, n, c, cc, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
+                           hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
+    if (c.d == 1)
+        hipLaunchKernelGGL((bin_hist_kernel<1>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+    else if (c.d == 2)
+        hipLaunchKernelGGL((bin_hist_kernel<2>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+    else
+        hipLaunchKernelGGL((bin_hist_kernel<3>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(const TileGeom& g, const BinWork& w, uint64_t* n_dropped, hipStream_t s) {
+    const int per_block = kBinThreads / 64;
+    const dim3 grid(static_cast<unsigned>((g.ntiles + per_block - 1) / per_block)), blk(kBinThreads);
+    hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, g, w.hist, w.tot, w.drops,
+                       reinterpret_cast<unsigned long long*>(n_dropped));
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
+                              hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
+    if (c.d == 1)
+        hipLaunchKernelGGL((bin_scatter_kernel<1>), grid, blk, 0, s, X, n, c, g, w);
+    else if (c.d == 2)
+        hipLaunchKernelGGL((bin_scatter_kernel<2>), grid, blk, 0, s, X, n, c, g, w);
+    else
+        hipLaunchKernelGGL((bin_scatter_kernel<3>), grid, blk, 0, s, X, n, c, g, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_accum(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
+                            hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(g.max_segments)), blk(kBinThreads);
+    if (c.d == 1)
+        hipLaunchKernelGGL((bin_accum_kernel<1>), grid, blk, 0, s, c, g, w, counts);
+    else if (c.d == 2)
+        hipLaunchKernelGGL((bin_accum_kernel<2>), grid, blk, 0, s, c, g, w, counts);
+    else
+        hipLaunchKernelGGL((bin_accum_kernel<3>), grid, blk, 0, s, c, g, w, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_reduce(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
+                             hipStream_t s) {
+    const dim3 grid(1024), blk(kBinThreads);
+    if (c.d == 1)
+        hipLaunchKernelGGL((bin_reduce_kernel<1>), grid, blk, 0, s, c, g, w, counts);
+    else if (c.d == 2)
+        hipLaunchKernelGGL((bin_reduce_kernel<2>), grid, blk, 0, s, c, g, w, counts);
+    else
+        hipLaunchKernelGGL((bin_reduce_kernel<3>), grid, blk, 0, s, c, g, w, counts);
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 //   * kfill      lag-box weights k_l = n^-1 K_H(delta l) over [-L, L]^d (Eq. 6, Eq. 12)
 //   * rows_r2c   forward transform along the contiguous (last) axis of real rows,
 //                two rows per complex FFT; input either u64 counts (zero padded)
-//                or lag-box rows placed circularly (lag l at position l mod P)
+//                or lag-box rows whose weights are computed in place and placed
+//                circularly (lag l at position l mod P)
 //   * cols       forward / fused forward x spectrum x inverse / inverse transforms
 //                along a strided axis; a workgroup owns B adjacent lines so each
 //                global access is a contiguous run of B complex values
@@ -345,8 +346,36 @@ struct RowShape {
     static constexpr int B = (256 / T) >= 1 ? 256 / T : 1;   // lines (row pairs) per workgroup
 };
 
-template <typename R, int P, int IN_KIND, bool OUT_REAL>
-__global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ in_, int64_t nrows,
+// Lag-box weight coefficients in the working precision.
+template <typename R>
+struct GaussR {
+    R a00, a01, a02, a11, a12, a22, norm;
+    int L0, L1;
+};
+
+template <typename R, int D>
+__device__ __forceinline__ R gauss_weight(const GaussR<R>& g, R l0, R l1, R l2) {
+    R q = g.a00 * l0 * l0;
+    if constexpr (D >= 2) q += g.a11 * l1 * l1 + R(2) * g.a01 * l0 * l1;
+    if constexpr (D == 3) q += g.a22 * l2 * l2 + R(2) * (g.a02 * l0 * l2 + g.a12 * l1 * l2);
+    return g.norm * fexp<R>(R(-0.5) * q);
+}
+
+// Leading lags of lag-box row r: d = 2 -> (r - L0); d = 3 -> (r / n1 - L0, r % n1 - L1).
+template <typename R, int D>
+__device__ __forceinline__ void row_lags(const GaussR<R>& g, int64_t r, R& l0, R& l1) {
+    if constexpr (D == 3) {
+        const int64_t n1 = 2 * g.L1 + 1;
+        l0 = static_cast<R>(r / n1 - g.L0);
+        l1 = static_cast<R>(r % n1 - g.L1);
+    } else {
+        l0 = static_cast<R>(r - g.L0);
+        l1 = 0;
+    }
+}
+
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D = 1>
+__global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ in_, GaussR<R> gw, int64_t nrows,
                                                        int64_t in_ld, int len, void* __restrict__ out_,
                                                        int64_t out_ld) {
     using C = cpx<R>;
@@ -356,25 +385,44 @@ __global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ 
     const int64_t r0 = 2 * (static_cast<int64_t>(blockIdx.x) * B + b), r1 = r0 + 1;
     const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
     C v[16];
+    if constexpr (IN_KIND == kRowCountsU64) {
+        const uint64_t* in = static_cast<const uint64_t*>(in_);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int p = t + T * m;
-        R x = 0, y = 0;
-        if constexpr (IN_KIND == kRowCountsU64) {
-            const uint64_t* in = static_cast<const uint64_t*>(in_);
+        for (int m = 0; m < 16; ++m) {
+            const int p = t + T * m;
+            R x = 0, y = 0;
             if (p < len) {
                 if (ok0) x = to_real<R>(in[r0 * in_ld + p]);
                 if (ok1) y = to_real<R>(in[r1 * in_ld + p]);
             }
-        } else {
-            const R* in = static_cast<const R*>(in_);
-            const int idx = p <= len ? p + len : (p >= P - len ? p - P + len : -1);
-            if (idx >= 0) {
-                if (ok0) x = in[r0 * in_ld + idx];
-                if (ok1) y = in[r1 * in_ld + idx];
-            }
+            v[m] = C{x, y};
         }
-        v[m] = C{x, y};
+    } else {
+        // weights of two lag-box rows; the last-axis lag l sits at position l mod P
+        R a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+        if (D > 1) {
+            row_lags<R, D>(gw, r0, a0, b0);
+            row_lags<R, D>(gw, r1, a1, b1);
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int p = t + T * m;
+            R x = 0, y = 0;
+            const bool on = p <= len || p >= P - len;
+            const R l = static_cast<R>(p <= len ? p : p - P);
+            if (on) {
+                if constexpr (D == 1) {
+                    if (ok0) x = gauss_weight<R, 1>(gw, l, R(0), R(0));
+                } else if constexpr (D == 2) {
+                    if (ok0) x = gauss_weight<R, 2>(gw, a0, l, R(0));
+                    if (ok1) y = gauss_weight<R, 2>(gw, a1, l, R(0));
+                } else {
+                    if (ok0) x = gauss_weight<R, 3>(gw, a0, b0, l);
+                    if (ok1) y = gauss_weight<R, 3>(gw, a1, b1, l);
+                }
+            }
+            v[m] = C{x, y};
+        }
     }
     C* line = lds + b * LINE;
     fft_line<R, P, 1>(v, line, t);
@@ -476,7 +524,7 @@ __global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs
     for (int m = 0; m < 16; ++m) {
         const int p = t + T * m;
         C x{0, 0};
-        if constexpr (MODE == kColFwdPrefix || MODE == kColConv) {
+        if constexpr (MODE == kColFwdPrefix || MODE == kColConv || MODE == kColConvLag) {
             if (act && p < a.len) x = in[p * a.in_ps];
         } else if constexpr (MODE == kColFwdCirc || MODE == kColFwdCircReal) {
             const int idx = p <= a.len ? p + a.len : (p >= P - a.len ? p - P + a.len : -1);
@@ -486,7 +534,23 @@ __global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs
         }
         v[m] = x;
     }
-    if constexpr (MODE == kColInvPrefix) {
+    if constexpr (MODE == kColConvLag) {
+        // the spectrum of this line: transform of the lag column, placed circularly
+        // (it is real because the lag box is centrally symmetric)
+        const C* kin = static_cast<const C*>(a.kt) + w;
+        C kv[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int p = t + T * m;
+            const int idx = p <= a.kt_len ? p + a.kt_len : (p >= P - a.kt_len ? p - P + a.kt_len : -1);
+            kv[m] = (act && idx >= 0) ? kin[idx * a.kt_ps] : C{0, 0};
+        }
+        fft_line<R, P, B>(kv, lds + b, t);
+        fft_line<R, P, B>(v, lds + b, t);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = scal(v[m], kv[m].re);
+        ifft_line<R, P, B>(v, lds + b, t);
+    } else if constexpr (MODE == kColInvPrefix) {
         ifft_line<R, P, B>(v, lds + b, t);
     } else {
         fft_line<R, P, B>(v, lds + b, t);
@@ -540,25 +604,36 @@ hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* la
 }
 
 template <typename R, int P>
-hipError_t rows_r2c_launch(int kind, const void* in, int64_t nrows, int64_t in_ld, int len, void* out,
-                           int64_t out_ld, bool out_real, hipStream_t s) {
+hipError_t rows_r2c_launch(int kind, const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len,
+                           void* out, int64_t out_ld, bool out_real, hipStream_t s) {
     const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
     const dim3 g(static_cast<unsigned>(blocks)), blk(256);
+    GaussR<R> gw{};
     if (kind == kRowCountsU64) {
-        if (out_real)
-            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, true>), g, blk, 0, s, in, nrows, in_ld,
-                               len, out, out_ld);
-        else
-            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false>), g, blk, 0, s, in, nrows, in_ld,
-                               len, out, out_ld);
-    } else {
-        if (out_real)
-            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowLagsCirc, true>), g, blk, 0, s, in, nrows, in_ld,
-                               len, out, out_ld);
-        else
-            hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowLagsCirc, false>), g, blk, 0, s, in, nrows, in_ld,
-                               len, out, out_ld);
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false>), g, blk, 0, s, in, gw, nrows, in_ld, len,
+                           out, out_ld);
+        return hipGetLastError();
     }
+    gw.a00 = static_cast<R>(gauss->A[0]);
+    gw.a01 = static_cast<R>(gauss->A[1]);
+    gw.a02 = static_cast<R>(gauss->A[2]);
+    gw.a11 = static_cast<R>(gauss->A[4]);
+    gw.a12 = static_cast<R>(gauss->A[5]);
+    gw.a22 = static_cast<R>(gauss->A[8]);
+    gw.norm = static_cast<R>(gauss->norm);
+    gw.L0 = gauss->L[0];
+    gw.L1 = gauss->L[1];
+    if (gauss->d == 1) {
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, in, gw, nrows, in_ld, len,
+                           out, out_ld);
+    } else if (gauss->d == 2) {
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, in, gw, nrows, in_ld,
+                           len, out, out_ld);
+    } else {
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, in, gw, nrows, in_ld,
+                           len, out, out_ld);
+    }
+    (void)out_real;
     return hipGetLastError();
 }
 
@@ -589,6 +664,7 @@ hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
         case kColFwdCircReal: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCircReal>), g, blk, 0, s, a); break;
         case kColConv: hipLaunchKernelGGL((cols_kernel<R, P, kColConv>), g, blk, 0, s, a); break;
         case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix>), g, blk, 0, s, a); break;
+        case kColConvLag: hipLaunchKernelGGL((cols_kernel<R, P, kColConvLag>), g, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -597,11 +673,11 @@ hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
 #define KDE_FOR_EACH_P(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename R>
-hipError_t rows_r2c_any(int P, int kind, const void* in, int64_t nrows, int64_t in_ld, int len, void* out,
-                        int64_t out_ld, bool out_real, hipStream_t s) {
+hipError_t rows_r2c_any(int P, int kind, const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len,
+                        void* out, int64_t out_ld, bool out_real, hipStream_t s) {
     switch (P) {
 #define KDE_CASE(PP) \
-    case PP: return rows_r2c_launch<R, PP>(kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
+    case PP: return rows_r2c_launch<R, PP>(kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -645,10 +721,11 @@ hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], doub
     return kfill_launch<float, 3>(L, A, norm, lags, s);
 }
 
-hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, int64_t nrows, int64_t in_ld,
-                           int len, void* out, int64_t out_ld, bool out_real, hipStream_t s) {
-    if (prec == 2) return rows_r2c_any<double>(P, input_kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
-    return rows_r2c_any<float>(P, input_kind, in, nrows, in_ld, len, out, out_ld, out_real, s);
+hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, const GaussLag* gauss, int64_t nrows,
+                           int64_t in_ld, int len, void* out, int64_t out_ld, bool out_real, hipStream_t s) {
+    if (prec == 2)
+        return rows_r2c_any<double>(P, input_kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
+    return rows_r2c_any<float>(P, input_kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
 }
 
 hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult,

@@ -21,10 +21,69 @@ struct BinConsts {
     double top[3];          // M_k - 1 as a double
 };
 
+// Tiled binning: the grid is cut into tiles of T_1 x ... x T_d cells; every
+// (sample, tile) pair the sample's 2^d corners touch becomes one packed 64-bit
+// record (tile-local lower corner + 1 and the d fixed-point fractions q), the
+// records are bucketed by tile with a counting sort, and each tile is summed
+// in LDS and stored with plain writes.
+constexpr int kBinThreads = 256;
+constexpr int kBinChunk = kBinThreads * 16;   // samples per histogram / scatter workgroup
+constexpr int kMaxTiles = 8192;
+constexpr int kMaxTileCells = 4096;
+constexpr int kSegment = 4096;                // records per accumulation segment
+
+struct TileGeom {
+    int T[3];               // tile extent (cells, power of two) per axis
+    int logT[3];
+    int nt[3];              // tiles per axis
+    int ntiles;
+    int tile_cells;         // prod T
+    int jbits[3];           // record bits of (tile-local lower corner + 1) per axis
+    int qbits;              // record bits of one fraction q (Q + 1)
+    int S;                  // records per accumulation segment
+    int64_t nchunk;         // ceil(n / kBinChunk)
+    int64_t max_records;    // n 2^d
+    int64_t max_segments;   // ntiles + ceil(max_records / S)
+};
+
+struct BinWork {
+    uint32_t* hist;         // [nchunk][ntiles] counts, then exclusive offsets over chunks
+    uint32_t* tot;          // [ntiles] records per tile
+    uint32_t* drops;        // [nchunk] dropped samples per chunk
+    uint32_t* tile_start;   // [ntiles + 1] first record of each tile
+    uint32_t* seg_base;     // [ntiles + 1] first segment of each tile
+    uint4* seg_info;        // [max_segments] (tile, first record, end record, tile has several segments)
+    uint32_t* nseg_total;   // [1] number of segments
+    uint64_t* records;      // [max_records]
+    uint64_t* partial;      // [max_segments][tile_cells] sums of segments of shared tiles
+    uint32_t* shared_tiles; // [ntiles] tiles with several segments (first nshared entries)
+    uint32_t* nshared;      // [1]
+};
+
+hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
+                           hipStream_t s);
+hipError_t launch_bin_scan(const TileGeom& g, const BinWork& w, uint64_t* n_dropped, hipStream_t s);
+hipError_t launch_bin_scatter(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
+                              hipStream_t s);
+hipError_t launch_bin_accum(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
+                            hipStream_t s);
+hipError_t launch_bin_reduce(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
+                             hipStream_t s);
+
 // Input kinds of the row (contiguous-axis) real-to-complex pass.
 enum RowInput : int {
     kRowCountsU64 = 0,      // uint64 counts, first `len` entries of each row nonzero
-    kRowLagsCirc = 1,       // lag box rows of 2L+1 reals, placed circularly (lag l at l mod P)
+    kRowGaussCirc = 1,      // kernel weights of the lag box computed in place (GaussLag),
+                            // placed circularly (lag l at l mod P)
+};
+
+// k_l = norm exp(-0.5 l'Al) on the lag box [-L, L]^d; A_ab = delta_a delta_b (H^-1)_ab.
+// Row r of the row pass is the lag box row with leading lags (l_1, .., l_{d-1}).
+struct GaussLag {
+    double A[9];
+    double norm;
+    int d;
+    int L[3];
 };
 
 // Modes of the strided-axis pass.
@@ -34,6 +93,8 @@ enum ColMode : int {
     kColFwdCircReal = 2,    // as kColFwdCirc, store the real part only
     kColConv = 3,           // forward FFT of [0, len), times real spectrum, inverse, keep [0, mout)
     kColInvPrefix = 4,      // inverse FFT of all P; keep [0, mout)
+    kColConvLag = 5,        // as kColConv, but the spectrum line is the FFT of a circularly
+                            // placed lag column (kt, 2 kt_len + 1 entries) computed in place
 };
 
 struct ColArgs {
@@ -47,6 +108,9 @@ struct ColArgs {
     int64_t k_ps;           // spectrum element stride (its line stride is 1)
     int len;                // nonzero input prefix length, or L for circular inputs
     int mout;               // kept output prefix length
+    const void* kt;         // kColConvLag: lag columns transformed along the other axes
+    int64_t kt_ps;          // their element stride (line stride is 1)
+    int kt_len;             // their half width L (2 L + 1 entries per column)
 };
 
 // All launchers return hipSuccess or the launch error.
@@ -56,8 +120,8 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
 // k_l = norm exp(-0.5 l'Al) on the lag box; A is d x d row-major, in FP64 from the host.
 hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], double norm,
                         void* lags, hipStream_t s);
-hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, int64_t nrows,
-                           int64_t in_ld, int len, void* out, int64_t out_ld, bool out_real,
+hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, const GaussLag* gauss,
+                           int64_t nrows, int64_t in_ld, int len, void* out, int64_t out_ld, bool out_real,
                            hipStream_t s);
 hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64_t in_ld,
                            const void* mult, void* out, int64_t out_ld, int mout, double scale,

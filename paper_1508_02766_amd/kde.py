@@ -55,7 +55,7 @@ class KdePlan(ctypes.Structure):
                 ("delta", ctypes.c_double * 3), ("lambda_max", ctypes.c_double), ("det_H", ctypes.c_double),
                 ("norm", ctypes.c_double), ("lag_count", ctypes.c_int64), ("lag_bytes", ctypes.c_size_t),
                 ("conv_ws_bytes", ctypes.c_size_t), ("eval_ws_bytes", ctypes.c_size_t),
-                ("density_bytes", ctypes.c_size_t)]
+                ("density_bytes", ctypes.c_size_t), ("bin_ws_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -77,7 +77,7 @@ def lib() -> ctypes.CDLL:
         vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
         G, Pp = ctypes.POINTER(KdeGrid), ctypes.POINTER(KdeParams)
         L.kde_plan_query.argtypes = [vp, i64, G, Pp, ctypes.POINTER(KdePlan)]
-        L.kde_bin.argtypes = [vp, i64, G, Pp, vp, vp, vp]
+        L.kde_bin.argtypes = [vp, i64, G, Pp, vp, vp, vp, sz, vp]
         L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
         L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
@@ -178,9 +178,13 @@ def _ptr(t) -> ctypes.c_void_p:
 # ---------------------------------------------------------------------------
 
 def kde_plan_query(H, n: int, grid, **opts) -> dict:
+    """Host plan; with H None only the binning quantities are filled (n >= 0)."""
     g = _grid(grid)
     p, _ = _params(**opts)
-    Hn, Hp = _H(H, g.d)
+    if H is None:
+        Hn, Hp = None, ctypes.c_void_p(0)
+    else:
+        Hn, Hp = _H(H, g.d)
     out = KdePlan()
     _check(lib().kde_plan_query(Hp, int(n), ctypes.byref(g), ctypes.byref(p), ctypes.byref(out)), "kde_plan_query")
     d = out.d
@@ -189,6 +193,7 @@ def kde_plan_query(H, n: int, grid, **opts) -> dict:
         "delta": tuple(out.delta[:d]), "lambda_max": out.lambda_max, "det_H": out.det_H, "norm": out.norm,
         "lag_count": out.lag_count, "lag_bytes": out.lag_bytes, "conv_ws_bytes": out.conv_ws_bytes,
         "eval_ws_bytes": out.eval_ws_bytes, "density_bytes": out.density_bytes,
+        "bin_ws_bytes": out.bin_ws_bytes,
     }
 
 
@@ -200,7 +205,7 @@ def _workspace(nbytes: int, device, ws=None) -> torch.Tensor:
     return ws
 
 
-def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, **opts):
+def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, ws=None, **opts):
     """Fixed-point counts (uint64 in units 2^-dQ, returned as a torch.uint64 tensor) and n_dropped."""
     g = _grid(grid)
     _need_cuda(X, torch.float64, "X")
@@ -211,9 +216,11 @@ def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, **opts):
         counts = torch.empty(_grid_shape(g), dtype=torch.uint64, device=dev)
     if n_dropped is None:
         n_dropped = torch.empty(1, dtype=torch.uint64, device=dev)
+    need = kde_plan_query(None, X.shape[0], g, **{k: v for k, v in opts.items() if k in ("Q",)})["bin_ws_bytes"]
+    ws = _workspace(need, dev, ws) if need else ws
     p, keep = _params(**opts)
     _check(lib().kde_bin(_ptr(X), X.shape[0], ctypes.byref(g), ctypes.byref(p), _ptr(counts), _ptr(n_dropped),
-                         _stream(dev)), "kde_bin")
+                         _ptr(ws), ws.numel() if ws is not None else 0, _stream(dev)), "kde_bin")
     _finish_trace(keep)
     return counts, n_dropped
 
@@ -316,12 +323,12 @@ def prepare_conv(counts: torch.Tensor, n: int, H, grid, out: torch.Tensor, ws: t
     return _Prepared(lib().kde_conv, args, keep, (g, p, Hn), "kde_conv")
 
 
-def prepare_bin(X: torch.Tensor, grid, counts: torch.Tensor, n_dropped=None, **opts) -> PreparedCall:
+def prepare_bin(X: torch.Tensor, grid, counts: torch.Tensor, n_dropped=None, ws=None, **opts) -> PreparedCall:
     g = _grid(grid)
     _need_cuda(X, torch.float64, "X")
     p, keep = _params(**opts)
     args = (_ptr(X), X.shape[0], ctypes.byref(g), ctypes.byref(p), _ptr(counts), _ptr(n_dropped),
-            _stream(X.device))
+            _ptr(ws), ws.numel() if ws is not None else 0, _stream(X.device))
     return _Prepared(lib().kde_bin, args, keep, (g, p), "kde_bin")
 
 

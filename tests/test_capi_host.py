@@ -69,6 +69,16 @@ def test_plan_random_spd_matches_oracle():
         assert plan["lambda_max"] == pytest.approx(O.lambda_max(H), rel=1e-12)
 
 
+def test_plan_binning_only():
+    """With H = NULL the planner fills the binning quantities and accepts n = 0."""
+    g = ([-1.0, -1.0], [1.0, 1.0], [512, 512])
+    p = K.kde_plan_query(None, 10 ** 6, g)
+    assert p["Q"] == 16 and p["bin_ws_bytes"] > 8 * 4 * 10 ** 6 and p["L"] == (0, 0)
+    assert K.kde_plan_query(None, 0, g)["bin_ws_bytes"] == 0
+    # Q too large for a 64-bit record falls back to atomics: no workspace
+    assert K.kde_plan_query(None, 10, g, Q=30)["bin_ws_bytes"] == 0
+
+
 def test_plan_overrides_and_precision():
     w = W.mix2d_small()
     g = (w.lo, w.hi, w.M)
@@ -120,8 +130,15 @@ def test_device_entry_points_reject_before_enqueue():
     H = np.array([[0.09, 0.06], [0.06, 0.08]])
     Hp = H.ctypes.data_as(ctypes.c_void_p)
     null = ctypes.c_void_p(0)
-    assert lib.kde_bin(null, 10, ctypes.byref(bad), ctypes.byref(p), ctypes.c_void_p(8), null, null) == -1
-    assert lib.kde_bin(null, 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), null, null) == -1
+    assert lib.kde_bin(null, 10, ctypes.byref(bad), ctypes.byref(p), ctypes.c_void_p(8), null, null, 0, null) == -1
+    assert lib.kde_bin(null, 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), null, null, 0, null) == -1
+    # the tiled binning needs its workspace: missing / misaligned / too small
+    assert lib.kde_bin(ctypes.c_void_p(8), 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), null, null, 0,
+                       null) == -1
+    assert lib.kde_bin(ctypes.c_void_p(8), 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), null,
+                       ctypes.c_void_p(100), 1 << 30, null) == -1
+    assert lib.kde_bin(ctypes.c_void_p(8), 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), null,
+                       ctypes.c_void_p(256), 16, null) == -4
     assert lib.kde_eval(ctypes.c_void_p(8), 0, Hp, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8),
                         ctypes.c_void_p(256), 1 << 30, null, null) == -1      # n = 0
     assert lib.kde_eval(ctypes.c_void_p(8), 10, Hp, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8),

@@ -78,6 +78,44 @@ def test_bin_ragged_bit_exact(d, M, Q):
     assert np.array_equal(got, ref)
 
 
+def test_bin_tile_edges_bit_exact():
+    """Samples whose cell straddles the edges of the 32 x 32 binning tiles (copied to each tile they touch)."""
+    lo, hi, M = np.array([0.0, 0.0]), np.array([99.0, 99.0]), (100, 100)   # unit spacing
+    rng = np.random.default_rng(3)
+    edge = np.array([31.0, 31.5, 31.999, 32.0, 32.25, 63.5, 64.0, 95.75, 98.5, 99.0, 0.0, 0.5])
+    X = np.stack(np.meshgrid(edge, edge, indexing="ij"), axis=-1).reshape(-1, 2)
+    X = np.concatenate([X, rng.uniform(0, 99, size=(5000, 2)), np.repeat(X, 50, axis=0)])
+    ref, rnd = O.bin_fixed(X, lo, hi, M)
+    got, gnd = _counts(X, lo, hi, M)
+    assert gnd == rnd == 0
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("d,M,Q", [(2, (300, 3), 27), (1, (50,), 60), (3, (9, 10, 11), 20)])
+def test_bin_atomic_fallback_bit_exact(d, M, Q):
+    """Records wider than 64 bits (large Q) take the global-atomic kernel; same results."""
+    plan = K.kde_plan_query(None, 10, ([0.0] * d, [1.0] * d, M), Q=Q)
+    assert plan["bin_ws_bytes"] == 0
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-0.1, 1.1, size=(10, d))
+    X[0] = 1.0
+    ref, rnd = O.bin_fixed(X, [0.0] * d, [1.0] * d, M, Q)
+    got, gnd = _counts(X, [0.0] * d, [1.0] * d, M, Q=Q)
+    assert gnd == rnd
+    assert np.array_equal(got, ref)
+
+
+def test_bin_heavy_tile_segments():
+    """All samples in one tile: thousands of records in one bucket, summed by many segments."""
+    rng = np.random.default_rng(5)
+    X = rng.normal(0.0, 0.05, size=(300_000, 2))
+    lo, hi, M = np.array([-1.0, -1.0]), np.array([1.0, 1.0]), (512, 512)
+    ref, rnd = O.bin_fixed(X, lo, hi, M)
+    got, gnd = _counts(X, lo, hi, M)
+    assert gnd == rnd
+    assert np.array_equal(got, ref)
+
+
 def test_bin_empty_and_order_independent():
     got, gnd = _counts(np.zeros((0, 2)), [0.0, 0.0], [1.0, 1.0], (8, 8))
     assert gnd == 0 and not got.any()
@@ -269,10 +307,72 @@ def test_trace_events_record_every_kernel():
     K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), trace_events=evs, trace=tr)
     torch.cuda.synchronize()
     assert tr["count"] == len(tr["names"]) + 1
-    assert tr["names"][:3] == ["zero_counts", "zero_dropped", "bin"] and tr["names"][-1] == "c2r"
+    assert tr["names"][:6] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "bin_reduce", "kspec_r2c"]
+    assert tr["names"][-1] == "c2r"
     for i in range(1, tr["count"]):
         ms = ctypes.c_float()
         assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(evs[i - 1]), ctypes.c_void_p(evs[i])) == 0
         assert ms.value >= 0.0
     for e in evs:
         hip.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def _hip_events(n):
+    import ctypes
+    hip = K.lib()
+    evs = []
+    for _ in range(n):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e.value)
+    return evs
+
+
+def test_overlapped_spectrum_matches_serial():
+    """Untraced calls compute the kernel spectrum on a second stream; traced calls run
+    serially on one stream. Same kernels, same arithmetic: bit-identical densities."""
+    for name, M in (("2d", 256), ("3d", 64)):
+        w = W.mix2d_512(n=200_000, M=M) if name == "2d" else W.mix3d_128(n=200_000, M=M)
+        g = (w.lo, w.hi, w.M)
+        X = _dev(w.X)
+        a = K.kde_eval(X, w.H, g)[0].cpu().numpy()
+        tr = {}
+        b = K.kde_eval(X, w.H, g, trace_events=_hip_events(16), trace=tr)[0].cpu().numpy()
+        assert tr["count"] > 5
+        assert np.array_equal(a, b)
+        f = K.kde_conv(K.kde_bin(X, g)[0], w.n, w.H, g).cpu().numpy()
+        assert np.array_equal(a, f)
+
+
+def test_graph_capture_replays_match_eager():
+    """The whole estimate captured in a HIP graph: every replay (with eager work and
+    synchronisations in between) reproduces the eager result exactly."""
+    w = W.mix2d_512(n=100_000, M=128)
+    g = (w.lo, w.hi, w.M)
+    X = _dev(w.X)
+    plan = K.kde_plan_query(w.H, w.n, g)
+    ws = torch.empty(plan["eval_ws_bytes"], dtype=torch.uint8, device=DEV)
+    out = torch.empty(w.M, dtype=torch.float32, device=DEV)
+    nd = torch.empty(1, dtype=torch.uint64, device=DEV)
+    K.kde_eval(X, w.H, g, out=out, ws=ws, n_dropped=nd)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        K.kde_eval(X, w.H, g, out=out, ws=ws, n_dropped=nd)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        K.kde_eval(X, w.H, g, out=out, ws=ws, n_dropped=nd)
+    w2 = W.mix2d_512(n=50_000, M=96, seed_offset=1)
+    X2 = _dev(w2.X)
+    for rep in range(3):
+        out.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        other = K.kde_eval(X2, w2.H, (w2.lo, w2.hi, w2.M))[0]     # eager work between replays
+        torch.cuda.synchronize()
+        assert float(other.sum()) > 0
