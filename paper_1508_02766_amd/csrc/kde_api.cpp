@@ -32,13 +32,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     // offsets into the convolution workspace
-    size_t lags = 0, khat = 0, kt1 = 0, kt2 = 0, z1 = 0, z2 = 0, total = 0;
+    size_t khat = 0, kt1 = 0, kt2 = 0, z1 = 0, z2 = 0, total = 0;
 };
 
 struct BinLayout {
     // offsets into the binning workspace (tiled path)
-    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, seg_base = 0, seg_info = 0, nseg = 0, records = 0,
-           partial = 0, shared_tiles = 0, nshared = 0, total = 0;
+    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, records = 0, partial = 0, total = 0;
 };
 
 struct Plan {
@@ -105,14 +104,9 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, kde::TileGeom* tg, Bi
     bl->hist = take(static_cast<size_t>(g.nchunk) * g.ntiles * 4);
     bl->tot = take(static_cast<size_t>(g.ntiles) * 4);
     bl->drops = take(static_cast<size_t>(g.nchunk) * 4);
-    bl->tile_start = take(static_cast<size_t>(g.ntiles + 1) * 4);
-    bl->seg_base = take(static_cast<size_t>(g.ntiles + 1) * 4);
-    bl->seg_info = take(static_cast<size_t>(g.max_segments) * 16);
-    bl->nseg = take(4);
+    bl->tile_start = take(static_cast<size_t>(g.ntiles) * 4);
     bl->records = take(static_cast<size_t>(g.max_records) * 8);
     bl->partial = take(static_cast<size_t>(g.max_segments) * g.tile_cells * 8);
-    bl->shared_tiles = take(static_cast<size_t>(g.ntiles) * 4);
-    bl->nshared = take(4);
     bl->total = off;
     *tg = g;
     return true;
@@ -366,13 +360,8 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
         w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
         w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
         w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
-        w.seg_base = reinterpret_cast<uint32_t*>(ws + b.seg_base);
-        w.seg_info = reinterpret_cast<uint4*>(ws + b.seg_info);
-        w.nseg_total = reinterpret_cast<uint32_t*>(ws + b.nseg);
         w.records = reinterpret_cast<uint64_t*>(ws + b.records);
         w.partial = reinterpret_cast<uint64_t*>(ws + b.partial);
-        w.shared_tiles = reinterpret_cast<uint32_t*>(ws + b.shared_tiles);
-        w.nshared = reinterpret_cast<uint32_t*>(ws + b.nshared);
         KDE_LAUNCH(kde::launch_bin_hist(c, pl.tg, w, X, n, s), "bin_hist");
         KDE_LAUNCH(kde::launch_bin_scan(pl.tg, w, n_dropped, s), "bin_scan");
         KDE_LAUNCH(kde::launch_bin_scatter(c, pl.tg, w, X, n, s), "bin_scatter");

@@ -20,6 +20,9 @@
 //     accum    LDS sum of one segment (<= S records) of one tile; a tile with
 //              one segment is stored directly, others as partial sub-grids
 //     reduce   sum of the partial sub-grids of tiles with several segments
+//   The accumulate and reduce workgroups rebuild the segment -> tile map from
+//   the tile totals in LDS, so no pass ends waiting on one workgroup's
+//   bookkeeping.
 //   A sample whose corners straddle a tile edge gets one record per tile it
 //   touches, so every cell is owned by exactly one tile and no global atomic
 //   is needed anywhere.
@@ -154,15 +157,15 @@ template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
                                                                TileGeom g, uint32_t* __restrict__ hist,
                                                                uint32_t* __restrict__ drops) {
-    __shared__ uint32_t h[kMaxTiles];
+    extern __shared__ uint32_t h[];     // [ntiles]
     __shared__ uint32_t nd;
     const int tid = threadIdx.x;
+    double x[kPer][D];
+    bool valid[kPer];
+    load_chunk<D>(X, n, blockIdx.x, x, valid);   // in flight while the histogram is cleared
     for (int t = tid; t < g.ntiles; t += kBinThreads) h[t] = 0;
     if (tid == 0) nd = 0;
     __syncthreads();
-    double x[kPer][D];
-    bool valid[kPer];
-    load_chunk<D>(X, n, blockIdx.x, x, valid);
     uint32_t dropped = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -226,56 +229,20 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(TileGeom g, uint3
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
                                                                   TileGeom g, BinWork w) {
-    __shared__ uint32_t cur[kMaxTiles];
+    extern __shared__ uint32_t cur[];   // [ntiles]
     __shared__ uint32_t wave_sums[kBinThreads / 64];
     const int tid = threadIdx.x;
+    double x[kPer][D];
+    bool valid[kPer];
+    load_chunk<D>(X, n, blockIdx.x, x, valid);   // in flight during the prologue
     for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] = w.tot[t];
     __syncthreads();
-    const uint32_t total = block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
-    if (blockIdx.x == 0) {
-        // publish tile starts and the segment -> tile map for the accumulation pass
+    block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
+    if (blockIdx.x == 0)
         for (int t = tid; t < g.ntiles; t += kBinThreads) w.tile_start[t] = cur[t];
-        if (tid == 0) w.tile_start[g.ntiles] = total;
-        __shared__ uint32_t nseg[kMaxTiles];
-        for (int t = tid; t < g.ntiles; t += kBinThreads) {
-            const uint32_t cnt = w.tot[t];
-            const uint32_t ns = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
-            nseg[t] = ns;
-        }
-        __syncthreads();
-        const uint32_t nsegs = block_exclusive_scan(nseg, g.ntiles, wave_sums);
-        for (int t = tid; t < g.ntiles; t += kBinThreads) {
-            const uint32_t b = nseg[t];
-            w.seg_base[t] = b;
-            const uint32_t e = t + 1 < g.ntiles ? nseg[t + 1] : nsegs;
-            const uint32_t start = cur[t];
-            const uint32_t end = start + w.tot[t];
-            for (uint32_t s2 = b; s2 < e; ++s2) {
-                const uint32_t r0 = start + (s2 - b) * static_cast<uint32_t>(g.S);
-                const uint32_t r1 = r0 + static_cast<uint32_t>(g.S) < end ? r0 + static_cast<uint32_t>(g.S) : end;
-                w.seg_info[s2] = make_uint4(static_cast<uint32_t>(t), r0, r1, e - b > 1 ? 1u : 0u);
-            }
-        }
-        if (tid == 0) {
-            w.seg_base[g.ntiles] = nsegs;
-            w.nseg_total[0] = nsegs;
-        }
-        __syncthreads();
-        // compact list of the tiles with several segments (summed by the reduce pass)
-        for (int t = tid; t < g.ntiles; t += kBinThreads) nseg[t] = w.tot[t] > static_cast<uint32_t>(g.S) ? 1u : 0u;
-        __syncthreads();
-        const uint32_t nshared = block_exclusive_scan(nseg, g.ntiles, wave_sums);
-        for (int t = tid; t < g.ntiles; t += kBinThreads)
-            if (w.tot[t] > static_cast<uint32_t>(g.S)) w.shared_tiles[nseg[t]] = static_cast<uint32_t>(t);
-        if (tid == 0) w.nshared[0] = nshared;
-        __syncthreads();
-    }
     const uint32_t* off = w.hist + static_cast<int64_t>(blockIdx.x) * g.ntiles;
     for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += off[t];
     __syncthreads();
-    double x[kPer][D];
-    bool valid[kPer];
-    load_chunk<D>(X, n, blockIdx.x, x, valid);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (!valid[k]) continue;
@@ -325,13 +292,33 @@ __device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const Til
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinConsts c, TileGeom g, BinWork w,
                                                                 uint64_t* __restrict__ counts) {
-    __shared__ unsigned long long grid[kMaxTileCells];
+    extern __shared__ unsigned long long accum_lds[];
+    unsigned long long* grid = accum_lds;                                            // [tile_cells]
+    uint32_t* seg_base = reinterpret_cast<uint32_t*>(accum_lds + g.tile_cells);      // [ntiles]
+    __shared__ uint32_t wave_sums[kBinThreads / 64];
+    __shared__ uint32_t found;
     const int tid = threadIdx.x;
     const uint32_t s = blockIdx.x;
-    if (s >= w.nseg_total[0]) return;
-    const uint4 info = w.seg_info[s];
-    const uint32_t tile = info.x, r0 = info.y, r1 = info.z;
-    const bool shared_tile = info.w != 0;
+    // segment -> tile: prefix of the per-tile segment counts max(1, ceil(tot / S))
+    for (int t = tid; t < g.ntiles; t += kBinThreads) {
+        const uint32_t cnt = w.tot[t];
+        seg_base[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+    }
+    __syncthreads();
+    const uint32_t nsegs = block_exclusive_scan(seg_base, g.ntiles, wave_sums);
+    if (s >= nsegs) return;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) {
+        const uint32_t e = t + 1 < g.ntiles ? seg_base[t + 1] : nsegs;
+        if (seg_base[t] <= s && s < e) found = static_cast<uint32_t>(t);
+    }
+    __syncthreads();
+    const uint32_t tile = found;
+    const uint32_t k = s - seg_base[tile];
+    const uint32_t tcount = w.tot[tile];
+    const uint32_t r0 = w.tile_start[tile] + k * static_cast<uint32_t>(g.S);
+    const uint32_t tend = w.tile_start[tile] + tcount;
+    const uint32_t r1 = r0 + static_cast<uint32_t>(g.S) < tend ? r0 + static_cast<uint32_t>(g.S) : tend;
+    const bool shared_tile = tcount > static_cast<uint32_t>(g.S);
     // this thread's records, loaded together
     constexpr int kRec = kSegment / kBinThreads;
     uint64_t recs[kRec];
@@ -389,20 +376,39 @@ __global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinConsts c, Til
 }
 
 // Tiles with several segments: sum their partial sub-grids into the counts
-// (the kernel boundary orders these reads after every partial store). Work
-// items are (shared tile, block of 64 cells); the 4 wavefronts of a workgroup
-// sum interleaved segments of the same 64 cells and combine through LDS.
+// (the kernel boundary orders these reads after every partial store). Each
+// workgroup rebuilds the segment prefix and the list of shared tiles from the
+// tile totals, then takes work items (shared tile, block of 64 cells); its 4
+// wavefronts sum interleaved segments of the same 64 cells and combine
+// through LDS.
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinConsts c, TileGeom g, BinWork w,
                                                                  uint64_t* __restrict__ counts) {
+    extern __shared__ uint32_t reduce_lds[];
+    uint32_t* seg_base = reduce_lds;                     // [ntiles]
+    uint32_t* rank = reduce_lds + g.ntiles;              // [ntiles]
+    uint32_t* shared_list = reduce_lds + 2 * g.ntiles;   // [ntiles]
+    __shared__ uint32_t wave_sums[kBinThreads / 64];
     __shared__ uint64_t part_sum[kBinThreads];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int t = tid; t < g.ntiles; t += kBinThreads) {
+        const uint32_t cnt = w.tot[t];
+        seg_base[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+        rank[t] = cnt > static_cast<uint32_t>(g.S) ? 1u : 0u;
+    }
+    __syncthreads();
+    block_exclusive_scan(seg_base, g.ntiles, wave_sums);
+    const uint32_t nshared = block_exclusive_scan(rank, g.ntiles, wave_sums);
+    for (int t = tid; t < g.ntiles; t += kBinThreads)
+        if (w.tot[t] > static_cast<uint32_t>(g.S)) shared_list[rank[t]] = static_cast<uint32_t>(t);
+    __syncthreads();
     const int blocks_per_tile = (g.tile_cells + 63) / 64;
-    const uint32_t items = w.nshared[0] * static_cast<uint32_t>(blocks_per_tile);
+    const uint32_t items = nshared * static_cast<uint32_t>(blocks_per_tile);
     for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint32_t tile = w.shared_tiles[it / blocks_per_tile];
+        const uint32_t tile = shared_list[it / blocks_per_tile];
         const int i = static_cast<int>(it % blocks_per_tile) * 64 + lane;
-        const uint32_t sb = w.seg_base[tile], nseg = w.seg_base[tile + 1] - sb;
+        const uint32_t cnt = w.tot[tile];
+        const uint32_t sb = seg_base[tile], nseg = (cnt + g.S - 1) / g.S;
         const uint64_t* base = w.partial + static_cast<int64_t>(sb) * g.tile_cells;
         uint64_t acc[4] = {0, 0, 0, 0};
         if (i < g.tile_cells) {
@@ -496,12 +502,13 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
 hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
                            hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
+    const size_t lds = static_cast<size_t>(g.ntiles) * 4;
     if (c.d == 1)
-        hipLaunchKernelGGL((bin_hist_kernel<1>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+        hipLaunchKernelGGL((bin_hist_kernel<1>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
     else if (c.d == 2)
-        hipLaunchKernelGGL((bin_hist_kernel<2>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+        hipLaunchKernelGGL((bin_hist_kernel<2>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
     else
-        hipLaunchKernelGGL((bin_hist_kernel<3>), grid, blk, 0, s, X, n, c, g, w.hist, w.drops);
+        hipLaunchKernelGGL((bin_hist_kernel<3>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
     return hipGetLastError();
 }
 
@@ -516,36 +523,39 @@ hipError_t launch_bin_scan(const TileGeom& g, const BinWork& w, uint64_t* n_drop
 hipError_t launch_bin_scatter(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
                               hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
+    const size_t lds = static_cast<size_t>(g.ntiles) * 4;
     if (c.d == 1)
-        hipLaunchKernelGGL((bin_scatter_kernel<1>), grid, blk, 0, s, X, n, c, g, w);
+        hipLaunchKernelGGL((bin_scatter_kernel<1>), grid, blk, lds, s, X, n, c, g, w);
     else if (c.d == 2)
-        hipLaunchKernelGGL((bin_scatter_kernel<2>), grid, blk, 0, s, X, n, c, g, w);
+        hipLaunchKernelGGL((bin_scatter_kernel<2>), grid, blk, lds, s, X, n, c, g, w);
     else
-        hipLaunchKernelGGL((bin_scatter_kernel<3>), grid, blk, 0, s, X, n, c, g, w);
+        hipLaunchKernelGGL((bin_scatter_kernel<3>), grid, blk, lds, s, X, n, c, g, w);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_accum(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
                             hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(g.max_segments)), blk(kBinThreads);
+    const size_t lds = static_cast<size_t>(g.tile_cells) * 8 + static_cast<size_t>(g.ntiles) * 4;
     if (c.d == 1)
-        hipLaunchKernelGGL((bin_accum_kernel<1>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_accum_kernel<1>), grid, blk, lds, s, c, g, w, counts);
     else if (c.d == 2)
-        hipLaunchKernelGGL((bin_accum_kernel<2>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_accum_kernel<2>), grid, blk, lds, s, c, g, w, counts);
     else
-        hipLaunchKernelGGL((bin_accum_kernel<3>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_accum_kernel<3>), grid, blk, lds, s, c, g, w, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_reduce(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
                              hipStream_t s) {
     const dim3 grid(1024), blk(kBinThreads);
+    const size_t lds = static_cast<size_t>(g.ntiles) * 12;
     if (c.d == 1)
-        hipLaunchKernelGGL((bin_reduce_kernel<1>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_reduce_kernel<1>), grid, blk, lds, s, c, g, w, counts);
     else if (c.d == 2)
-        hipLaunchKernelGGL((bin_reduce_kernel<2>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_reduce_kernel<2>), grid, blk, lds, s, c, g, w, counts);
     else
-        hipLaunchKernelGGL((bin_reduce_kernel<3>), grid, blk, 0, s, c, g, w, counts);
+        hipLaunchKernelGGL((bin_reduce_kernel<3>), grid, blk, lds, s, c, g, w, counts);
     return hipGetLastError();
 }
 

@@ -9,7 +9,9 @@
 //                circularly (lag l at position l mod P)
 //   * cols       forward / fused forward x spectrum x inverse / inverse transforms
 //                along a strided axis; a workgroup owns B adjacent lines so each
-//                global access is a contiguous run of B complex values
+//                global access is a contiguous run of B complex values; the
+//                fused pass transforms the lag column of its line in place, so
+//                the spectrum of the slowest axis is never stored
 //   * rows_c2r   inverse transform along the contiguous axis back to real rows,
 //                with the 1/prod(P) and fixed-point scale, keeping the M window
 //
@@ -228,12 +230,49 @@ struct LineShape {
     static constexpr int LDS = P + P / 16;    // padded LDS elements per line
 };
 
+// Radices of the stages after the first radix-16 one.
+template <int P>
+struct Stages {
+    static constexpr int R1 = P > 16 ? ((P / 16 >= 16) ? 16 : P / 16) : 1;   // second stage (NS = 16)
+    static constexpr int R2 = P > 256 ? P / 256 : 1;                         // third stage (NS = 256)
+    static constexpr int N1 = P > 16 ? (16 / R1) * (R1 - 1) : 0;            // twiddles per thread
+    static constexpr int N2 = P > 256 ? (16 / R2) * (R2 - 1) : 0;
+};
+
+// The twiddles one thread uses in the second and third stages, loaded
+// together at the start of the transform so their latency overlaps the first
+// stage instead of stalling each later one.
+template <typename R, int P>
+struct LineTwiddles {
+    cpx<R> w1[Stages<P>::N1 > 0 ? Stages<P>::N1 : 1];
+    cpx<R> w2[Stages<P>::N2 > 0 ? Stages<P>::N2 : 1];
+};
+
+template <typename R, int P, int RAD, int NS, int N>
+__device__ __forceinline__ void load_stage_twiddles(cpx<R> (&w)[N], int t) {
+    constexpr int T = LineShape<P>::T;
+    constexpr int NB = 16 / RAD;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int jm = (t + T * u) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+    }
+}
+
+template <typename R, int P>
+__device__ __forceinline__ void load_twiddles(LineTwiddles<R, P>& tw, int t) {
+    if constexpr (Stages<P>::N1 > 0) load_stage_twiddles<R, P, Stages<P>::R1, 16>(tw.w1, t);
+    if constexpr (Stages<P>::N2 > 0) load_stage_twiddles<R, P, Stages<P>::R2, 256>(tw.w2, t);
+}
+
 // One radix-RAD pass with NS = product of the earlier radices. Thread t owns
 // the butterflies j = t + T u, u < 16/RAD; butterfly j reads elements
 // j + r P/RAD and writes (j / NS) NS RAD + j % NS + r NS. Element
-// t + T m always lives in register slot m.
-template <typename R, int P, int LS, int RAD, int NS>
-__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t) {
+// t + T m always lives in register slot m. `w` holds this thread's twiddles
+// exp(-2 pi i r (j mod NS) / (NS RAD)) for u, r >= 1.
+template <typename R, int P, int LS, int RAD, int NS, int NW>
+__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t, const cpx<R> (&w)[NW]) {
     constexpr int T = LineShape<P>::T;
     constexpr int NB = 16 / RAD;
     constexpr bool kFirst = (NS == 1);
@@ -249,9 +288,8 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t) {
 #pragma unroll
         for (int r = 0; r < RAD; ++r) a[r] = v[u + r * NB];
         if constexpr (NS > 1) {
-            const int jm = (t + T * u) & (NS - 1);
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) a[r] = a[r] * twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+            for (int r = 1; r < RAD; ++r) a[r] = a[r] * w[u * (RAD - 1) + r - 1];
         }
         dft<RAD>(a);
 #pragma unroll
@@ -275,11 +313,12 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t) {
 template <typename R, int P, int LS>
 __device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
     static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
-    fft_stage<R, P, LS, 16, 1>(v, lds, t);
+    LineTwiddles<R, P> tw;
+    load_twiddles<R, P>(tw, t);
+    fft_stage<R, P, LS, 16, 1>(v, lds, t, tw.w1);
     if constexpr (P > 16) {
-        constexpr int R1 = (P / 16 >= 16) ? 16 : P / 16;
-        fft_stage<R, P, LS, R1, 16>(v, lds, t);
-        if constexpr (P > 256) fft_stage<R, P, LS, P / 256, 256>(v, lds, t);
+        fft_stage<R, P, LS, Stages<P>::R1, 16>(v, lds, t, tw.w1);
+        if constexpr (P > 256) fft_stage<R, P, LS, Stages<P>::R2, 256>(v, lds, t, tw.w2);
     }
 }
 
@@ -343,7 +382,8 @@ __global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_
 template <int P>
 struct RowShape {
     static constexpr int T = P / 16;
-    static constexpr int B = (256 / T) >= 1 ? 256 / T : 1;   // lines (row pairs) per workgroup
+    static constexpr int B = (128 / T) >= 1 ? 128 / T : 1;   // lines (row pairs) per workgroup
+    static constexpr int THREADS = T * B;
 };
 
 // Lag-box weight coefficients in the working precision.
@@ -375,7 +415,7 @@ __device__ __forceinline__ void row_lags(const GaussR<R>& g, int64_t r, R& l0, R
 }
 
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D = 1>
-__global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ in_, GaussR<R> gw, int64_t nrows,
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(const void* __restrict__ in_, GaussR<R> gw, int64_t nrows,
                                                        int64_t in_ld, int len, void* __restrict__ out_,
                                                        int64_t out_ld) {
     using C = cpx<R>;
@@ -453,7 +493,7 @@ __global__ __launch_bounds__(256) void rows_r2c_kernel(const void* __restrict__ 
 // ---------------------------------------------------------------------------
 
 template <typename R, int P, bool MULT>
-__global__ __launch_bounds__(256) void rows_c2r_kernel(const cpx<R>* __restrict__ in, int64_t nrows,
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(const cpx<R>* __restrict__ in, int64_t nrows,
                                                        int64_t in_ld, const R* __restrict__ mult,
                                                        R* __restrict__ out, int64_t out_ld, int mout,
                                                        R scale) {
@@ -498,21 +538,24 @@ __global__ __launch_bounds__(256) void rows_c2r_kernel(const cpx<R>* __restrict_
 // cols: transforms along a strided axis, B adjacent lines per workgroup
 // ---------------------------------------------------------------------------
 
-template <typename R, int P>
+// B adjacent lines per workgroup: the widest that fits 72 KiB of LDS and 1024
+// threads (up to 16), or 2 for launches that would otherwise leave CUs idle.
+template <typename R, int P, bool NARROW>
 struct ColShape {
     static constexpr int T = P / 16;
     static constexpr int kLineBytes = LineShape<P>::LDS * static_cast<int>(sizeof(cpx<R>));
     static constexpr int kCap = 73728 / kLineBytes;                 // at most 72 KiB of LDS
     static constexpr int kThr = 1024 / T;
     static constexpr int kRaw = kCap < kThr ? (kCap < 16 ? kCap : 16) : (kThr < 16 ? kThr : 16);
-    static constexpr int B = kRaw >= 16 ? 16 : kRaw >= 8 ? 8 : kRaw >= 4 ? 4 : kRaw >= 2 ? 2 : 1;
+    static constexpr int kWide = kRaw >= 16 ? 16 : kRaw >= 8 ? 8 : kRaw >= 4 ? 4 : kRaw >= 2 ? 2 : 1;
+    static constexpr int B = NARROW ? (kWide < 2 ? kWide : 2) : kWide;
     static constexpr int THREADS = T * B;
 };
 
-template <typename R, int P, int MODE>
-__global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs a) {
+template <typename R, int P, int MODE, bool NARROW>
+__global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
     using C = cpx<R>;
-    constexpr int T = ColShape<R, P>::T, B = ColShape<R, P>::B;
+    constexpr int T = ColShape<R, P, NARROW>::T, B = ColShape<R, P, NARROW>::B;
     __shared__ C lds[B * LineShape<P>::LDS];
     const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
     const int64_t w = static_cast<int64_t>(blockIdx.x) * B + b;
@@ -524,9 +567,9 @@ __global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs
     for (int m = 0; m < 16; ++m) {
         const int p = t + T * m;
         C x{0, 0};
-        if constexpr (MODE == kColFwdPrefix || MODE == kColConv || MODE == kColConvLag) {
+        if constexpr (MODE == kColFwdPrefix || MODE == kColConvLag) {
             if (act && p < a.len) x = in[p * a.in_ps];
-        } else if constexpr (MODE == kColFwdCirc || MODE == kColFwdCircReal) {
+        } else if constexpr (MODE == kColFwdCirc) {
             const int idx = p <= a.len ? p + a.len : (p >= P - a.len ? p - P + a.len : -1);
             if (act && idx >= 0) x = in[idx * a.in_ps];
         } else {   // kColInvPrefix
@@ -555,26 +598,12 @@ __global__ __launch_bounds__((ColShape<R, P>::THREADS)) void cols_kernel(ColArgs
     } else {
         fft_line<R, P, B>(v, lds + b, t);
     }
-    if constexpr (MODE == kColConv) {
-        const R* kh = static_cast<const R*>(a.khat) + w;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int p = t + T * m;
-            const R kk = act ? kh[p * a.k_ps] : R(0);
-            v[m] = scal(v[m], kk);
-        }
-        ifft_line<R, P, B>(v, lds + b, t);
-    }
     if (!act) return;
-    if constexpr (MODE == kColFwdCircReal) {
-        R* out = static_cast<R*>(a.out) + o * a.out_os + w;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m].re;
-    } else if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
+    if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
         C* out = static_cast<C*>(a.out) + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m];
-    } else {   // kColConv (in place) and kColInvPrefix: keep [0, mout)
+    } else {   // kColConvLag (in place) and kColInvPrefix: keep [0, mout)
         C* out = static_cast<C*>(a.out) + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -607,7 +636,7 @@ template <typename R, int P>
 hipError_t rows_r2c_launch(int kind, const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len,
                            void* out, int64_t out_ld, bool out_real, hipStream_t s) {
     const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks)), blk(256);
+    const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
     GaussR<R> gw{};
     if (kind == kRowCountsU64) {
         hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false>), g, blk, 0, s, in, gw, nrows, in_ld, len,
@@ -641,7 +670,7 @@ template <typename R, int P>
 hipError_t rows_c2r_launch(const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
                            int64_t out_ld, int mout, double scale, hipStream_t s) {
     const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks)), blk(256);
+    const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
     if (mult)
         hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, static_cast<const cpx<R>*>(in), nrows,
                            in_ld, static_cast<const R*>(mult), static_cast<R*>(out), out_ld, mout,
@@ -653,21 +682,26 @@ hipError_t rows_c2r_launch(const void* in, int64_t nrows, int64_t in_ld, const v
     return hipGetLastError();
 }
 
-template <typename R, int P>
-hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
-    constexpr int B = ColShape<R, P>::B;
+template <typename R, int P, bool NARROW>
+hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
+    constexpr int B = ColShape<R, P, NARROW>::B;
     const dim3 g(static_cast<unsigned>(ceil_div(a.W, B)), static_cast<unsigned>(a.outer));
-    const dim3 blk(ColShape<R, P>::THREADS);
+    const dim3 blk(ColShape<R, P, NARROW>::THREADS);
     switch (mode) {
-        case kColFwdPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdPrefix>), g, blk, 0, s, a); break;
-        case kColFwdCirc: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCirc>), g, blk, 0, s, a); break;
-        case kColFwdCircReal: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCircReal>), g, blk, 0, s, a); break;
-        case kColConv: hipLaunchKernelGGL((cols_kernel<R, P, kColConv>), g, blk, 0, s, a); break;
-        case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix>), g, blk, 0, s, a); break;
-        case kColConvLag: hipLaunchKernelGGL((cols_kernel<R, P, kColConvLag>), g, blk, 0, s, a); break;
+        case kColFwdPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, a); break;
+        case kColFwdCirc: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, a); break;
+        case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, a); break;
+        case kColConvLag: hipLaunchKernelGGL((cols_kernel<R, P, kColConvLag, NARROW>), g, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
+    // fewer workgroups than CUs with the wide shape: use two lines per workgroup
+    if (ceil_div(a.W, ColShape<R, P, false>::B) * a.outer < 128) return cols_launch_b<R, P, true>(mode, a, s);
+    return cols_launch_b<R, P, false>(mode, a, s);
 }
 
 #define KDE_FOR_EACH_P(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)

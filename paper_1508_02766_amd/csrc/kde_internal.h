@@ -28,7 +28,7 @@ struct BinConsts {
 // in LDS and stored with plain writes.
 constexpr int kBinThreads = 256;
 constexpr int kBinChunk = kBinThreads * 16;   // samples per histogram / scatter workgroup
-constexpr int kMaxTiles = 8192;
+constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
 constexpr int kMaxTileCells = 4096;
 constexpr int kSegment = 4096;                // records per accumulation segment
 
@@ -50,14 +50,9 @@ struct BinWork {
     uint32_t* hist;         // [nchunk][ntiles] counts, then exclusive offsets over chunks
     uint32_t* tot;          // [ntiles] records per tile
     uint32_t* drops;        // [nchunk] dropped samples per chunk
-    uint32_t* tile_start;   // [ntiles + 1] first record of each tile
-    uint32_t* seg_base;     // [ntiles + 1] first segment of each tile
-    uint4* seg_info;        // [max_segments] (tile, first record, end record, tile has several segments)
-    uint32_t* nseg_total;   // [1] number of segments
+    uint32_t* tile_start;   // [ntiles] first record of each tile
     uint64_t* records;      // [max_records]
     uint64_t* partial;      // [max_segments][tile_cells] sums of segments of shared tiles
-    uint32_t* shared_tiles; // [ntiles] tiles with several segments (first nshared entries)
-    uint32_t* nshared;      // [1]
 };
 
 hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
@@ -90,22 +85,19 @@ struct GaussLag {
 enum ColMode : int {
     kColFwdPrefix = 0,      // forward FFT of rows [0, len), zero padded; store all P
     kColFwdCirc = 1,        // forward FFT of a circularly placed lag axis (L = len); store all P
-    kColFwdCircReal = 2,    // as kColFwdCirc, store the real part only
-    kColConv = 3,           // forward FFT of [0, len), times real spectrum, inverse, keep [0, mout)
     kColInvPrefix = 4,      // inverse FFT of all P; keep [0, mout)
-    kColConvLag = 5,        // as kColConv, but the spectrum line is the FFT of a circularly
-                            // placed lag column (kt, 2 kt_len + 1 entries) computed in place
+    kColConvLag = 5,        // forward FFT of [0, len), times the real spectrum line, inverse,
+                            // keep [0, mout); the spectrum line is the FFT of the circularly
+                            // placed lag column (kt, 2 kt_len + 1 entries), computed in place
 };
 
 struct ColArgs {
     const void* in;
     void* out;
-    const void* khat;       // real spectrum for kColConv
     int64_t W;              // lines per outer index (lines are adjacent in memory)
     int64_t outer;          // number of outer indices (grid.y)
     int64_t in_os, in_ps;   // input: outer stride, element stride (complex elements)
     int64_t out_os, out_ps; // output: outer stride, element stride
-    int64_t k_ps;           // spectrum element stride (its line stride is 1)
     int len;                // nonzero input prefix length, or L for circular inputs
     int mout;               // kept output prefix length
     const void* kt;         // kColConvLag: lag columns transformed along the other axes
