@@ -26,6 +26,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1508_02766_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    readings, scaled by what the same counters read for a plain copy of known
+    size; None when the kernels changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except OSError:
+        return None
+    if c.get("source_sha256") != kernel_source_hash():
+        return None
+    k = c.get("workloads", {}).get(workload, {}).get(kernel)
+    cal = c.get("copy_calibration", {}).get(workload)
+    if not k or not cal:
+        return None
+    return int((k["FETCH_SIZE"] * cal["fetch_factor"] + k["WRITE_SIZE"] * cal["write_factor"]) * 1024)
 
 
 def parse():
@@ -38,6 +67,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / FP64 side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -164,6 +195,9 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         us = float(np.mean(per[nm])) * 1e3
         b = kernel_bytes(nm, w, plan, prec)
         kern[nm] = {"us": round(us, 3), "alg_bytes": int(b), "alg_GBs": round(b / (us * 1e-6) / 1e9, 1)}
+        hbm = measured_traffic(name, nm) if prec == "f32" else None
+        if hbm is not None:
+            kern[nm]["hbm_bytes"] = hbm
     conv_us = sum(v["us"] for k, v in kern.items() if k in CONV_KERNELS)
     bin_us = sum(v["us"] for k, v in kern.items() if k not in CONV_KERNELS)
     cells = int(np.prod(w.M))
@@ -219,8 +253,16 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["us"])
     ach = kern[dom]["alg_bytes"] / (kern[dom]["us"] * 1e-6) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(a.workload, dom) if a.prec == "f32" else None,
             "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_us": kern[dom]["us"]}
+    if a.copy_mb:
+        src = torch.ones(a.copy_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cpu = None if a.no_cpu else cpu_baseline(W, a.workload, a.cpu_reps)
     line = {
         "metric": "samples/s and grid pts/s for 2-D 512^2 / 3-D 128^3 KDE, FP32 vs FP64, % HBM peak",

@@ -30,6 +30,11 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// Row pitch (complex elements) of half spectra along the last axis: P/2 + 1
+// bins, padded to a multiple of 16 so that every 16-column block a strided
+// pass reads starts on a 128-byte boundary.
+int64_t half_pitch(int P) { return (static_cast<int64_t>(P) / 2 + 1 + 15) / 16 * 16; }
+
 struct Layout {
     // offsets into the convolution workspace
     size_t khat = 0, kt1 = 0, kt2 = 0, z1 = 0, z2 = 0, total = 0;
@@ -275,7 +280,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     Layout& L = out->lay;
     const int64_t M0 = g->M[0], M1 = d > 1 ? g->M[1] : 1;
     const int64_t P1 = d > 1 ? p.P[1] : 1;
-    const int64_t Hl = p.P[d - 1] / 2 + 1;   // bins kept along the last axis
+    const int64_t Hl = d == 1 ? p.P[0] / 2 + 1 : half_pitch(p.P[d - 1]);   // row pitch of half spectra
     const int64_t n0 = 2 * p.L[0] + 1, n1 = d > 1 ? 2 * p.L[1] + 1 : 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -406,24 +411,24 @@ int run_kspec(const Plan& pl, const kde_grid* g, char* ws, hipStream_t s, Tracer
     }
     if (d == 2) {
         const int P1 = p.P[1];
-        const int64_t H1 = P1 / 2 + 1, n0 = 2 * p.L[0] + 1;
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, H1, false,
+        const int64_t n0 = 2 * p.L[0] + 1;
+        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, half_pitch(P1), false,
                                         s), "kspec_r2c");
         return KDE_OK;
     }
     const int P1 = p.P[1], P2 = p.P[2];
-    const int64_t H2 = P2 / 2 + 1, n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
-    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowGaussCirc, nullptr, &gl, n0 * n1, 0, p.L[2], b.kt1, H2, false,
+    const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
+    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowGaussCirc, nullptr, &gl, n0 * n1, 0, p.L[2], b.kt1, Hp, false,
                                     s), "kspec_r2c");
     kde::ColArgs k1{};
     k1.in = b.kt1;
     k1.out = b.kt2;
     k1.W = H2;
     k1.outer = n0;
-    k1.in_os = n1 * H2;
-    k1.in_ps = H2;
-    k1.out_os = static_cast<int64_t>(P1) * H2;
-    k1.out_ps = H2;
+    k1.in_os = n1 * Hp;
+    k1.in_ps = Hp;
+    k1.out_os = static_cast<int64_t>(P1) * Hp;
+    k1.out_ps = Hp;
     k1.len = p.L[1];
     KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdCirc, k1, s), "kspec_col2");
     return KDE_OK;
@@ -435,12 +440,12 @@ int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, ch
     const int d = p.d, prec = p.prec;
     const ConvBufs b = conv_bufs(pl, ws);
     const int Pl = p.P[d - 1];
-    const int64_t Hl = Pl / 2 + 1;
+    const int64_t Hl = Pl / 2 + 1, Hp = d == 1 ? Hl : half_pitch(Pl);
     const int64_t Ml = g->M[d - 1];
     int64_t rows = 1;
     for (int k = 0; k < d - 1; ++k) rows *= g->M[k];
     KDE_LAUNCH(kde::launch_rows_r2c(prec, Pl, kde::kRowCountsU64, counts, nullptr, rows, Ml, static_cast<int>(Ml), b.z1,
-                                    Hl, false, s), "counts_r2c");
+                                    Hp, false, s), "counts_r2c");
     if (d == 3) {
         const int P1 = p.P[1];
         const int64_t M0 = g->M[0], M1 = g->M[1];
@@ -449,10 +454,10 @@ int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, ch
         f1.out = b.z2;
         f1.W = Hl;
         f1.outer = M0;
-        f1.in_os = M1 * Hl;
-        f1.in_ps = Hl;
-        f1.out_os = static_cast<int64_t>(P1) * Hl;
-        f1.out_ps = Hl;
+        f1.in_os = M1 * Hp;
+        f1.in_ps = Hp;
+        f1.out_os = static_cast<int64_t>(P1) * Hp;
+        f1.out_ps = Hp;
         f1.len = static_cast<int>(M1);
         KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdPrefix, f1, s), "counts_col2");
     }
@@ -476,36 +481,39 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     }
     if (d == 2) {
         const int P0 = p.P[0], P1 = p.P[1];
-        const int64_t H1 = P1 / 2 + 1, M0 = g->M[0], M1 = g->M[1];
+        const int64_t H1 = P1 / 2 + 1, Hp = half_pitch(P1), M0 = g->M[0], M1 = g->M[1];
         kde::ColArgs ca{};
         ca.in = b.z1;
         ca.out = b.z1;
         ca.kt = b.kt1;
-        ca.kt_ps = H1;
+        ca.kt_ps = Hp;
         ca.kt_len = p.L[0];
         ca.W = H1;
         ca.outer = 1;
-        ca.in_ps = H1;
-        ca.out_ps = H1;
+        ca.in_ps = Hp;
+        ca.out_ps = Hp;
         ca.len = static_cast<int>(M0);
         ca.mout = static_cast<int>(M0);
         KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, ca, s), "conv_col");
-        KDE_LAUNCH(kde::launch_rows_c2r(prec, P1, b.z1, M0, H1, nullptr, density, M1, static_cast<int>(M1), scale, s),
+        KDE_LAUNCH(kde::launch_rows_c2r(prec, P1, b.z1, M0, Hp, nullptr, density, M1, static_cast<int>(M1), scale, s),
                    "c2r");
         return KDE_OK;
     }
     const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2];
-    const int64_t H2 = P2 / 2 + 1, M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
+    const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
     kde::ColArgs cv{};
     cv.in = b.z2;
     cv.out = b.z2;
     cv.kt = b.kt2;
-    cv.W = static_cast<int64_t>(P1) * H2;
-    cv.kt_ps = cv.W;
+    cv.W = H2;                                  // lines (w2, w3): outer index w2, inner w3
+    cv.outer = P1;
+    cv.in_os = Hp;
+    cv.out_os = Hp;
+    cv.kt_os = Hp;
+    cv.in_ps = static_cast<int64_t>(P1) * Hp;   // axis-1 element stride
+    cv.out_ps = cv.in_ps;
+    cv.kt_ps = cv.in_ps;
     cv.kt_len = p.L[0];
-    cv.outer = 1;
-    cv.in_ps = cv.W;
-    cv.out_ps = cv.W;
     cv.len = static_cast<int>(M0);
     cv.mout = static_cast<int>(M0);
     KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, cv, s), "conv_col1");
@@ -514,13 +522,13 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     i1.out = b.z1;
     i1.W = H2;
     i1.outer = M0;
-    i1.in_os = static_cast<int64_t>(P1) * H2;
-    i1.in_ps = H2;
-    i1.out_os = M1 * H2;
-    i1.out_ps = H2;
+    i1.in_os = static_cast<int64_t>(P1) * Hp;
+    i1.in_ps = Hp;
+    i1.out_os = M1 * Hp;
+    i1.out_ps = Hp;
     i1.mout = static_cast<int>(M1);
     KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColInvPrefix, i1, s), "inv_col2");
-    KDE_LAUNCH(kde::launch_rows_c2r(prec, P2, b.z1, M0 * M1, H2, nullptr, density, M2, static_cast<int>(M2), scale, s),
+    KDE_LAUNCH(kde::launch_rows_c2r(prec, P2, b.z1, M0 * M1, Hp, nullptr, density, M2, static_cast<int>(M2), scale, s),
                "c2r");
     return KDE_OK;
 }

@@ -539,7 +539,7 @@ __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(const 
 // ---------------------------------------------------------------------------
 
 // B adjacent lines per workgroup: the widest that fits 72 KiB of LDS and 1024
-// threads (up to 16), or 2 for launches that would otherwise leave CUs idle.
+// threads (up to 16), or 4 for launches that would otherwise leave CUs idle.
 template <typename R, int P, bool NARROW>
 struct ColShape {
     static constexpr int T = P / 16;
@@ -548,7 +548,7 @@ struct ColShape {
     static constexpr int kThr = 1024 / T;
     static constexpr int kRaw = kCap < kThr ? (kCap < 16 ? kCap : 16) : (kThr < 16 ? kThr : 16);
     static constexpr int kWide = kRaw >= 16 ? 16 : kRaw >= 8 ? 8 : kRaw >= 4 ? 4 : kRaw >= 2 ? 2 : 1;
-    static constexpr int B = NARROW ? (kWide < 2 ? kWide : 2) : kWide;
+    static constexpr int B = NARROW ? (kWide < 4 ? kWide : 4) : kWide;
     static constexpr int THREADS = T * B;
 };
 
@@ -580,7 +580,7 @@ __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel
     if constexpr (MODE == kColConvLag) {
         // the spectrum of this line: transform of the lag column, placed circularly
         // (it is real because the lag box is centrally symmetric)
-        const C* kin = static_cast<const C*>(a.kt) + w;
+        const C* kin = static_cast<const C*>(a.kt) + o * a.kt_os + w;
         C kv[16];
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
@@ -699,7 +699,7 @@ hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
 
 template <typename R, int P>
 hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
-    // fewer workgroups than CUs with the wide shape: use two lines per workgroup
+    // far fewer workgroups than CUs with the wide shape: use four lines per workgroup
     if (ceil_div(a.W, ColShape<R, P, false>::B) * a.outer < 128) return cols_launch_b<R, P, true>(mode, a, s);
     return cols_launch_b<R, P, false>(mode, a, s);
 }

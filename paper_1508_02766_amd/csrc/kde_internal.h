@@ -101,7 +101,7 @@ struct ColArgs {
     int len;                // nonzero input prefix length, or L for circular inputs
     int mout;               // kept output prefix length
     const void* kt;         // kColConvLag: lag columns transformed along the other axes
-    int64_t kt_ps;          // their element stride (line stride is 1)
+    int64_t kt_os, kt_ps;   // their outer and element strides (line stride is 1)
     int kt_len;             // their half width L (2 L + 1 entries per column)
 };
 
