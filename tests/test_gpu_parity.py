@@ -161,7 +161,8 @@ CONV_CASES = [
     (2, (24, 19), 8, (23, 18), 1.0),       # full lag box, L = M - 1
     (3, (20, 17, 23), 9, None, 1.0),
     (3, (33, 40, 31), 10, None, 2.0),
-    (3, (6, 5, 4), 11, (5, 4, 3), 1.0),
+    (3, (6, 5, 4), 11, (5, 4, 3), 1.0),    # P = 16: separate row / column passes
+    (3, (24, 40, 10), 13, None, 1.0),      # P = (32, 64, 16): P_2 != P_3, separate passes
 ]
 
 
