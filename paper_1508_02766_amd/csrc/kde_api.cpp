@@ -341,8 +341,26 @@ struct Tracer {
         KDE_TRY(tr.mark(name));             \
     } while (0)
 
-int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
-            char* ws, hipStream_t s, Tracer& tr) {
+kde::BinArgs bin_args(const Plan& pl, const kde::BinConsts& c, const double* X, int64_t n, uint64_t* counts,
+                      uint64_t* n_dropped, char* ws) {
+    const BinLayout& b = pl.blay;
+    kde::BinArgs a{};
+    a.X = X;
+    a.n = n;
+    a.c = c;
+    a.g = pl.tg;
+    a.w.hist = reinterpret_cast<uint32_t*>(ws + b.hist);
+    a.w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
+    a.w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
+    a.w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
+    a.w.records = reinterpret_cast<uint64_t*>(ws + b.records);
+    a.w.partial = reinterpret_cast<uint64_t*>(ws + b.partial);
+    a.counts = counts;
+    a.n_dropped = reinterpret_cast<unsigned long long*>(n_dropped);
+    return a;
+}
+
+kde::BinConsts bin_consts(const Plan& pl, const kde_grid* g) {
     const int d = pl.pub.d;
     kde::BinConsts c{};
     c.d = d;
@@ -358,20 +376,21 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
         c.delta[k] = pl.pub.delta[k];
         c.top[k] = static_cast<double>(g->M[k] - 1);
     }
+    return c;
+}
+
+int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
+            char* ws, hipStream_t s, Tracer& tr) {
+    const kde::BinConsts c = bin_consts(pl, g);
+    int64_t cells = 1;
+    for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
     if (pl.tiled && n > 0) {
-        const BinLayout& b = pl.blay;
-        kde::BinWork w{};
-        w.hist = reinterpret_cast<uint32_t*>(ws + b.hist);
-        w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
-        w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
-        w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
-        w.records = reinterpret_cast<uint64_t*>(ws + b.records);
-        w.partial = reinterpret_cast<uint64_t*>(ws + b.partial);
-        KDE_LAUNCH(kde::launch_bin_hist(c, pl.tg, w, X, n, s), "bin_hist");
-        KDE_LAUNCH(kde::launch_bin_scan(pl.tg, w, n_dropped, s), "bin_scan");
-        KDE_LAUNCH(kde::launch_bin_scatter(c, pl.tg, w, X, n, s), "bin_scatter");
-        KDE_LAUNCH(kde::launch_bin_accum(c, pl.tg, w, counts, s), "bin_accum");
-        KDE_LAUNCH(kde::launch_bin_reduce(c, pl.tg, w, counts, s), "bin_reduce");
+        const kde::BinArgs a = bin_args(pl, c, X, n, counts, n_dropped, ws);
+        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinHist, a, s), "bin_hist");
+        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinScan, a, s), "bin_scan");
+        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinScatter, a, s), "bin_scatter");
+        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinAccum, a, s), "bin_accum");
+        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinReduce, a, s), "bin_reduce");
         return KDE_OK;
     }
     KDE_LAUNCH(kde::launch_zero_u64(counts, cells, s), "zero_counts");

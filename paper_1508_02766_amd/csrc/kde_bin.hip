@@ -154,15 +154,19 @@ __device__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* wave_sums
 // ---------------------------------------------------------------------------
 
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
-                                                               TileGeom g, uint32_t* __restrict__ hist,
-                                                               uint32_t* __restrict__ drops) {
+__device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
+    const double* __restrict__ X = a.X;
+    const int64_t n = a.n;
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    uint32_t* __restrict__ hist = a.w.hist;
+    uint32_t* __restrict__ drops = a.w.drops;
     extern __shared__ uint32_t h[];     // [ntiles]
     __shared__ uint32_t nd;
     const int tid = threadIdx.x;
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D>(X, n, blockIdx.x, x, valid);   // in flight while the histogram is cleared
+    load_chunk<D>(X, n, blk, x, valid);   // in flight while the histogram is cleared
     for (int t = tid; t < g.ntiles; t += kBinThreads) h[t] = 0;
     if (tid == 0) nd = 0;
     __syncthreads();
@@ -180,19 +184,21 @@ __global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const double* __r
     }
     if (dropped) atomicAdd(&nd, dropped);
     __syncthreads();
-    uint32_t* row = hist + static_cast<int64_t>(blockIdx.x) * g.ntiles;
+    uint32_t* row = hist + static_cast<int64_t>(blk) * g.ntiles;
     for (int t = tid; t < g.ntiles; t += kBinThreads) row[t] = h[t];
-    if (tid == 0) drops[blockIdx.x] = nd;
+    if (tid == 0) drops[blk] = nd;
 }
 
 // One wavefront per tile: exclusive scan of hist[., tile] over the chunks,
 // tot[tile] = the tile's record count. Block 0 also totals the dropped samples.
-__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(TileGeom g, uint32_t* __restrict__ hist,
-                                                               uint32_t* __restrict__ tot,
-                                                               const uint32_t* __restrict__ drops,
-                                                               unsigned long long* __restrict__ n_dropped) {
+__device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
+    const TileGeom& g = a.g;
+    uint32_t* __restrict__ hist = a.w.hist;
+    uint32_t* __restrict__ tot = a.w.tot;
+    const uint32_t* __restrict__ drops = a.w.drops;
+    unsigned long long* __restrict__ n_dropped = a.n_dropped;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = blockIdx.x * (kBinThreads / 64) + wave;
+    const int tile = static_cast<int>(blk) * (kBinThreads / 64) + wave;
     const int64_t nch = g.nchunk;
     if (tile < g.ntiles) {
         const int64_t per = (nch + 63) / 64;
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(TileGeom g, uint3
         }
         if (lane == 63) tot[tile] = x;
     }
-    if (blockIdx.x == 0 && n_dropped) {
+    if (blk == 0 && n_dropped) {
         __shared__ unsigned long long acc;
         if (tid == 0) acc = 0;
         __syncthreads();
@@ -227,20 +233,24 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(TileGeom g, uint3
 }
 
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(const double* __restrict__ X, int64_t n, BinConsts c,
-                                                                  TileGeom g, BinWork w) {
+__device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk) {
+    const double* __restrict__ X = a.X;
+    const int64_t n = a.n;
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    const BinWork& w = a.w;
     extern __shared__ uint32_t cur[];   // [ntiles]
     __shared__ uint32_t wave_sums[kBinThreads / 64];
     const int tid = threadIdx.x;
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D>(X, n, blockIdx.x, x, valid);   // in flight during the prologue
+    load_chunk<D>(X, n, blk, x, valid);   // in flight during the prologue
     for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] = w.tot[t];
     __syncthreads();
     block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
-    if (blockIdx.x == 0)
+    if (blk == 0)
         for (int t = tid; t < g.ntiles; t += kBinThreads) w.tile_start[t] = cur[t];
-    const uint32_t* off = w.hist + static_cast<int64_t>(blockIdx.x) * g.ntiles;
+    const uint32_t* off = w.hist + static_cast<int64_t>(blk) * g.ntiles;
     for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += off[t];
     __syncthreads();
 #pragma unroll
@@ -290,15 +300,18 @@ __device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const Til
 // One workgroup per segment (<= S records of one tile): sum the records'
 // corner weights in LDS, then store the tile (sole segment) or its partial.
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinConsts c, TileGeom g, BinWork w,
-                                                                uint64_t* __restrict__ counts) {
+__device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    const BinWork& w = a.w;
+    uint64_t* __restrict__ counts = a.counts;
     extern __shared__ unsigned long long accum_lds[];
     unsigned long long* grid = accum_lds;                                            // [tile_cells]
     uint32_t* seg_base = reinterpret_cast<uint32_t*>(accum_lds + g.tile_cells);      // [ntiles]
     __shared__ uint32_t wave_sums[kBinThreads / 64];
     __shared__ uint32_t found;
     const int tid = threadIdx.x;
-    const uint32_t s = blockIdx.x;
+    const uint32_t s = blk;
     // segment -> tile: prefix of the per-tile segment counts max(1, ceil(tot / S))
     for (int t = tid; t < g.ntiles; t += kBinThreads) {
         const uint32_t cnt = w.tot[t];
@@ -382,8 +395,11 @@ __global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinConsts c, Til
 // wavefronts sum interleaved segments of the same 64 cells and combine
 // through LDS.
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinConsts c, TileGeom g, BinWork w,
-                                                                 uint64_t* __restrict__ counts) {
+__device__ __forceinline__ void bin_reduce_body(const BinArgs& a, uint32_t blk, uint32_t nblk) {
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    const BinWork& w = a.w;
+    uint64_t* __restrict__ counts = a.counts;
     extern __shared__ uint32_t reduce_lds[];
     uint32_t* seg_base = reduce_lds;                     // [ntiles]
     uint32_t* rank = reduce_lds + g.ntiles;              // [ntiles]
@@ -404,7 +420,7 @@ __global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinConsts c, Ti
     __syncthreads();
     const int blocks_per_tile = (g.tile_cells + 63) / 64;
     const uint32_t items = nshared * static_cast<uint32_t>(blocks_per_tile);
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+    for (uint32_t it = blk; it < items; it += nblk) {
         const uint32_t tile = shared_list[it / blocks_per_tile];
         const int i = static_cast<int>(it % blocks_per_tile) * 64 + lane;
         const uint32_t cnt = w.tot[tile];
@@ -431,6 +447,51 @@ __global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinConsts c, Ti
         }
         __syncthreads();
     }
+}
+
+// Single-instance and batched entry points of the five stages. Batched
+// launches index the instance by blockIdx.z and return early from blocks past
+// the instance's own extent.
+constexpr uint32_t kReduceBlocks = 1024;        // persistent reduce grid (single instance)
+constexpr uint32_t kReduceBlocksBatch = 64;     // ... per instance of a batch
+
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(BinArgs a) { bin_hist_body<D>(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_hist_batch(const BinArgs* __restrict__ tab) {
+    const BinArgs& a = tab[blockIdx.z];
+    if (blockIdx.x >= a.g.nchunk) return;
+    bin_hist_body<D>(a, blockIdx.x);
+}
+__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(BinArgs a) { bin_scan_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kBinThreads) void bin_scan_batch(const BinArgs* __restrict__ tab) {
+    const BinArgs& a = tab[blockIdx.z];
+    if (blockIdx.x > 0 && blockIdx.x * (kBinThreads / 64) >= static_cast<uint32_t>(a.g.ntiles)) return;
+    bin_scan_body(a, blockIdx.x);
+}
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_batch(const BinArgs* __restrict__ tab) {
+    const BinArgs& a = tab[blockIdx.z];
+    if (blockIdx.x >= a.g.nchunk) return;
+    bin_scatter_body<D>(a, blockIdx.x);
+}
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_accum_batch(const BinArgs* __restrict__ tab) {
+    const BinArgs& a = tab[blockIdx.z];
+    if (blockIdx.x >= a.g.max_segments) return;
+    bin_accum_body<D>(a, blockIdx.x);
+}
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinArgs a) {
+    bin_reduce_body<D>(a, blockIdx.x, gridDim.x);
+}
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_reduce_batch(const BinArgs* __restrict__ tab) {
+    bin_reduce_body<D>(tab[blockIdx.z], blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -499,64 +560,78 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
-                           hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
-    const size_t lds = static_cast<size_t>(g.ntiles) * 4;
-    if (c.d == 1)
-        hipLaunchKernelGGL((bin_hist_kernel<1>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
-    else if (c.d == 2)
-        hipLaunchKernelGGL((bin_hist_kernel<2>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
-    else
-        hipLaunchKernelGGL((bin_hist_kernel<3>), grid, blk, lds, s, X, n, c, g, w.hist, w.drops);
+int64_t bin_stage_extent(int stage, const TileGeom& g) {
+    switch (stage) {
+        case kBinHist:
+        case kBinScatter: return g.nchunk;
+        case kBinScan: return (g.ntiles + kBinThreads / 64 - 1) / (kBinThreads / 64);
+        case kBinAccum: return g.max_segments;
+        default: return kReduceBlocks;
+    }
+}
+
+size_t bin_stage_lds(int stage, const TileGeom& g) {
+    switch (stage) {
+        case kBinHist:
+        case kBinScatter: return static_cast<size_t>(g.ntiles) * 4;
+        case kBinAccum: return static_cast<size_t>(g.tile_cells) * 8 + static_cast<size_t>(g.ntiles) * 4;
+        case kBinReduce: return static_cast<size_t>(g.ntiles) * 12;
+        default: return 0;
+    }
+}
+
+namespace {
+
+template <int D>
+hipError_t bin_stage_d(int stage, const BinArgs* one, const BinArgs* tab, int count, int64_t ext, size_t lds,
+                       hipStream_t s) {
+    const dim3 blk(kBinThreads);
+    const bool batch = tab != nullptr;
+    const dim3 grid(static_cast<unsigned>(stage == kBinReduce ? (batch ? kReduceBlocksBatch : kReduceBlocks) : ext), 1,
+                    static_cast<unsigned>(batch ? count : 1));
+    switch (stage) {
+        case kBinHist:
+            if (batch) hipLaunchKernelGGL((bin_hist_batch<D>), grid, blk, lds, s, tab);
+            else hipLaunchKernelGGL((bin_hist_kernel<D>), grid, blk, lds, s, *one);
+            break;
+        case kBinScan:
+            if (batch) hipLaunchKernelGGL(bin_scan_batch, grid, blk, 0, s, tab);
+            else hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, *one);
+            break;
+        case kBinScatter:
+            if (batch) hipLaunchKernelGGL((bin_scatter_batch<D>), grid, blk, lds, s, tab);
+            else hipLaunchKernelGGL((bin_scatter_kernel<D>), grid, blk, lds, s, *one);
+            break;
+        case kBinAccum:
+            if (batch) hipLaunchKernelGGL((bin_accum_batch<D>), grid, blk, lds, s, tab);
+            else hipLaunchKernelGGL((bin_accum_kernel<D>), grid, blk, lds, s, *one);
+            break;
+        case kBinReduce:
+            if (batch) hipLaunchKernelGGL((bin_reduce_batch<D>), grid, blk, lds, s, tab);
+            else hipLaunchKernelGGL((bin_reduce_kernel<D>), grid, blk, lds, s, *one);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_bin_scan(const TileGeom& g, const BinWork& w, uint64_t* n_dropped, hipStream_t s) {
-    const int per_block = kBinThreads / 64;
-    const dim3 grid(static_cast<unsigned>((g.ntiles + per_block - 1) / per_block)), blk(kBinThreads);
-    hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, g, w.hist, w.tot, w.drops,
-                       reinterpret_cast<unsigned long long*>(n_dropped));
-    return hipGetLastError();
+hipError_t bin_stage_any(int stage, int d, const BinArgs* one, const BinArgs* tab, int count, int64_t ext, size_t lds,
+                         hipStream_t s) {
+    if (d == 1) return bin_stage_d<1>(stage, one, tab, count, ext, lds, s);
+    if (d == 2) return bin_stage_d<2>(stage, one, tab, count, ext, lds, s);
+    return bin_stage_d<3>(stage, one, tab, count, ext, lds, s);
 }
 
-hipError_t launch_bin_scatter(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
-                              hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(g.nchunk)), blk(kBinThreads);
-    const size_t lds = static_cast<size_t>(g.ntiles) * 4;
-    if (c.d == 1)
-        hipLaunchKernelGGL((bin_scatter_kernel<1>), grid, blk, lds, s, X, n, c, g, w);
-    else if (c.d == 2)
-        hipLaunchKernelGGL((bin_scatter_kernel<2>), grid, blk, lds, s, X, n, c, g, w);
-    else
-        hipLaunchKernelGGL((bin_scatter_kernel<3>), grid, blk, lds, s, X, n, c, g, w);
-    return hipGetLastError();
+}  // namespace
+
+hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s) {
+    return bin_stage_any(stage, a.c.d, &a, nullptr, 1, bin_stage_extent(stage, a.g), bin_stage_lds(stage, a.g), s);
 }
 
-hipError_t launch_bin_accum(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
-                            hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(g.max_segments)), blk(kBinThreads);
-    const size_t lds = static_cast<size_t>(g.tile_cells) * 8 + static_cast<size_t>(g.ntiles) * 4;
-    if (c.d == 1)
-        hipLaunchKernelGGL((bin_accum_kernel<1>), grid, blk, lds, s, c, g, w, counts);
-    else if (c.d == 2)
-        hipLaunchKernelGGL((bin_accum_kernel<2>), grid, blk, lds, s, c, g, w, counts);
-    else
-        hipLaunchKernelGGL((bin_accum_kernel<3>), grid, blk, lds, s, c, g, w, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_bin_reduce(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
-                             hipStream_t s) {
-    const dim3 grid(1024), blk(kBinThreads);
-    const size_t lds = static_cast<size_t>(g.ntiles) * 12;
-    if (c.d == 1)
-        hipLaunchKernelGGL((bin_reduce_kernel<1>), grid, blk, lds, s, c, g, w, counts);
-    else if (c.d == 2)
-        hipLaunchKernelGGL((bin_reduce_kernel<2>), grid, blk, lds, s, c, g, w, counts);
-    else
-        hipLaunchKernelGGL((bin_reduce_kernel<3>), grid, blk, lds, s, c, g, w, counts);
-    return hipGetLastError();
+hipError_t launch_bin_stage_batch(int stage, int d, const BinArgs* tab, int count, int64_t ext, size_t lds,
+                                  hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    return bin_stage_any(stage, d, nullptr, tab, count, ext, lds, s);
 }
 
 }  // namespace kde

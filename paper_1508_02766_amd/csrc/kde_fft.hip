@@ -386,15 +386,8 @@ struct RowShape {
     static constexpr int THREADS = T * B;
 };
 
-// Lag-box weight coefficients in the working precision.
-template <typename R>
-struct GaussR {
-    R a00, a01, a02, a11, a12, a22, norm;
-    int L0, L1;
-};
-
 template <typename R, int D>
-__device__ __forceinline__ R gauss_weight(const GaussR<R>& g, R l0, R l1, R l2) {
+__device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2) {
     R q = g.a00 * l0 * l0;
     if constexpr (D >= 2) q += g.a11 * l1 * l1 + R(2) * g.a01 * l0 * l1;
     if constexpr (D == 3) q += g.a22 * l2 * l2 + R(2) * (g.a02 * l0 * l2 + g.a12 * l1 * l2);
@@ -403,7 +396,7 @@ __device__ __forceinline__ R gauss_weight(const GaussR<R>& g, R l0, R l1, R l2) 
 
 // Leading lags of lag-box row r: d = 2 -> (r - L0); d = 3 -> (r / n1 - L0, r % n1 - L1).
 template <typename R, int D>
-__device__ __forceinline__ void row_lags(const GaussR<R>& g, int64_t r, R& l0, R& l1) {
+__device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, R& l1) {
     if constexpr (D == 3) {
         const int64_t n1 = 2 * g.L1 + 1;
         l0 = static_cast<R>(r / n1 - g.L0);
@@ -414,15 +407,17 @@ __device__ __forceinline__ void row_lags(const GaussR<R>& g, int64_t r, R& l0, R
     }
 }
 
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D = 1>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(const void* __restrict__ in_, GaussR<R> gw, int64_t nrows,
-                                                       int64_t in_ld, int len, void* __restrict__ out_,
-                                                       int64_t out_ld) {
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
+__device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
     using C = cpx<R>;
     constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
     __shared__ C lds[B * LINE];
+    const void* __restrict__ in_ = gw.in;
+    void* __restrict__ out_ = gw.out;
+    const int64_t nrows = gw.nrows, in_ld = gw.in_ld, out_ld = gw.out_ld;
+    const int len = gw.len;
     const int b = threadIdx.x / T, t = threadIdx.x - b * T;
-    const int64_t r0 = 2 * (static_cast<int64_t>(blockIdx.x) * B + b), r1 = r0 + 1;
+    const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
     const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
     C v[16];
     if constexpr (IN_KIND == kRowCountsU64) {
@@ -488,20 +483,35 @@ __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(const 
     }
 }
 
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
+    rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(a, blockIdx.x);
+}
+
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_batch(const RowArgs<R>* __restrict__ tab) {
+    const RowArgs<R>& a = tab[blockIdx.z];
+    if (2 * static_cast<int64_t>(blockIdx.x) * RowShape<P>::B >= a.nrows) return;
+    rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // rows_c2r: half spectra -> real rows, scaled, window [0, mout)
 // ---------------------------------------------------------------------------
 
 template <typename R, int P, bool MULT>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(const cpx<R>* __restrict__ in, int64_t nrows,
-                                                       int64_t in_ld, const R* __restrict__ mult,
-                                                       R* __restrict__ out, int64_t out_ld, int mout,
-                                                       R scale) {
+__device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk) {
     using C = cpx<R>;
     constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
     __shared__ C lds[B * LINE];
+    const C* __restrict__ in = static_cast<const C*>(a.in);
+    const R* __restrict__ mult = static_cast<const R*>(a.mult);
+    R* __restrict__ out = static_cast<R*>(a.out);
+    const int64_t nrows = a.nrows, in_ld = a.in_ld, out_ld = a.out_ld;
+    const int mout = a.mout;
+    const R scale = a.scale;
     const int b = threadIdx.x / T, t = threadIdx.x - b * T;
-    const int64_t r0 = 2 * (static_cast<int64_t>(blockIdx.x) * B + b), r1 = r0 + 1;
+    const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
     const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
     C v[16];
 #pragma unroll
@@ -534,6 +544,18 @@ __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(const 
     }
 }
 
+template <typename R, int P, bool MULT>
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(C2RArgs<R> a) {
+    rows_c2r_body<R, P, MULT>(a, blockIdx.x);
+}
+
+template <typename R, int P, bool MULT>
+__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_batch(const C2RArgs<R>* __restrict__ tab) {
+    const C2RArgs<R>& a = tab[blockIdx.z];
+    if (2 * static_cast<int64_t>(blockIdx.x) * RowShape<P>::B >= a.nrows) return;
+    rows_c2r_body<R, P, MULT>(a, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // cols: transforms along a strided axis, B adjacent lines per workgroup
 // ---------------------------------------------------------------------------
@@ -553,13 +575,13 @@ struct ColShape {
 };
 
 template <typename R, int P, int MODE, bool NARROW>
-__global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
+__device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_t by) {
     using C = cpx<R>;
     constexpr int T = ColShape<R, P, NARROW>::T, B = ColShape<R, P, NARROW>::B;
     __shared__ C lds[B * LineShape<P>::LDS];
     const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
-    const int64_t w = static_cast<int64_t>(blockIdx.x) * B + b;
-    const int64_t o = blockIdx.y;
+    const int64_t w = static_cast<int64_t>(bx) * B + b;
+    const int64_t o = by;
     const bool act = w < a.W;
     const C* in = static_cast<const C*>(a.in) + o * a.in_os + w;
     C v[16];
@@ -613,6 +635,18 @@ __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel
     }
 }
 
+template <typename R, int P, int MODE, bool NARROW>
+__global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
+    cols_body<R, P, MODE, NARROW>(a, blockIdx.x, blockIdx.y);
+}
+
+template <typename R, int P, int MODE, bool NARROW>
+__global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_batch(const ColArgs* __restrict__ tab) {
+    const ColArgs& a = tab[blockIdx.z];
+    if (static_cast<int64_t>(blockIdx.x) * ColShape<R, P, NARROW>::B >= a.W || blockIdx.y >= a.outer) return;
+    cols_body<R, P, MODE, NARROW>(a, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
@@ -637,32 +671,49 @@ hipError_t rows_r2c_launch(int kind, const void* in, const GaussLag* gauss, int6
                            void* out, int64_t out_ld, bool out_real, hipStream_t s) {
     const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
     const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
-    GaussR<R> gw{};
+    RowArgs<R> a{};
+    a.in = in;
+    a.nrows = nrows;
+    a.in_ld = in_ld;
+    a.len = len;
+    a.out = out;
+    a.out_ld = out_ld;
     if (kind == kRowCountsU64) {
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false>), g, blk, 0, s, in, gw, nrows, in_ld, len,
-                           out, out_ld);
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, a);
         return hipGetLastError();
     }
-    gw.a00 = static_cast<R>(gauss->A[0]);
-    gw.a01 = static_cast<R>(gauss->A[1]);
-    gw.a02 = static_cast<R>(gauss->A[2]);
-    gw.a11 = static_cast<R>(gauss->A[4]);
-    gw.a12 = static_cast<R>(gauss->A[5]);
-    gw.a22 = static_cast<R>(gauss->A[8]);
-    gw.norm = static_cast<R>(gauss->norm);
-    gw.L0 = gauss->L[0];
-    gw.L1 = gauss->L[1];
-    if (gauss->d == 1) {
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, in, gw, nrows, in_ld, len,
-                           out, out_ld);
-    } else if (gauss->d == 2) {
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, in, gw, nrows, in_ld,
-                           len, out, out_ld);
-    } else {
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, in, gw, nrows, in_ld,
-                           len, out, out_ld);
-    }
+    a.a00 = static_cast<R>(gauss->A[0]);
+    a.a01 = static_cast<R>(gauss->A[1]);
+    a.a02 = static_cast<R>(gauss->A[2]);
+    a.a11 = static_cast<R>(gauss->A[4]);
+    a.a12 = static_cast<R>(gauss->A[5]);
+    a.a22 = static_cast<R>(gauss->A[8]);
+    a.norm = static_cast<R>(gauss->norm);
+    a.L0 = gauss->L[0];
+    a.L1 = gauss->L[1];
+    if (gauss->d == 1)
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, a);
+    else if (gauss->d == 2)
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, a);
     (void)out_real;
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t rows_r2c_batch_launch(int kind, int d, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
+    const int64_t blocks = ceil_div(ceil_div(max_nrows, 2), RowShape<P>::B);
+    const dim3 g(static_cast<unsigned>(blocks), 1, static_cast<unsigned>(count)), blk(RowShape<P>::THREADS);
+    const auto* t = static_cast<const RowArgs<R>*>(tab);
+    if (kind == kRowCountsU64)
+        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, t);
+    else if (d == 1)
+        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, t);
+    else if (d == 2)
+        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, t);
+    else
+        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, t);
     return hipGetLastError();
 }
 
@@ -671,14 +722,31 @@ hipError_t rows_c2r_launch(const void* in, int64_t nrows, int64_t in_ld, const v
                            int64_t out_ld, int mout, double scale, hipStream_t s) {
     const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
     const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
+    C2RArgs<R> a{};
+    a.in = in;
+    a.nrows = nrows;
+    a.in_ld = in_ld;
+    a.mult = mult;
+    a.out = out;
+    a.out_ld = out_ld;
+    a.mout = mout;
+    a.scale = static_cast<R>(scale);
     if (mult)
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, static_cast<const cpx<R>*>(in), nrows,
-                           in_ld, static_cast<const R*>(mult), static_cast<R*>(out), out_ld, mout,
-                           static_cast<R>(scale));
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false>), g, blk, 0, s, static_cast<const cpx<R>*>(in), nrows,
-                           in_ld, static_cast<const R*>(nullptr), static_cast<R*>(out), out_ld, mout,
-                           static_cast<R>(scale));
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false>), g, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t rows_c2r_batch_launch(bool mult, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
+    const int64_t blocks = ceil_div(ceil_div(max_nrows, 2), RowShape<P>::B);
+    const dim3 g(static_cast<unsigned>(blocks), 1, static_cast<unsigned>(count)), blk(RowShape<P>::THREADS);
+    const auto* t = static_cast<const C2RArgs<R>*>(tab);
+    if (mult)
+        hipLaunchKernelGGL((rows_c2r_batch<R, P, true>), g, blk, 0, s, t);
+    else
+        hipLaunchKernelGGL((rows_c2r_batch<R, P, false>), g, blk, 0, s, t);
     return hipGetLastError();
 }
 
@@ -692,6 +760,23 @@ hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
         case kColFwdCirc: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, a); break;
         case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, a); break;
         case kColConvLag: hipLaunchKernelGGL((cols_kernel<R, P, kColConvLag, NARROW>), g, blk, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t cols_batch_launch(int mode, const ColArgs* tab, int count, int64_t max_W, int64_t max_outer,
+                             hipStream_t s) {
+    constexpr int B = ColShape<R, P, false>::B;
+    const dim3 g(static_cast<unsigned>(ceil_div(max_W, B)), static_cast<unsigned>(max_outer),
+                 static_cast<unsigned>(count));
+    const dim3 blk(ColShape<R, P, false>::THREADS);
+    switch (mode) {
+        case kColFwdPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColFwdPrefix, false>), g, blk, 0, s, tab); break;
+        case kColFwdCirc: hipLaunchKernelGGL((cols_batch<R, P, kColFwdCirc, false>), g, blk, 0, s, tab); break;
+        case kColInvPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColInvPrefix, false>), g, blk, 0, s, tab); break;
+        case kColConvLag: hipLaunchKernelGGL((cols_batch<R, P, kColConvLag, false>), g, blk, 0, s, tab); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -724,6 +809,40 @@ hipError_t rows_c2r_any(int P, const void* in, int64_t nrows, int64_t in_ld, con
     switch (P) {
 #define KDE_CASE(PP) \
     case PP: return rows_c2r_launch<R, PP>(in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t rows_r2c_batch_any(int P, int kind, int d, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return rows_r2c_batch_launch<R, PP>(kind, d, tab, count, max_nrows, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t rows_c2r_batch_any(int P, bool mult, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return rows_c2r_batch_launch<R, PP>(mult, tab, count, max_nrows, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t cols_batch_any(int P, int mode, const ColArgs* tab, int count, int64_t max_W, int64_t max_outer,
+                          hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return cols_batch_launch<R, PP>(mode, tab, count, max_W, max_outer, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -771,6 +890,27 @@ hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64
 hipError_t launch_cols(int prec, int P, int mode, const ColArgs& a, hipStream_t s) {
     if (prec == 2) return cols_any<double>(P, mode, a, s);
     return cols_any<float>(P, mode, a, s);
+}
+
+hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const void* tab, int count,
+                                 int64_t max_nrows, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (prec == 2) return rows_r2c_batch_any<double>(P, input_kind, d, tab, count, max_nrows, s);
+    return rows_r2c_batch_any<float>(P, input_kind, d, tab, count, max_nrows, s);
+}
+
+hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const void* tab, int count, int64_t max_nrows,
+                                 hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (prec == 2) return rows_c2r_batch_any<double>(P, mult, tab, count, max_nrows, s);
+    return rows_c2r_batch_any<float>(P, mult, tab, count, max_nrows, s);
+}
+
+hipError_t launch_cols_batch(int prec, int P, int mode, const ColArgs* tab, int count, int64_t max_W,
+                             int64_t max_outer, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (prec == 2) return cols_batch_any<double>(P, mode, tab, count, max_W, max_outer, s);
+    return cols_batch_any<float>(P, mode, tab, count, max_W, max_outer, s);
 }
 
 }  // namespace kde

@@ -55,15 +55,28 @@ struct BinWork {
     uint64_t* partial;      // [max_segments][tile_cells] sums of segments of shared tiles
 };
 
-hipError_t launch_bin_hist(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
-                           hipStream_t s);
-hipError_t launch_bin_scan(const TileGeom& g, const BinWork& w, uint64_t* n_dropped, hipStream_t s);
-hipError_t launch_bin_scatter(const BinConsts& c, const TileGeom& g, const BinWork& w, const double* X, int64_t n,
-                              hipStream_t s);
-hipError_t launch_bin_accum(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
-                            hipStream_t s);
-hipError_t launch_bin_reduce(const BinConsts& c, const TileGeom& g, const BinWork& w, uint64_t* counts,
-                             hipStream_t s);
+// Everything one instance of the tiled binning reads and writes.
+struct BinArgs {
+    const double* X;
+    int64_t n;
+    BinConsts c;
+    TileGeom g;
+    BinWork w;
+    uint64_t* counts;
+    unsigned long long* n_dropped;   // may be null
+};
+
+enum BinStage : int { kBinHist = 0, kBinScan = 1, kBinScatter = 2, kBinAccum = 3, kBinReduce = 4 };
+
+// One stage of the tiled binning for one instance...
+hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s);
+// ...or for `count` instances of dimension d whose BinArgs are the device array
+// `tab`; `ext` is the largest per-instance grid size of the stage and `lds`
+// the largest per-instance LDS size (bin_stage_extent / bin_stage_lds).
+hipError_t launch_bin_stage_batch(int stage, int d, const BinArgs* tab, int count, int64_t ext, size_t lds,
+                                  hipStream_t s);
+int64_t bin_stage_extent(int stage, const TileGeom& g);
+size_t bin_stage_lds(int stage, const TileGeom& g);
 
 // Input kinds of the row (contiguous-axis) real-to-complex pass.
 enum RowInput : int {
@@ -79,6 +92,30 @@ struct GaussLag {
     double norm;
     int d;
     int L[3];
+};
+
+// Arguments of the row (contiguous-axis) r2c pass in the working precision R.
+template <typename R>
+struct RowArgs {
+    const void* in;         // uint64 counts rows (kRowCountsU64); unused for kRowGaussCirc
+    int64_t nrows, in_ld;
+    int len;                // nonzero prefix of a counts row, or L of the last axis (weights)
+    R a00, a01, a02, a11, a12, a22, norm;   // weights: norm exp(-0.5 l'Al)
+    int L0, L1;             // weights: half widths of the leading axes
+    void* out;
+    int64_t out_ld;
+};
+
+// Arguments of the row c2r pass (half spectra -> real rows).
+template <typename R>
+struct C2RArgs {
+    const void* in;
+    int64_t nrows, in_ld;
+    const void* mult;       // optional real spectrum indexed by the bin, or null
+    void* out;
+    int64_t out_ld;
+    int mout;
+    R scale;
 };
 
 // Modes of the strided-axis pass.
@@ -119,5 +156,16 @@ hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64
                            const void* mult, void* out, int64_t out_ld, int mout, double scale,
                            hipStream_t s);
 hipError_t launch_cols(int prec, int P, int mode, const ColArgs& a, hipStream_t s);
+
+// Batched forms: `tab` is a device array of `count` argument structs
+// (RowArgs<R> / C2RArgs<R> / ColArgs) of instances with the same P; blockIdx.z
+// selects the instance and blocks past an instance's own extent return early.
+// max_* are the largest per-instance extents.
+hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const void* tab, int count,
+                                 int64_t max_nrows, hipStream_t s);
+hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const void* tab, int count, int64_t max_nrows,
+                                 hipStream_t s);
+hipError_t launch_cols_batch(int prec, int P, int mode, const ColArgs* tab, int count, int64_t max_W,
+                             int64_t max_outer, hipStream_t s);
 
 }  // namespace kde
