@@ -5,8 +5,10 @@ samples, lag-box fill, kernel spectrum, forward FFTs of the counts, product,
 inverse FFTs, window) over inputs already resident in HBM. Default workload:
 d = 2, n = 1,000,000 samples of a 5-component normal mixture, 512 x 512 grid,
 full H with correlation 0.8, FP32 convolution. The JSON line also carries the
-3-D 128^3 and FP64 variants, the per-kernel roofline of the dominant kernel
-and the FP64 CPU oracle timed on the host.
+3-D 128^3 and FP64 variants, the batched form (256 independent 2-D problems
+of uneven size through kde_batch_*, autotuned, eager and graph-replayed), the
+per-kernel roofline of the dominant kernel and the FP64 CPU oracle timed on
+the host.
 
     python bench.py [--steps K] [--warmup W] [--workload mix2d_512|mix3d_128] [--prec f32|f64]
 """
@@ -64,7 +66,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="mix2d_512", choices=["mix2d_512", "mix3d_128"])
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / FP64 side measurements")
+    ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / FP64 / batched side measurements")
+    ap.add_argument("--batch", type=int, default=256, help="problems in the batched measurement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -210,6 +213,102 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     }
 
 
+def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
+    """The batched form: `count` independent 2-D problems (n log-uniform in
+    [1e3, 1e6], grid side in {64, 128, 256, 512}, random SPD H) per step."""
+    import torch
+    wl = W.batch2d(count)
+    dev = "cuda:0"
+    items = [(torch.as_tensor(w.X, device=dev), w.H, (w.lo, w.hi, w.M)) for w in wl]
+    B = K.KdeBatch(items, prec="f32")
+    t0 = time.perf_counter()
+    info = B.tune(reps=3)
+    tune_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        B.eval()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.eval()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / steps
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.eval()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        B.eval()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # the same problems as one kde_eval call each
+    plans = [K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M)) for w in wl]
+    wss = [torch.empty(p["eval_ws_bytes"], dtype=torch.uint8, device=dev) for p in plans]
+    outs = [torch.empty(w.M, dtype=torch.float32, device=dev) for w in wl]
+    calls = [K.prepare_eval(X, H, g, outs[i], wss[i]) for i, (X, H, g) in enumerate(items)]
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    loop_steps = max(3, steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(loop_steps):
+        for c in calls:
+            c()
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3 / loop_steps
+    same = all(torch.equal(outs[i], B.densities[i]) for i in range(len(wl)))
+    del wss, outs, calls
+    # per-kernel times of the batched launches (traced: one stream, an event after each launch)
+    evs = [hip.event() for _ in range(64)]
+    T = K.KdeBatch(items, prec="f32", trace_events=evs, trace={}, tile=info["tile"] if any(info["tile"]) else None)
+    T.eval()
+    torch.cuda.synchronize()
+    per = {}
+    reps = max(5, steps // 10)
+    for _ in range(reps):
+        T.eval()
+        torch.cuda.synchronize()
+        names = T.trace()["names"]
+        for i, nm in enumerate(names):
+            per.setdefault(nm, []).append(hip.elapsed_ms(evs[i], evs[i + 1]))
+    for e in evs:
+        hip.destroy(e)
+    T.close()
+    alg = {}
+    for w in wl:
+        plan = K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M))
+        for nm in set(per):
+            alg[nm] = alg.get(nm, 0) + kernel_bytes(nm, w, plan, "f32")
+    kern = {}
+    for nm, v in per.items():
+        us = float(np.sum(v)) / reps * 1e3        # a name can repeat (one launch per padded length)
+        kern[nm] = {"us": round(us, 3), "alg_bytes": int(alg[nm]), "alg_GBs": round(alg[nm] / (us * 1e-6) / 1e9, 1)}
+    n_tot = int(sum(w.n for w in wl))
+    cells = int(sum(np.prod(w.M) for w in wl))
+    alg_tot = sum(v["alg_bytes"] for v in kern.values())
+    best = min(eager_ms, graph_ms)
+    B.close()
+    return {
+        "problems": count, "n_total": n_tot, "grid_pts_total": cells, "launches": info["launches"],
+        "tuned_tile": list(info["tile"]), "tuned_narrow_mask": info["narrow_mask"], "tune_s": round(tune_s, 3),
+        "ms_per_batch": round(eager_ms, 4), "ms_per_batch_graph": round(graph_ms, 4),
+        "samples_per_s": round(n_tot / (best * 1e-3), 1), "grid_pts_per_s": round(cells / (best * 1e-3), 1),
+        "problems_per_s": round(count / (best * 1e-3), 1),
+        "ms_per_item_calls": round(loop_ms, 4), "speedup_vs_item_calls": round(loop_ms / best, 2),
+        "item_calls_bit_identical": bool(same),
+        "alg_bytes_per_batch": int(alg_tot), "alg_GBs": round(alg_tot / (best * 1e-3) / 1e9, 1),
+        "hbm_frac": round(alg_tot / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "kernels": kern,
+    }
+
+
 def cpu_baseline(W, name: str, reps: int):
     import oracle as O
     w = W.WORKLOADS[name]()
@@ -248,6 +347,8 @@ def main():
             variants[f"{name}_{prec}"] = {k: v[k] for k in ("ms_per_step", "ms_per_step_traced", "samples_per_s",
                                                             "grid_pts_per_s", "conv_us", "conv_grid_pts_per_s",
                                                             "bin_us", "bin_samples_per_s", "kernels")}
+        if a.batch > 0:
+            variants[f"batch2d_{a.batch}_f32"] = measure_batch(K, W, hip, a.batch, max(20, a.steps // 4), 5)
     # roofline of the dominant kernel of the main workload
     kern = main_run["kernels"]
     dom = max(kern, key=lambda k: kern[k]["us"])

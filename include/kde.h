@@ -76,6 +76,10 @@ typedef struct kde_params {
     int32_t Q;                /* fixed-point bits of the binning weights; 0: floor(32 / d);
                                  else 1 <= Q and d Q <= 62 */
     int32_t prec;             /* KDE_F32 (also when 0) or KDE_F64 */
+    int32_t tile[3];          /* > 0: binning tile extent (cells, a power of two <= 4096) on
+                                 axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 16;
+                                 the product must stay <= 4096. Changes speed and workspace
+                                 size, never the counts */
     int32_t trace_capacity;   /* optional per-kernel timing, see below */
     hipEvent_t* trace_events; /* if non-NULL: events[0] is recorded before the first kernel
                                  and events[i] after the i-th kernel, on `stream`, up to
@@ -157,6 +161,67 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
 int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid,
              const kde_params* params, void* density, void* ws, size_t ws_bytes,
              uint64_t* n_dropped, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched evaluation: many independent estimates (each its own X, n, H and
+ * grid; d may differ between items) computed together. Every pass of the
+ * pipeline runs as one launch for all items that share its kernel template
+ * (precision and padded length P), with each item owning exactly the
+ * workgroups its own size needs, so a batch of B items takes a few dozen
+ * launches instead of about 10 B. Results are bit-identical to kde_eval of
+ * each item with the same params.
+ * ------------------------------------------------------------------------- */
+
+typedef struct kde_batch_item {
+    const double* X;          /* device, n x d FP64 samples */
+    int64_t n;                /* >= 1 */
+    double H[9];              /* bandwidth matrix, d x d row-major in the first d*d entries */
+    kde_grid grid;
+    void* density;            /* device, prod M_k reals of the batch precision (output) */
+    uint64_t* n_dropped;      /* device, may be NULL: samples outside the grid (as kde_bin) */
+} kde_batch_item;
+
+typedef struct kde_batch kde_batch;   /* opaque; host memory only */
+
+typedef struct kde_batch_info {
+    int32_t count;            /* items */
+    int32_t launches;         /* kernel launches per kde_batch_eval */
+    size_t ws_bytes;          /* device workspace kde_batch_bind needs */
+    int32_t tile[3];          /* binning tile in use (the autotuner may change it) */
+    int32_t narrow_mask;      /* bit log2(P): strided-axis passes of length P use 4 lines
+                                 per workgroup (else the widest shape) */
+} kde_batch_info;
+
+/* Plan `count` items with shared params (precision, tau, Q, overrides; the
+ * trace fields apply to kde_batch_eval). Validates every item as kde_eval
+ * would and returns the first failing status. The items' pointers are kept:
+ * X, density and n_dropped must stay valid while the batch is used.
+ * *out receives a host object to release with kde_batch_destroy. */
+int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_params* params, kde_batch** out);
+
+int kde_batch_query(const kde_batch* b, kde_batch_info* info);
+
+/* Attach the device workspace (256-byte aligned, info.ws_bytes long, owned by
+ * the caller) and copy the launch tables into its head on `stream`. The copy
+ * reads host memory owned by the batch object: keep the object alive until
+ * the stream has passed this point. Must precede kde_batch_eval; binding
+ * again (e.g. another workspace) is allowed. */
+int kde_batch_bind(kde_batch* b, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Enqueue the whole batch (binning, kernel spectra, convolutions) on `stream`.
+ * Only kernel launches and event records: capturable in a HIP graph, which
+ * then replays the batch on whatever the items' X buffers hold. Calls on one
+ * bound workspace must not overlap. */
+int kde_batch_eval(const kde_batch* b, hipStream_t stream);
+
+/* Autotuner: times kde_batch_eval (reps runs per candidate, HIP events) over
+ * the binning tile shapes that fit the workspace and, for each padded length
+ * on a strided axis, the wide and narrow workgroup shapes; keeps the fastest
+ * and rebinds. Synchronises `stream`; overwrites the densities. None of the
+ * choices changes any result bit. */
+int kde_batch_tune(kde_batch* b, int32_t reps, hipStream_t stream);
+
+void kde_batch_destroy(kde_batch* b);
 
 /* Static description of a status code. */
 const char* kde_strerror(int status);

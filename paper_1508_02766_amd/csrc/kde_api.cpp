@@ -14,10 +14,14 @@
 // origin; P_k >= M_k + L_k makes the circular convolution equal to Eq. (7) on
 // the window [0, M_k), which replaces the extraction of Eq. (14).
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <new>
+#include <vector>
 
 #include "../../include/kde.h"
 #include "kde_internal.h"
@@ -56,15 +60,16 @@ struct Plan {
     BinLayout blay;
 };
 
-// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 8 x 8 in 3-D,
-// 1024 in 1-D (clamped to the grid), widened until the tile count fits the
-// per-workgroup histogram. Returns false when the tiled path cannot be used:
-// too many cells per tile, records wider than 64 bits, or n 2^d >= 2^32.
-bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, kde::TileGeom* tg, BinLayout* bl) {
+// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 16 x 16 in
+// 3-D, 1024 in 1-D, or the caller's tile (clamped to the grid), widened until
+// the tile count fits the per-workgroup histogram. Returns false when the
+// tiled path cannot be used: too many cells per tile, records wider than 64
+// bits, or n 2^d >= 2^32.
+bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde::TileGeom* tg, BinLayout* bl) {
     kde::TileGeom g{};
     static const int base[3][3] = {{1024, 0, 0}, {32, 32, 0}, {8, 16, 16}};
     for (int k = 0; k < d; ++k) {
-        int T = base[d - 1][k];
+        int T = tile[k] > 0 ? tile[k] : base[d - 1][k];
         while (T > 1 && T / 2 >= M[k]) T /= 2;
         g.T[k] = T;
     }
@@ -137,7 +142,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     // options
     double tau = kTauDefault;
     int prec = KDE_F32, Q = 32 / d;
-    int Lovr[3] = {0, 0, 0};
+    int Lovr[3] = {0, 0, 0}, tile[3] = {0, 0, 0};
     if (prm) {
         if (std::isnan(prm->tau) || std::isinf(prm->tau)) return KDE_ERR_ARG;
         if (prm->tau > 0.0) tau = prm->tau;
@@ -153,6 +158,14 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
             if (prm->L[k] < 0 || prm->L[k] > g->M[k] - 1) return KDE_ERR_ARG;
             Lovr[k] = prm->L[k];
         }
+        int64_t tcells = 1;
+        for (int k = 0; k < d; ++k) {
+            const int T = prm->tile[k];
+            if (T < 0 || T > kde::kMaxTileCells || (T & (T - 1)) != 0) return KDE_ERR_ARG;
+            tile[k] = T;
+            tcells *= T > 0 ? T : 1;
+        }
+        if (tcells > kde::kMaxTileCells) return KDE_ERR_ARG;
         if (prm->trace_events && prm->trace_capacity < 0) return KDE_ERR_ARG;
     }
     p.prec = prec;
@@ -164,7 +177,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     int64_t cells = 1;
     for (int k = 0; k < d; ++k) cells *= g->M[k];
     out->counts_bytes = static_cast<size_t>(cells) * sizeof(uint64_t);
-    out->tiled = plan_tiles(d, g->M, Q, n, &out->tg, &out->blay);
+    out->tiled = plan_tiles(d, g->M, Q, n, tile, &out->tg, &out->blay);
     p.bin_ws_bytes = out->tiled ? out->blay.total : 0;
     if (!need_H) return KDE_OK;
 
@@ -335,11 +348,90 @@ struct Tracer {
         if ((expr) != hipSuccess) return KDE_ERR_HIP; \
     } while (0)
 
-#define KDE_LAUNCH(expr, name)              \
-    do {                                    \
-        KDE_TRY(expr);                      \
-        KDE_TRY(tr.mark(name));             \
+#define KDE_CHECK(expr)              \
+    do {                             \
+        const int rc_ = (expr);      \
+        if (rc_ != KDE_OK) return rc_; \
     } while (0)
+
+// One kernel launch of the pipeline for one problem: which kernel (kind and
+// template parameters), its argument struct, and the workgroups it takes in a
+// batched launch. The single-instance path launches passes as they are
+// produced; the batched path collects them and launches all passes with the
+// same kernel together.
+enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols };
+
+struct Pass {
+    PassKind kind;
+    int prec = 0, P = 0, sub = 0, d = 0;   // sub: bin stage / row input kind / c2r multiplier / column mode
+    int narrow = -1;                       // column passes: -1 by launch size, 0 wide, 1 four lines
+    int order = 0;                         // position in the pipeline (increasing along an instance)
+    const char* name = "";
+    int64_t blocks = 0;                    // workgroups in a batched launch
+    size_t lds = 0;                        // dynamic LDS (binning stages)
+    size_t size = 0;                       // bytes of args
+    alignas(16) unsigned char args[384];
+    // kPassZero / kPassBinAtomic
+    uint64_t* zptr = nullptr;
+    int64_t zcount = 0;
+    kde::BinConsts bc{};
+    const double* X = nullptr;
+    int64_t n = 0;
+    uint64_t* counts = nullptr;
+    uint64_t* n_dropped = nullptr;
+
+    template <typename T>
+    void set_args(const T& a) {
+        static_assert(sizeof(T) <= sizeof(args), "argument struct too large");
+        std::memcpy(args, &a, sizeof(T));
+        size = sizeof(T);
+    }
+};
+
+int exec_pass(const Pass& p, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    switch (p.kind) {
+        case kPassZero: e = kde::launch_zero_u64(p.zptr, p.zcount, s); break;
+        case kPassBinAtomic: e = kde::launch_bin(p.bc, p.X, p.n, p.counts, p.n_dropped, s); break;
+        case kPassBin:
+            e = kde::launch_bin_stage(p.sub, *reinterpret_cast<const kde::BinArgs*>(p.args), s);
+            break;
+        case kPassRowR2C: e = kde::launch_rows_r2c(p.prec, p.P, p.sub, p.d, p.args, s); break;
+        case kPassRowC2R: e = kde::launch_rows_c2r(p.prec, p.P, p.args, s); break;
+        case kPassCols:
+            e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
+            break;
+    }
+    return e == hipSuccess ? KDE_OK : KDE_ERR_HIP;
+}
+
+// Consumer of the passes of one stream of work.
+struct Emit {
+    virtual int operator()(const Pass& p) = 0;
+    virtual ~Emit() = default;
+};
+
+// Launch at once (and mark the trace).
+struct Direct : Emit {
+    hipStream_t s;
+    Tracer& tr;
+    Direct(hipStream_t st, Tracer& t) : s(st), tr(t) {}
+    int operator()(const Pass& p) override {
+        KDE_CHECK(exec_pass(p, s));
+        KDE_TRY(tr.mark(p.name));
+        return KDE_OK;
+    }
+};
+
+// Collect for a batched launch.
+struct Collect : Emit {
+    std::vector<Pass>& out;
+    explicit Collect(std::vector<Pass>& o) : out(o) {}
+    int operator()(const Pass& p) override {
+        out.push_back(p);
+        return KDE_OK;
+    }
+};
 
 kde::BinArgs bin_args(const Plan& pl, const kde::BinConsts& c, const double* X, int64_t n, uint64_t* counts,
                       uint64_t* n_dropped, char* ws) {
@@ -379,23 +471,55 @@ kde::BinConsts bin_consts(const Plan& pl, const kde_grid* g) {
     return c;
 }
 
+// Binning (Section 2, first step): the five tiled stages, or zero fill and
+// global atomics where the tiled path does not apply.
 int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
-            char* ws, hipStream_t s, Tracer& tr) {
+            char* ws, Emit& emit) {
     const kde::BinConsts c = bin_consts(pl, g);
     int64_t cells = 1;
     for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
     if (pl.tiled && n > 0) {
+        static const char* names[5] = {"bin_hist", "bin_scan", "bin_scatter", "bin_accum", "bin_reduce"};
         const kde::BinArgs a = bin_args(pl, c, X, n, counts, n_dropped, ws);
-        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinHist, a, s), "bin_hist");
-        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinScan, a, s), "bin_scan");
-        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinScatter, a, s), "bin_scatter");
-        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinAccum, a, s), "bin_accum");
-        KDE_LAUNCH(kde::launch_bin_stage(kde::kBinReduce, a, s), "bin_reduce");
+        for (int st = kde::kBinHist; st <= kde::kBinReduce; ++st) {
+            Pass p;
+            p.kind = kPassBin;
+            p.sub = st;
+            p.d = pl.pub.d;
+            p.order = st;
+            p.name = names[st];
+            p.blocks = kde::bin_stage_batch_blocks(st, pl.tg);
+            p.lds = kde::bin_stage_lds(st, pl.tg);
+            p.set_args(a);
+            KDE_CHECK(emit(p));
+        }
         return KDE_OK;
     }
-    KDE_LAUNCH(kde::launch_zero_u64(counts, cells, s), "zero_counts");
-    if (n_dropped) KDE_LAUNCH(kde::launch_zero_u64(n_dropped, 1, s), "zero_dropped");
-    if (n > 0) KDE_LAUNCH(kde::launch_bin(c, X, n, counts, n_dropped, s), "bin");
+    Pass z;
+    z.kind = kPassZero;
+    z.name = "zero_counts";
+    z.zptr = counts;
+    z.zcount = cells;
+    KDE_CHECK(emit(z));
+    if (n_dropped) {
+        z.name = "zero_dropped";
+        z.order = 1;
+        z.zptr = n_dropped;
+        z.zcount = 1;
+        KDE_CHECK(emit(z));
+    }
+    if (n > 0) {
+        Pass b;
+        b.kind = kPassBinAtomic;
+        b.order = 2;
+        b.name = "bin";
+        b.bc = c;
+        b.X = X;
+        b.n = n;
+        b.counts = counts;
+        b.n_dropped = n_dropped;
+        KDE_CHECK(emit(b));
+    }
     return KDE_OK;
 }
 
@@ -409,36 +533,88 @@ ConvBufs conv_bufs(const Plan& pl, char* ws) {
     return {ws + L.khat, ws + L.kt1, ws + L.kt2, ws + L.z1, ws + L.z2};
 }
 
+Pass row_r2c_pass(const Plan& pl, int P, int kind, const void* in, const kde::GaussLag* gl, int64_t nrows,
+                  int64_t in_ld, int len, void* out, int64_t out_ld, int order, const char* name) {
+    Pass p;
+    p.kind = kPassRowR2C;
+    p.prec = pl.pub.prec;
+    p.P = P;
+    p.sub = kind;
+    p.d = kind == kde::kRowGaussCirc ? pl.pub.d : 1;
+    p.order = order;
+    p.name = name;
+    p.blocks = kde::rows_pass_blocks(P, nrows);
+    if (p.prec == KDE_F64)
+        p.set_args(kde::make_row_args<double>(in, gl, nrows, in_ld, len, out, out_ld));
+    else
+        p.set_args(kde::make_row_args<float>(in, gl, nrows, in_ld, len, out, out_ld));
+    return p;
+}
+
+Pass row_c2r_pass(const Plan& pl, int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
+                  int64_t out_ld, int mout, double scale, int order, const char* name) {
+    Pass p;
+    p.kind = kPassRowC2R;
+    p.prec = pl.pub.prec;
+    p.P = P;
+    p.sub = mult ? 1 : 0;
+    p.order = order;
+    p.name = name;
+    p.blocks = kde::rows_pass_blocks(P, nrows);
+    if (p.prec == KDE_F64)
+        p.set_args(kde::make_c2r_args<double>(in, nrows, in_ld, mult, out, out_ld, mout, scale));
+    else
+        p.set_args(kde::make_c2r_args<float>(in, nrows, in_ld, mult, out, out_ld, mout, scale));
+    return p;
+}
+
+// nmask < 0: workgroup shape chosen at launch from its size; else bit
+// log2(P) of nmask selects the narrow shape for length P.
+Pass cols_pass(const Plan& pl, int P, int mode, const kde::ColArgs& a, int nmask, int order, const char* name) {
+    int lg = 0;
+    while ((1 << lg) < P) ++lg;
+    const int narrow = nmask < 0 ? -1 : (nmask >> lg) & 1;
+    Pass p;
+    p.kind = kPassCols;
+    p.prec = pl.pub.prec;
+    p.P = P;
+    p.sub = mode;
+    p.narrow = narrow;
+    p.order = order;
+    p.name = name;
+    p.blocks = kde::cols_pass_blocks(p.prec, P, narrow == 1, a.W, a.outer);
+    p.set_args(a);
+    return p;
+}
+
 // Kernel spectrum: lag-box weights computed in place (Eq. 6 over the signed
-// box of Eq. 12), transformed along every axis; real because the box is
+// box of Eq. 12), transformed along every axis but the slowest (whose
+// transform the product pass computes per line); real because the box is
 // centrally symmetric and placed circularly.
-int run_kspec(const Plan& pl, const kde_grid* g, char* ws, hipStream_t s, Tracer& tr) {
+int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
     const kde_plan& p = pl.pub;
-    const int d = p.d, prec = p.prec;
+    const int d = p.d;
     const ConvBufs b = conv_bufs(pl, ws);
     kde::GaussLag gl{};
     for (int i = 0; i < 9; ++i) gl.A[i] = pl.A[i];
     gl.norm = p.norm;
     gl.d = d;
     for (int k = 0; k < 3; ++k) gl.L[k] = k < d ? p.L[k] : 0;
-    (void)g;
     if (d == 1) {
         const int P0 = p.P[0];
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P0, kde::kRowGaussCirc, nullptr, &gl, 1, 0, p.L[0], b.khat, P0 / 2 + 1,
-                                        true, s), "kspec_r2c");
-        return KDE_OK;
+        return emit(row_r2c_pass(pl, P0, kde::kRowGaussCirc, nullptr, &gl, 1, 0, p.L[0], b.khat, P0 / 2 + 1, 0,
+                                 "kspec_r2c"));
     }
     if (d == 2) {
         const int P1 = p.P[1];
         const int64_t n0 = 2 * p.L[0] + 1;
-        KDE_LAUNCH(kde::launch_rows_r2c(prec, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, half_pitch(P1), false,
-                                        s), "kspec_r2c");
-        return KDE_OK;
+        return emit(row_r2c_pass(pl, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, half_pitch(P1), 0,
+                                 "kspec_r2c"));
     }
     const int P1 = p.P[1], P2 = p.P[2];
     const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
-    KDE_LAUNCH(kde::launch_rows_r2c(prec, P2, kde::kRowGaussCirc, nullptr, &gl, n0 * n1, 0, p.L[2], b.kt1, Hp, false,
-                                    s), "kspec_r2c");
+    KDE_CHECK(emit(row_r2c_pass(pl, P2, kde::kRowGaussCirc, nullptr, &gl, n0 * n1, 0, p.L[2], b.kt1, Hp, 0,
+                                "kspec_r2c")));
     kde::ColArgs k1{};
     k1.in = b.kt1;
     k1.out = b.kt2;
@@ -449,22 +625,21 @@ int run_kspec(const Plan& pl, const kde_grid* g, char* ws, hipStream_t s, Tracer
     k1.out_os = static_cast<int64_t>(P1) * Hp;
     k1.out_ps = Hp;
     k1.len = p.L[1];
-    KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdCirc, k1, s), "kspec_col2");
-    return KDE_OK;
+    return emit(cols_pass(pl, P1, kde::kColFwdCirc, k1, nmask, 1, "kspec_col2"));
 }
 
 // Forward transforms of the zero-padded counts that do not need the spectrum.
-int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, char* ws, hipStream_t s, Tracer& tr) {
+int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, char* ws, int nmask, Emit& emit) {
     const kde_plan& p = pl.pub;
-    const int d = p.d, prec = p.prec;
+    const int d = p.d;
     const ConvBufs b = conv_bufs(pl, ws);
     const int Pl = p.P[d - 1];
     const int64_t Hl = Pl / 2 + 1, Hp = d == 1 ? Hl : half_pitch(Pl);
     const int64_t Ml = g->M[d - 1];
     int64_t rows = 1;
     for (int k = 0; k < d - 1; ++k) rows *= g->M[k];
-    KDE_LAUNCH(kde::launch_rows_r2c(prec, Pl, kde::kRowCountsU64, counts, nullptr, rows, Ml, static_cast<int>(Ml), b.z1,
-                                    Hp, false, s), "counts_r2c");
+    KDE_CHECK(emit(row_r2c_pass(pl, Pl, kde::kRowCountsU64, counts, nullptr, rows, Ml, static_cast<int>(Ml), b.z1, Hp,
+                                10, "counts_r2c")));
     if (d == 3) {
         const int P1 = p.P[1];
         const int64_t M0 = g->M[0], M1 = g->M[1];
@@ -478,25 +653,24 @@ int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, ch
         f1.out_os = static_cast<int64_t>(P1) * Hp;
         f1.out_ps = Hp;
         f1.len = static_cast<int>(M1);
-        KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColFwdPrefix, f1, s), "counts_col2");
+        KDE_CHECK(emit(cols_pass(pl, P1, kde::kColFwdPrefix, f1, nmask, 11, "counts_col2")));
     }
     return KDE_OK;
 }
 
 // Product with the spectrum, inverse transforms, window [0, M_k) and the
 // 2^-(dQ) / prod P_k scale.
-int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, hipStream_t s, Tracer& tr) {
+int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, int nmask, Emit& emit) {
     const kde_plan& p = pl.pub;
-    const int d = p.d, prec = p.prec;
+    const int d = p.d;
     const ConvBufs b = conv_bufs(pl, ws);
     double scale = std::ldexp(1.0, -d * p.Q);
     for (int k = 0; k < d; ++k) scale /= static_cast<double>(p.P[k]);
     if (d == 1) {
         const int P0 = p.P[0];
         const int64_t H0 = P0 / 2 + 1, M0 = g->M[0];
-        KDE_LAUNCH(kde::launch_rows_c2r(prec, P0, b.z1, 1, H0, b.khat, density, M0, static_cast<int>(M0), scale, s),
-                   "product_c2r");
-        return KDE_OK;
+        return emit(row_c2r_pass(pl, P0, b.z1, 1, H0, b.khat, density, M0, static_cast<int>(M0), scale, 20,
+                                 "product_c2r"));
     }
     if (d == 2) {
         const int P0 = p.P[0], P1 = p.P[1];
@@ -513,10 +687,8 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         ca.out_ps = Hp;
         ca.len = static_cast<int>(M0);
         ca.mout = static_cast<int>(M0);
-        KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, ca, s), "conv_col");
-        KDE_LAUNCH(kde::launch_rows_c2r(prec, P1, b.z1, M0, Hp, nullptr, density, M1, static_cast<int>(M1), scale, s),
-                   "c2r");
-        return KDE_OK;
+        KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, ca, nmask, 20, "conv_col")));
+        return emit(row_c2r_pass(pl, P1, b.z1, M0, Hp, nullptr, density, M1, static_cast<int>(M1), scale, 21, "c2r"));
     }
     const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2];
     const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
@@ -535,7 +707,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     cv.kt_len = p.L[0];
     cv.len = static_cast<int>(M0);
     cv.mout = static_cast<int>(M0);
-    KDE_LAUNCH(kde::launch_cols(prec, P0, kde::kColConvLag, cv, s), "conv_col1");
+    KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, cv, nmask, 20, "conv_col1")));
     kde::ColArgs i1{};
     i1.in = b.z2;
     i1.out = b.z1;
@@ -546,10 +718,8 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     i1.out_os = M1 * Hp;
     i1.out_ps = Hp;
     i1.mout = static_cast<int>(M1);
-    KDE_LAUNCH(kde::launch_cols(prec, P1, kde::kColInvPrefix, i1, s), "inv_col2");
-    KDE_LAUNCH(kde::launch_rows_c2r(prec, P2, b.z1, M0 * M1, Hp, nullptr, density, M2, static_cast<int>(M2), scale, s),
-               "c2r");
-    return KDE_OK;
+    KDE_CHECK(emit(cols_pass(pl, P1, kde::kColInvPrefix, i1, nmask, 21, "inv_col2")));
+    return emit(row_c2r_pass(pl, P2, b.z1, M0 * M1, Hp, nullptr, density, M2, static_cast<int>(M2), scale, 22, "c2r"));
 }
 
 // A second stream per device on which the kernel spectrum is computed while
@@ -583,34 +753,246 @@ Aux* aux_for(hipStream_t s) {
     return &a;
 }
 
-// The convolution of counts (already on / being computed on stream s), with
-// the spectrum on the auxiliary stream unless per-kernel tracing asks for one
-// serial stream. `pre` enqueues the work that produces the counts (binning)
-// or nothing.
-template <typename Pre>
-int run_pipeline(const Plan& pl, const kde_grid* g, const uint64_t* counts, void* density, char* conv_ws, hipStream_t s,
-                 Tracer& tr, Pre&& pre) {
+// Runs the three phases of the pipeline: `spec` (the kernel spectrum) on the
+// auxiliary stream, `fwd` (binning and forward transforms of the counts) on
+// the caller's stream, then `inv` (product and inverse transforms) on the
+// caller's stream after both. With tracing on, everything runs in order on
+// the caller's stream so that each kernel sits between two events.
+template <typename Spec, typename Fwd, typename Inv>
+int run_phases(hipStream_t s, Tracer& tr, Spec&& spec, Fwd&& fwd, Inv&& inv) {
     if (!tr.on) {
         std::lock_guard<std::mutex> lock(g_aux_mu);
         Aux* a = aux_for(s);
         if (a) {
             KDE_TRY(hipEventRecord(a->fork, s));
             KDE_TRY(hipStreamWaitEvent(a->stream, a->fork, 0));
-            int r = run_kspec(pl, g, conv_ws, a->stream, tr);
-            if (r != KDE_OK) return r;
+            KDE_CHECK(spec(a->stream));
             KDE_TRY(hipEventRecord(a->join, a->stream));
-            r = pre();
-            if (r == KDE_OK) r = run_counts_fwd(pl, counts, g, conv_ws, s, tr);
-            if (r != KDE_OK) return r;
+            KDE_CHECK(fwd(s));
             KDE_TRY(hipStreamWaitEvent(s, a->join, 0));
-            return run_product_inv(pl, g, density, conv_ws, s, tr);
+            return inv(s);
         }
     }
-    int r = pre();
-    if (r == KDE_OK) r = run_kspec(pl, g, conv_ws, s, tr);
-    if (r == KDE_OK) r = run_counts_fwd(pl, counts, g, conv_ws, s, tr);
-    if (r == KDE_OK) r = run_product_inv(pl, g, density, conv_ws, s, tr);
-    return r;
+    KDE_CHECK(fwd(s));
+    KDE_CHECK(spec(s));
+    return inv(s);
+}
+
+// ---------------------------------------------------------------------------
+// batched evaluation
+// ---------------------------------------------------------------------------
+
+// Passes of one kernel template, launched together.
+struct Group {
+    int phase = 0;                 // 0 spectrum (auxiliary stream), 1 forward, 2 inverse
+    Pass key;                      // kernel and template parameters (first member)
+    std::vector<int> members;      // indices into Batch::passes, in instance order
+    bool batched = false;          // false: zero / atomic binning, launched one by one
+    size_t tab_off = 0, start_off = 0, owner_off = 0;
+    uint32_t blocks = 0;
+    size_t lds = 0;
+};
+
+bool same_kernel(const Pass& a, const Pass& b) {
+    return a.kind == b.kind && a.prec == b.prec && a.P == b.P && a.sub == b.sub && a.d == b.d &&
+           a.narrow == b.narrow && a.order == b.order;
+}
+
+}  // namespace
+
+struct kde_batch {
+    std::vector<kde_batch_item> items;
+    kde_params prm{};
+    bool has_prm = false;
+    int tile[3] = {0, 0, 0};       // binning tile of the current configuration (0: default)
+    int narrow_mask = 0;           // bit log2(P): narrow strided passes of length P
+    std::vector<Plan> plans;
+    std::vector<size_t> inst_off;  // per item: offset of its eval workspace in ws
+    size_t table_cap = 0, ws_bytes = 0;
+    // the current configuration, laid out for ws
+    std::vector<Pass> passes;
+    std::vector<Group> groups;
+    std::vector<unsigned char> table;
+    char* ws = nullptr;
+    bool bound = false;
+};
+
+namespace {
+
+constexpr int kTuneTiles2[][3] = {{0, 0, 0}, {16, 64, 0}, {64, 16, 0}, {64, 64, 0}, {16, 16, 0}};
+constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 8, 8}, {4, 16, 16}, {16, 16, 16}, {8, 8, 32}};
+constexpr int kTuneTiles1[][3] = {{0, 0, 0}, {512, 0, 0}, {2048, 0, 0}, {4096, 0, 0}};
+
+kde_params batch_params(const kde_batch& b, const int tile[3]) {
+    kde_params q = b.prm;
+    for (int k = 0; k < 3; ++k) q.tile[k] = tile[k];
+    return q;
+}
+
+int plan_item(const kde_batch& b, const kde_batch_item& it, const int tile[3], Plan* pl) {
+    const kde_params q = batch_params(b, tile);
+    return make_plan(it.H, it.n, 1, true, &it.grid, &q, pl);
+}
+
+// Binning tile shapes the autotuner tries, the first being the one in use at
+// creation: the caller's shape alone if params set one or the items differ in
+// d; otherwise the default and the alternatives for that d.
+std::vector<std::array<int, 3>> tile_candidates(const kde_batch& b) {
+    std::vector<std::array<int, 3>> c;
+    const bool fixed = b.has_prm && (b.prm.tile[0] || b.prm.tile[1] || b.prm.tile[2]);
+    int d = b.items[0].grid.d;
+    for (const auto& it : b.items)
+        if (it.grid.d != d) d = 0;
+    if (fixed || d == 0) {
+        c.push_back({b.has_prm ? b.prm.tile[0] : 0, b.has_prm ? b.prm.tile[1] : 0, b.has_prm ? b.prm.tile[2] : 0});
+        return c;
+    }
+    auto add = [&](const int (*t)[3], size_t nt) {
+        for (size_t j = 0; j < nt; ++j) c.push_back({t[j][0], t[j][1], t[j][2]});
+    };
+    if (d == 1) add(kTuneTiles1, sizeof(kTuneTiles1) / sizeof(kTuneTiles1[0]));
+    if (d == 2) add(kTuneTiles2, sizeof(kTuneTiles2) / sizeof(kTuneTiles2[0]));
+    if (d == 3) add(kTuneTiles3, sizeof(kTuneTiles3) / sizeof(kTuneTiles3[0]));
+    return c;
+}
+
+// Collect every item's passes (workspace base `ws`, possibly null for sizing)
+// and group them by phase, pipeline position and kernel.
+int build_groups(kde_batch& b, char* ws, std::vector<Pass>& passes, std::vector<Group>& groups, size_t& table_bytes) {
+    passes.clear();
+    groups.clear();
+    const int count = static_cast<int>(b.items.size());
+    std::vector<std::vector<Pass>> ph[3];
+    for (auto& v : ph) v.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const kde_batch_item& it = b.items[i];
+        const Plan& pl = b.plans[i];
+        char* base = ws + b.inst_off[i];
+        auto* counts = reinterpret_cast<uint64_t*>(base);
+        char* bin_ws = base + align_up(pl.counts_bytes);
+        char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
+        Collect c0(ph[0][i]), c1(ph[1][i]), c2(ph[2][i]);
+        KDE_CHECK(run_kspec(pl, conv_ws, b.narrow_mask, c0));
+        KDE_CHECK(run_bin(pl, it.X, it.n, &it.grid, counts, it.n_dropped, bin_ws, c1));
+        KDE_CHECK(run_counts_fwd(pl, counts, &it.grid, conv_ws, b.narrow_mask, c1));
+        KDE_CHECK(run_product_inv(pl, &it.grid, it.density, conv_ws, b.narrow_mask, c2));
+    }
+    for (int phase = 0; phase < 3; ++phase) {
+        // all (order, kernel) keys of this phase, by order then first appearance
+        std::vector<Pass> keys;
+        for (int i = 0; i < count; ++i)
+            for (const Pass& p : ph[phase][i]) {
+                bool found = false;
+                for (const Pass& k : keys) found = found || same_kernel(k, p);
+                if (!found) keys.push_back(p);
+            }
+        std::stable_sort(keys.begin(), keys.end(), [](const Pass& x, const Pass& y) { return x.order < y.order; });
+        for (const Pass& k : keys) {
+            Group g;
+            g.phase = phase;
+            g.key = k;
+            g.batched = k.kind != kPassZero && k.kind != kPassBinAtomic;
+            for (int i = 0; i < count; ++i)
+                for (const Pass& p : ph[phase][i])
+                    if (same_kernel(k, p)) {
+                        g.members.push_back(static_cast<int>(passes.size()));
+                        passes.push_back(p);
+                    }
+            groups.push_back(std::move(g));
+        }
+    }
+    // table layout: per batched group, the argument structs then the offsets
+    size_t off = 0;
+    for (Group& g : groups) {
+        if (!g.batched) continue;
+        uint64_t total = 0;
+        for (int m : g.members) {
+            total += static_cast<uint64_t>(passes[m].blocks);
+            g.lds = std::max(g.lds, passes[m].lds);
+        }
+        if (total >= (uint64_t(1) << 32)) return KDE_ERR_SIZE;
+        g.blocks = static_cast<uint32_t>(total);
+        g.tab_off = off;
+        off = align_up(off + g.members.size() * g.key.size);
+        g.start_off = off;
+        off = align_up(off + (g.members.size() + 1) * sizeof(uint32_t));
+        g.owner_off = off;
+        off = align_up(off + static_cast<size_t>(g.blocks) * sizeof(uint32_t));
+    }
+    table_bytes = off;
+    return KDE_OK;
+}
+
+// Fill the host copy of the launch tables for the device address `dev`.
+void fill_table(const std::vector<Pass>& passes, const std::vector<Group>& groups, std::vector<unsigned char>& t,
+                size_t bytes) {
+    t.assign(bytes, 0);
+    for (const Group& g : groups) {
+        if (!g.batched) continue;
+        uint32_t acc = 0;
+        auto* start = reinterpret_cast<uint32_t*>(t.data() + g.start_off);
+        auto* owner = reinterpret_cast<uint32_t*>(t.data() + g.owner_off);
+        for (size_t j = 0; j < g.members.size(); ++j) {
+            const Pass& p = passes[g.members[j]];
+            std::memcpy(t.data() + g.tab_off + j * g.key.size, p.args, p.size);
+            start[j] = acc;
+            for (int64_t k = 0; k < p.blocks; ++k) owner[acc + k] = static_cast<uint32_t>(j);
+            acc += static_cast<uint32_t>(p.blocks);
+        }
+        start[g.members.size()] = acc;
+    }
+}
+
+int launch_group(const kde_batch& b, const Group& g, hipStream_t s) {
+    if (!g.batched) {
+        for (int m : g.members) KDE_CHECK(exec_pass(b.passes[m], s));
+        return KDE_OK;
+    }
+    const char* dev = b.ws;
+    kde::BatchMap m{dev + g.tab_off, reinterpret_cast<const uint32_t*>(dev + g.start_off),
+                    reinterpret_cast<const uint32_t*>(dev + g.owner_off), static_cast<int>(g.members.size()),
+                    g.blocks};
+    const Pass& k = g.key;
+    hipError_t e = hipSuccess;
+    switch (k.kind) {
+        case kPassBin: e = kde::launch_bin_stage_batch(k.sub, k.d, m, g.lds, s); break;
+        case kPassRowR2C: e = kde::launch_rows_r2c_batch(k.prec, k.P, k.sub, k.d, m, s); break;
+        case kPassRowC2R: e = kde::launch_rows_c2r_batch(k.prec, k.P, k.sub != 0, m, s); break;
+        case kPassCols: e = kde::launch_cols_batch(k.prec, k.P, k.sub, k.narrow == 1, m, s); break;
+        default: return KDE_ERR_ARG;
+    }
+    return e == hipSuccess ? KDE_OK : KDE_ERR_HIP;
+}
+
+int run_batch_phase(const kde_batch& b, int phase, hipStream_t s, Tracer& tr) {
+    for (const Group& g : b.groups) {
+        if (g.phase != phase) continue;
+        KDE_CHECK(launch_group(b, g, s));
+        KDE_TRY(tr.mark(g.key.name));
+    }
+    return KDE_OK;
+}
+
+// Plans every item under the configuration (b.tile) and lays the items'
+// workspaces out after a table region of b.table_cap bytes.
+int layout_batch(kde_batch& b) {
+    const int count = static_cast<int>(b.items.size());
+    b.plans.assign(count, Plan{});
+    for (int i = 0; i < count; ++i) KDE_CHECK(plan_item(b, b.items[i], b.tile, &b.plans[i]));
+    return KDE_OK;
+}
+
+int rebind(kde_batch& b, hipStream_t s) {
+    size_t tb = 0;
+    KDE_CHECK(build_groups(b, b.ws, b.passes, b.groups, tb));
+    if (tb > b.table_cap) return KDE_ERR_WS;
+    fill_table(b.passes, b.groups, b.table, tb);
+    if (tb > 0) {
+        KDE_TRY(hipMemcpyAsync(b.ws, b.table.data(), tb, hipMemcpyHostToDevice, s));
+        KDE_TRY(hipStreamSynchronize(s));
+    }
+    b.bound = true;
+    return KDE_OK;
 }
 
 }  // namespace
@@ -638,7 +1020,8 @@ int kde_bin(const double* X, int64_t n, const kde_grid* grid, const kde_params* 
     }
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    const int r = run_bin(pl, X, n, grid, counts, n_dropped, static_cast<char*>(ws), stream, tr);
+    Direct emit(stream, tr);
+    const int r = run_bin(pl, X, n, grid, counts, n_dropped, static_cast<char*>(ws), emit);
     tr.finish();
     return r;
 }
@@ -652,7 +1035,8 @@ int kde_kernel_grid(const double* H, int64_t n, const kde_grid* grid, const kde_
     if (lags_bytes < pl.pub.lag_bytes) return KDE_ERR_WS;
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    KDE_LAUNCH(kde::launch_kfill(pl.pub.prec, pl.pub.d, pl.pub.L, pl.A, pl.pub.norm, lags, stream), "kfill");
+    KDE_TRY(kde::launch_kfill(pl.pub.prec, pl.pub.d, pl.pub.L, pl.A, pl.pub.norm, lags, stream));
+    KDE_TRY(tr.mark("kfill"));
     tr.finish();
     return KDE_OK;
 }
@@ -665,9 +1049,23 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     if (!counts || !density || !ws) return KDE_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
     if (ws_bytes < pl.pub.conv_ws_bytes) return KDE_ERR_WS;
+    char* conv_ws = static_cast<char*>(ws);
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    const int r = run_pipeline(pl, grid, counts, density, static_cast<char*>(ws), stream, tr, [] { return KDE_OK; });
+    const int r = run_phases(
+        stream, tr,
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_kspec(pl, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_product_inv(pl, grid, density, conv_ws, -1, e);
+        });
     tr.finish();
     return r;
 }
@@ -685,11 +1083,186 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
-    const int r = run_pipeline(pl, grid, counts, density, conv_ws, stream, tr,
-                               [&] { return run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, stream, tr); });
+    const int r = run_phases(
+        stream, tr,
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_kspec(pl, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e));
+            return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_product_inv(pl, grid, density, conv_ws, -1, e);
+        });
     tr.finish();
     return r;
 }
+
+int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_params* params, kde_batch** out) {
+    if (!out) return KDE_ERR_ARG;
+    *out = nullptr;
+    if (!items || count < 1) return KDE_ERR_ARG;
+    auto* b = new (std::nothrow) kde_batch;
+    if (!b) return KDE_ERR_ARG;
+    b->items.assign(items, items + count);
+    if (params) {
+        b->prm = *params;
+        b->has_prm = true;
+    }
+    for (const auto& it : b->items)
+        if (!it.X || !it.density) {
+            delete b;
+            return KDE_ERR_ARG;
+        }
+    for (int k = 0; k < 3; ++k) b->tile[k] = params ? params->tile[k] : 0;
+    // workspace: per item the largest eval workspace over the binning tile
+    // shapes the autotuner may pick; table region: the largest over the same
+    const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
+    std::vector<size_t> need(count, 0);
+    size_t cap = 0;
+    int rc = KDE_OK;
+    for (const auto& c : cands) {
+        for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+        rc = layout_batch(*b);
+        if (rc != KDE_OK) break;
+        for (int i = 0; i < count; ++i) need[i] = std::max(need[i], b->plans[i].pub.eval_ws_bytes);
+    }
+    if (rc == KDE_OK) {
+        b->inst_off.assign(count, 0);
+        size_t off_items = 0;
+        for (int i = 0; i < count; ++i) {
+            b->inst_off[i] = off_items;
+            off_items += align_up(need[i]);
+        }
+        for (const auto& c : cands) {
+            for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+            size_t tb = 0;
+            rc = layout_batch(*b);
+            if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
+            if (rc != KDE_OK) break;
+            cap = std::max(cap, tb);
+        }
+        b->table_cap = align_up(cap);
+        for (int i = 0; i < count; ++i) b->inst_off[i] += b->table_cap;
+        b->ws_bytes = b->table_cap + off_items;
+    }
+    if (rc == KDE_OK) {
+        for (int k = 0; k < 3; ++k) b->tile[k] = cands[0][k];
+        rc = layout_batch(*b);
+        size_t tb = 0;
+        if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
+    }
+    if (rc != KDE_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return KDE_OK;
+}
+
+int kde_batch_query(const kde_batch* b, kde_batch_info* info) {
+    if (!b || !info) return KDE_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->count = static_cast<int32_t>(b->items.size());
+    info->ws_bytes = b->ws_bytes;
+    for (int k = 0; k < 3; ++k) info->tile[k] = b->tile[k];
+    info->narrow_mask = b->narrow_mask;
+    int launches = 0;
+    for (const Group& g : b->groups) launches += g.batched ? 1 : static_cast<int>(g.members.size());
+    info->launches = launches;
+    return KDE_OK;
+}
+
+int kde_batch_bind(kde_batch* b, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!b || !ws || reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
+    if (ws_bytes < b->ws_bytes) return KDE_ERR_WS;
+    b->ws = static_cast<char*>(ws);
+    b->bound = false;
+    return rebind(*b, stream);
+}
+
+int kde_batch_eval(const kde_batch* b, hipStream_t stream) {
+    if (!b || !b->bound) return KDE_ERR_ARG;
+    const kde_params* prm = b->has_prm ? &b->prm : nullptr;
+    Tracer tr(prm, stream);
+    KDE_TRY(tr.start());
+    const int r = run_phases(
+        stream, tr, [&](hipStream_t s) { return run_batch_phase(*b, 0, s, tr); },
+        [&](hipStream_t s) { return run_batch_phase(*b, 1, s, tr); },
+        [&](hipStream_t s) { return run_batch_phase(*b, 2, s, tr); });
+    tr.finish();
+    return r;
+}
+
+int kde_batch_tune(kde_batch* b, int32_t reps, hipStream_t stream) {
+    if (!b || !b->bound || reps < 1) return KDE_ERR_ARG;
+    if (b->has_prm && b->prm.trace_events) return KDE_ERR_ARG;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KDE_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return KDE_ERR_HIP;
+    }
+    auto time_config = [&](float* ms) -> int {
+        KDE_CHECK(rebind(*b, stream));
+        KDE_CHECK(kde_batch_eval(b, stream));   // warm-up
+        KDE_TRY(hipEventRecord(e0, stream));
+        for (int r = 0; r < reps; ++r) KDE_CHECK(kde_batch_eval(b, stream));
+        KDE_TRY(hipEventRecord(e1, stream));
+        KDE_TRY(hipEventSynchronize(e1));
+        KDE_TRY(hipEventElapsedTime(ms, e0, e1));
+        return KDE_OK;
+    };
+    int rc = KDE_OK;
+    int best_tile[3] = {b->tile[0], b->tile[1], b->tile[2]};
+    float best = 0.f;
+    do {
+        rc = time_config(&best);
+        if (rc != KDE_OK) break;
+        // binning tile shape
+        const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
+        for (size_t j = 1; j < cands.size(); ++j) {
+            for (int k = 0; k < 3; ++k) b->tile[k] = cands[j][k];
+            rc = layout_batch(*b);
+            float ms = 0.f;
+            if (rc == KDE_OK) rc = time_config(&ms);
+            if (rc != KDE_OK) break;
+            if (ms < best) {
+                best = ms;
+                for (int k = 0; k < 3; ++k) best_tile[k] = cands[j][k];
+            }
+        }
+        if (rc != KDE_OK) break;
+        for (int k = 0; k < 3; ++k) b->tile[k] = best_tile[k];
+        rc = layout_batch(*b);
+        if (rc != KDE_OK) break;
+        // strided-pass shape, one padded length at a time
+        int lens = 0;
+        for (const auto& pl : b->plans)
+            for (int k = 0; k + 1 < pl.pub.d; ++k) lens |= pl.pub.P[k];
+        for (int lg = 4; lg <= 12; ++lg) {
+            if (!(lens & (1 << lg))) continue;
+            b->narrow_mask ^= 1 << lg;
+            float ms = 0.f;
+            rc = time_config(&ms);
+            if (rc != KDE_OK) break;
+            if (ms < best) best = ms;
+            else b->narrow_mask ^= 1 << lg;
+        }
+        if (rc != KDE_OK) break;
+        rc = rebind(*b, stream);
+        if (rc == KDE_OK && hipStreamSynchronize(stream) != hipSuccess) rc = KDE_ERR_HIP;
+    } while (false);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+void kde_batch_destroy(kde_batch* b) { delete b; }
 
 const char* kde_strerror(int status) {
     switch (status) {

@@ -449,50 +449,54 @@ __device__ __forceinline__ void bin_reduce_body(const BinArgs& a, uint32_t blk, 
     }
 }
 
-// Single-instance and batched entry points of the five stages. Batched
-// launches index the instance by blockIdx.z and return early from blocks past
-// the instance's own extent.
+// Single-instance and batched entry points of the five stages (see BatchMap
+// for how a batched launch assigns workgroups to instances).
 constexpr uint32_t kReduceBlocks = 1024;        // persistent reduce grid (single instance)
-constexpr uint32_t kReduceBlocksBatch = 64;     // ... per instance of a batch
+constexpr uint32_t kReduceBlocksBatch = 64;     // at most this many per instance of a batch
+
+#define KDE_BATCH_PROLOGUE                                              \
+    const auto* tab = static_cast<const BinArgs*>(m.tab);               \
+    const int inst = static_cast<int>(m.owner[blockIdx.x]);      \
+    const BinArgs& a = tab[inst];                                       \
+    const uint32_t blk = blockIdx.x - m.start[inst];
 
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(BinArgs a) { bin_hist_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_hist_batch(const BinArgs* __restrict__ tab) {
-    const BinArgs& a = tab[blockIdx.z];
-    if (blockIdx.x >= a.g.nchunk) return;
-    bin_hist_body<D>(a, blockIdx.x);
+__global__ __launch_bounds__(kBinThreads) void bin_hist_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_hist_body<D>(a, blk);
 }
 __global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(BinArgs a) { bin_scan_body(a, blockIdx.x); }
-__global__ __launch_bounds__(kBinThreads) void bin_scan_batch(const BinArgs* __restrict__ tab) {
-    const BinArgs& a = tab[blockIdx.z];
-    if (blockIdx.x > 0 && blockIdx.x * (kBinThreads / 64) >= static_cast<uint32_t>(a.g.ntiles)) return;
-    bin_scan_body(a, blockIdx.x);
+__global__ __launch_bounds__(kBinThreads) void bin_scan_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_scan_body(a, blk);
 }
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_batch(const BinArgs* __restrict__ tab) {
-    const BinArgs& a = tab[blockIdx.z];
-    if (blockIdx.x >= a.g.nchunk) return;
-    bin_scatter_body<D>(a, blockIdx.x);
+__global__ __launch_bounds__(kBinThreads) void bin_scatter_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_scatter_body<D>(a, blk);
 }
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_accum_batch(const BinArgs* __restrict__ tab) {
-    const BinArgs& a = tab[blockIdx.z];
-    if (blockIdx.x >= a.g.max_segments) return;
-    bin_accum_body<D>(a, blockIdx.x);
+__global__ __launch_bounds__(kBinThreads) void bin_accum_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_accum_body<D>(a, blk);
 }
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinArgs a) {
     bin_reduce_body<D>(a, blockIdx.x, gridDim.x);
 }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_reduce_batch(const BinArgs* __restrict__ tab) {
-    bin_reduce_body<D>(tab[blockIdx.z], blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kBinThreads) void bin_reduce_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_reduce_body<D>(a, blk, m.start[inst + 1] - m.start[inst]);
 }
+
+#undef KDE_BATCH_PROLOGUE
 
 // ---------------------------------------------------------------------------
 // atomic path
@@ -560,6 +564,8 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
     return hipGetLastError();
 }
 
+namespace {
+
 int64_t bin_stage_extent(int stage, const TileGeom& g) {
     switch (stage) {
         case kBinHist:
@@ -569,6 +575,37 @@ int64_t bin_stage_extent(int stage, const TileGeom& g) {
         default: return kReduceBlocks;
     }
 }
+
+template <int D>
+hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
+    const dim3 blk(kBinThreads), grid(static_cast<unsigned>(bin_stage_extent(stage, a.g)));
+    const size_t lds = bin_stage_lds(stage, a.g);
+    switch (stage) {
+        case kBinHist: hipLaunchKernelGGL((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinScan: hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, a); break;
+        case kBinScatter: hipLaunchKernelGGL((bin_scatter_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinAccum: hipLaunchKernelGGL((bin_accum_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinReduce: hipLaunchKernelGGL((bin_reduce_kernel<D>), grid, blk, lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream_t s) {
+    const dim3 blk(kBinThreads), grid(m.blocks);
+    switch (stage) {
+        case kBinHist: hipLaunchKernelGGL((bin_hist_batch<D>), grid, blk, lds, s, m); break;
+        case kBinScan: hipLaunchKernelGGL(bin_scan_batch, grid, blk, 0, s, m); break;
+        case kBinScatter: hipLaunchKernelGGL((bin_scatter_batch<D>), grid, blk, lds, s, m); break;
+        case kBinAccum: hipLaunchKernelGGL((bin_accum_batch<D>), grid, blk, lds, s, m); break;
+        case kBinReduce: hipLaunchKernelGGL((bin_reduce_batch<D>), grid, blk, lds, s, m); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
 
 size_t bin_stage_lds(int stage, const TileGeom& g) {
     switch (stage) {
@@ -580,58 +617,29 @@ size_t bin_stage_lds(int stage, const TileGeom& g) {
     }
 }
 
-namespace {
-
-template <int D>
-hipError_t bin_stage_d(int stage, const BinArgs* one, const BinArgs* tab, int count, int64_t ext, size_t lds,
-                       hipStream_t s) {
-    const dim3 blk(kBinThreads);
-    const bool batch = tab != nullptr;
-    const dim3 grid(static_cast<unsigned>(stage == kBinReduce ? (batch ? kReduceBlocksBatch : kReduceBlocks) : ext), 1,
-                    static_cast<unsigned>(batch ? count : 1));
-    switch (stage) {
-        case kBinHist:
-            if (batch) hipLaunchKernelGGL((bin_hist_batch<D>), grid, blk, lds, s, tab);
-            else hipLaunchKernelGGL((bin_hist_kernel<D>), grid, blk, lds, s, *one);
-            break;
-        case kBinScan:
-            if (batch) hipLaunchKernelGGL(bin_scan_batch, grid, blk, 0, s, tab);
-            else hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, *one);
-            break;
-        case kBinScatter:
-            if (batch) hipLaunchKernelGGL((bin_scatter_batch<D>), grid, blk, lds, s, tab);
-            else hipLaunchKernelGGL((bin_scatter_kernel<D>), grid, blk, lds, s, *one);
-            break;
-        case kBinAccum:
-            if (batch) hipLaunchKernelGGL((bin_accum_batch<D>), grid, blk, lds, s, tab);
-            else hipLaunchKernelGGL((bin_accum_kernel<D>), grid, blk, lds, s, *one);
-            break;
-        case kBinReduce:
-            if (batch) hipLaunchKernelGGL((bin_reduce_batch<D>), grid, blk, lds, s, tab);
-            else hipLaunchKernelGGL((bin_reduce_kernel<D>), grid, blk, lds, s, *one);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+// The reduce stage gets one workgroup per 8 possible shared segments of the
+// instance (at least 1, at most kReduceBlocksBatch); the other stages their
+// single-instance extent.
+int64_t bin_stage_batch_blocks(int stage, const TileGeom& g) {
+    if (stage != kBinReduce) return bin_stage_extent(stage, g);
+    const int64_t segs = g.max_records / g.S;
+    int64_t b = (segs + 7) / 8;
+    if (b < 1) b = 1;
+    if (b > kReduceBlocksBatch) b = kReduceBlocksBatch;
+    return b;
 }
-
-hipError_t bin_stage_any(int stage, int d, const BinArgs* one, const BinArgs* tab, int count, int64_t ext, size_t lds,
-                         hipStream_t s) {
-    if (d == 1) return bin_stage_d<1>(stage, one, tab, count, ext, lds, s);
-    if (d == 2) return bin_stage_d<2>(stage, one, tab, count, ext, lds, s);
-    return bin_stage_d<3>(stage, one, tab, count, ext, lds, s);
-}
-
-}  // namespace
 
 hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s) {
-    return bin_stage_any(stage, a.c.d, &a, nullptr, 1, bin_stage_extent(stage, a.g), bin_stage_lds(stage, a.g), s);
+    if (a.c.d == 1) return bin_stage_d<1>(stage, a, s);
+    if (a.c.d == 2) return bin_stage_d<2>(stage, a, s);
+    return bin_stage_d<3>(stage, a, s);
 }
 
-hipError_t launch_bin_stage_batch(int stage, int d, const BinArgs* tab, int count, int64_t ext, size_t lds,
-                                  hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    return bin_stage_any(stage, d, nullptr, tab, count, ext, lds, s);
+hipError_t launch_bin_stage_batch(int stage, int d, const BatchMap& m, size_t lds, hipStream_t s) {
+    if (m.count <= 0 || m.blocks == 0) return hipSuccess;
+    if (d == 1) return bin_stage_batch_d<1>(stage, m, lds, s);
+    if (d == 2) return bin_stage_batch_d<2>(stage, m, lds, s);
+    return bin_stage_batch_d<3>(stage, m, lds, s);
 }
 
 }  // namespace kde

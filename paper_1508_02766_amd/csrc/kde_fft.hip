@@ -26,321 +26,10 @@
 // the counts sit at the origin, so with P_k >= M_k + L_k the circular
 // convolution equals Eq. (7) on the window [0, M_k) of every axis.
 
-#include "kde_internal.h"
+#include "kde_fft_dev.h"
 
 namespace kde {
 namespace {
-
-// ---------------------------------------------------------------------------
-// complex arithmetic
-// ---------------------------------------------------------------------------
-
-template <typename R>
-struct cpx {
-    R re, im;
-};
-
-template <typename R>
-__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename R>
-__device__ __forceinline__ cpx<R> scal(cpx<R> a, R s) { return {a.re * s, a.im * s}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> conj(cpx<R> a) { return {a.re, -a.im}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> mul_minus_i(cpx<R> a) { return {a.im, -a.re}; }
-
-// ---------------------------------------------------------------------------
-// compile-time twiddle table: exp(-2 pi i k / 4096), k = 0..4095
-// ---------------------------------------------------------------------------
-
-constexpr double kPi = 3.14159265358979323846264338327950288;
-
-// Taylor series on [0, pi/4]; 14 terms leave a truncation error far below
-// one FP64 ulp there.
-constexpr double sin_series(double x) {
-    double x2 = x * x, term = x, s = x;
-    for (int k = 1; k < 14; ++k) {
-        term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
-        s += term;
-    }
-    return s;
-}
-constexpr double cos_series(double x) {
-    double x2 = x * x, term = 1.0, s = 1.0;
-    for (int k = 1; k < 14; ++k) {
-        term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
-        s += term;
-    }
-    return s;
-}
-
-struct SinCos {
-    double s, c;
-};
-
-// sin and cos of 2 pi k / N with the argument reduced exactly in integers
-// (quadrant, then reflection about pi/4), N divisible by 8.
-constexpr SinCos sincos_turn(long k, long N) {
-    k %= N;
-    if (k < 0) k += N;
-    const long quarter = N / 4;
-    const long quad = k / quarter, r = k % quarter;
-    double s = 0.0, c = 0.0;
-    if (2 * r <= quarter) {
-        const double x = 2.0 * kPi * static_cast<double>(r) / static_cast<double>(N);
-        s = sin_series(x);
-        c = cos_series(x);
-    } else {
-        const double x = 2.0 * kPi * static_cast<double>(quarter - r) / static_cast<double>(N);
-        s = cos_series(x);
-        c = sin_series(x);
-    }
-    switch (quad) {
-        case 0: return {s, c};
-        case 1: return {c, -s};
-        case 2: return {-s, -c};
-        default: return {-c, s};
-    }
-}
-
-template <typename R>
-struct TwiddleTable {
-    cpx<R> w[kMaxP];
-};
-
-template <typename R>
-constexpr TwiddleTable<R> make_twiddles() {
-    TwiddleTable<R> t{};
-    for (int k = 0; k < kMaxP; ++k) {
-        const SinCos v = sincos_turn(k, kMaxP);
-        t.w[k] = cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
-    }
-    return t;
-}
-
-__device__ constexpr TwiddleTable<float> g_tw32 = make_twiddles<float>();
-__device__ constexpr TwiddleTable<double> g_tw64 = make_twiddles<double>();
-
-template <typename R>
-__device__ __forceinline__ cpx<R> twiddle(int k);
-template <>
-__device__ __forceinline__ cpx<float> twiddle<float>(int k) { return g_tw32.w[k]; }
-template <>
-__device__ __forceinline__ cpx<double> twiddle<double>(int k) { return g_tw64.w[k]; }
-
-// multiply by the compile-time constant exp(-2 pi i m / 16)
-template <int m, typename R>
-__device__ __forceinline__ cpx<R> rot16(cpx<R> a) {
-    constexpr int mm = ((m % 16) + 16) % 16;
-    if constexpr (mm == 0) {
-        return a;
-    } else if constexpr (mm == 4) {
-        return mul_minus_i(a);
-    } else if constexpr (mm == 8) {
-        return cpx<R>{-a.re, -a.im};
-    } else if constexpr (mm == 12) {
-        return cpx<R>{-a.im, a.re};
-    } else {
-        constexpr SinCos v = sincos_turn(mm, 16);
-        return a * cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
-    }
-}
-
-// ---------------------------------------------------------------------------
-// register DFTs, forward sign, natural order in and out
-// ---------------------------------------------------------------------------
-
-template <typename R>
-__device__ __forceinline__ void dft4(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {
-    const cpx<R> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_minus_i(a1 - a3);
-    a0 = t0 + t2;
-    a2 = t0 - t2;
-    a1 = t1 + t3;
-    a3 = t1 - t3;
-}
-
-template <int RAD, typename R>
-__device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
-    if constexpr (RAD == 2) {
-        const cpx<R> t = a[0] - a[1];
-        a[0] = a[0] + a[1];
-        a[1] = t;
-    } else if constexpr (RAD == 4) {
-        dft4(a[0], a[1], a[2], a[3]);
-    } else if constexpr (RAD == 8) {
-        // even and odd halves, then the radix-2 combination with exp(-2 pi i k / 8)
-        dft4(a[0], a[2], a[4], a[6]);
-        dft4(a[1], a[3], a[5], a[7]);
-        const cpx<R> o1 = rot16<2>(a[3]), o2 = rot16<4>(a[5]), o3 = rot16<6>(a[7]);
-        const cpx<R> y0 = a[0] + a[1], y4 = a[0] - a[1];
-        const cpx<R> y1 = a[2] + o1, y5 = a[2] - o1;
-        const cpx<R> y2 = a[4] + o2, y6 = a[4] - o2;
-        const cpx<R> y3 = a[6] + o3, y7 = a[6] - o3;
-        a[0] = y0; a[1] = y1; a[2] = y2; a[3] = y3;
-        a[4] = y4; a[5] = y5; a[6] = y6; a[7] = y7;
-    } else if constexpr (RAD == 16) {
-        // 16 = 4 x 4: length-4 DFTs over n1 (input n = 4 n1 + n2), twiddle
-        // exp(-2 pi i n2 k1 / 16), length-4 DFTs over n2; output k = k1 + 4 k2.
-        dft4(a[0], a[4], a[8], a[12]);
-        dft4(a[1], a[5], a[9], a[13]);
-        dft4(a[2], a[6], a[10], a[14]);
-        dft4(a[3], a[7], a[11], a[15]);
-        // a[n2 + 4 k1] now holds the inner result for (n2, k1)
-        a[5] = rot16<1>(a[5]);
-        a[6] = rot16<2>(a[6]);
-        a[7] = rot16<3>(a[7]);
-        a[9] = rot16<2>(a[9]);
-        a[10] = rot16<4>(a[10]);
-        a[11] = rot16<6>(a[11]);
-        a[13] = rot16<3>(a[13]);
-        a[14] = rot16<6>(a[14]);
-        a[15] = rot16<9>(a[15]);
-        dft4(a[0], a[1], a[2], a[3]);
-        dft4(a[4], a[5], a[6], a[7]);
-        dft4(a[8], a[9], a[10], a[11]);
-        dft4(a[12], a[13], a[14], a[15]);
-        // a[4 k1 + k2] holds output k1 + 4 k2: transpose the 4 x 4 block
-        cpx<R> y[16];
-#pragma unroll
-        for (int k1 = 0; k1 < 4; ++k1)
-#pragma unroll
-            for (int k2 = 0; k2 < 4; ++k2) y[k1 + 4 * k2] = a[4 * k1 + k2];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) a[i] = y[i];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// in-workgroup Stockham FFT of one line of length P
-// ---------------------------------------------------------------------------
-
-// LDS index of line element p: one padding slot after every 16 elements keeps
-// the stride-16 stores of the first stage off a single bank.
-__device__ __forceinline__ int padi(int p) { return p + (p >> 4); }
-
-template <int P>
-struct LineShape {
-    static constexpr int T = P / 16;          // threads per line
-    static constexpr int LDS = P + P / 16;    // padded LDS elements per line
-};
-
-// Radices of the stages after the first radix-16 one.
-template <int P>
-struct Stages {
-    static constexpr int R1 = P > 16 ? ((P / 16 >= 16) ? 16 : P / 16) : 1;   // second stage (NS = 16)
-    static constexpr int R2 = P > 256 ? P / 256 : 1;                         // third stage (NS = 256)
-    static constexpr int N1 = P > 16 ? (16 / R1) * (R1 - 1) : 0;            // twiddles per thread
-    static constexpr int N2 = P > 256 ? (16 / R2) * (R2 - 1) : 0;
-};
-
-// The twiddles one thread uses in the second and third stages, loaded
-// together at the start of the transform so their latency overlaps the first
-// stage instead of stalling each later one.
-template <typename R, int P>
-struct LineTwiddles {
-    cpx<R> w1[Stages<P>::N1 > 0 ? Stages<P>::N1 : 1];
-    cpx<R> w2[Stages<P>::N2 > 0 ? Stages<P>::N2 : 1];
-};
-
-template <typename R, int P, int RAD, int NS, int N>
-__device__ __forceinline__ void load_stage_twiddles(cpx<R> (&w)[N], int t) {
-    constexpr int T = LineShape<P>::T;
-    constexpr int NB = 16 / RAD;
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int jm = (t + T * u) & (NS - 1);
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
-    }
-}
-
-template <typename R, int P>
-__device__ __forceinline__ void load_twiddles(LineTwiddles<R, P>& tw, int t) {
-    if constexpr (Stages<P>::N1 > 0) load_stage_twiddles<R, P, Stages<P>::R1, 16>(tw.w1, t);
-    if constexpr (Stages<P>::N2 > 0) load_stage_twiddles<R, P, Stages<P>::R2, 256>(tw.w2, t);
-}
-
-// One radix-RAD pass with NS = product of the earlier radices. Thread t owns
-// the butterflies j = t + T u, u < 16/RAD; butterfly j reads elements
-// j + r P/RAD and writes (j / NS) NS RAD + j % NS + r NS. Element
-// t + T m always lives in register slot m. `w` holds this thread's twiddles
-// exp(-2 pi i r (j mod NS) / (NS RAD)) for u, r >= 1.
-template <typename R, int P, int LS, int RAD, int NS, int NW>
-__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t, const cpx<R> (&w)[NW]) {
-    constexpr int T = LineShape<P>::T;
-    constexpr int NB = 16 / RAD;
-    constexpr bool kFirst = (NS == 1);
-    constexpr bool kLast = (NS * RAD == P);
-    if constexpr (!kFirst) {
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = lds[padi(t + T * m) * LS];
-    }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        cpx<R> a[RAD];
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) a[r] = v[u + r * NB];
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) a[r] = a[r] * w[u * (RAD - 1) + r - 1];
-        }
-        dft<RAD>(a);
-#pragma unroll
-        for (int r = 0; r < RAD; ++r) v[u + r * NB] = a[r];
-    }
-    if constexpr (!kLast) {
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int j = t + T * u;
-            const int base = (j / NS) * (NS * RAD) + (j & (NS - 1));
-#pragma unroll
-            for (int r = 0; r < RAD; ++r) lds[padi(base + r * NS) * LS] = v[u + r * NB];
-        }
-    }
-}
-
-// Forward DFT (sign -1) of the line whose element t + T m is in v[m]; on
-// return v[m] holds output t + T m. Every thread of the workgroup must call
-// it (it contains barriers). LS is the LDS distance between padded elements.
-template <typename R, int P, int LS>
-__device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
-    static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
-    LineTwiddles<R, P> tw;
-    load_twiddles<R, P>(tw, t);
-    fft_stage<R, P, LS, 16, 1>(v, lds, t, tw.w1);
-    if constexpr (P > 16) {
-        fft_stage<R, P, LS, Stages<P>::R1, 16>(v, lds, t, tw.w1);
-        if constexpr (P > 256) fft_stage<R, P, LS, Stages<P>::R2, 256>(v, lds, t, tw.w2);
-    }
-}
-
-// Unnormalised inverse DFT (sign +1) through conj(F(conj(x))).
-template <typename R, int P, int LS>
-__device__ __forceinline__ void ifft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
-    fft_line<R, P, LS>(v, lds, t);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
-}
-
-template <typename R>
-__device__ __forceinline__ R to_real(uint64_t x) { return static_cast<R>(x); }
-
-template <typename R>
-__device__ __forceinline__ R fexp(R x);
-template <>
-__device__ __forceinline__ float fexp<float>(float x) { return expf(x); }
-template <>
-__device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
 
 // ---------------------------------------------------------------------------
 // kfill: k_l = norm exp(-0.5 l'Al), A_ab = delta_a delta_b (H^-1)_ab (Eq. 6, Eq. 1)
@@ -370,178 +59,18 @@ __global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_
         l0 = static_cast<R>(rem - L0);
     }
     R q = a00 * l0 * l0;
-    if constexpr (D >= 2) q += a11 * l1 * l1 + R(2) * a01 * l0 * l1;
-    if constexpr (D == 3) q += a22 * l2 * l2 + R(2) * (a02 * l0 * l2 + a12 * l1 * l2);
+    if constexpr (D >= 2) q = fmaR(a11 * l1, l1, fmaR(R(2) * a01 * l0, l1, q));
+    if constexpr (D == 3) q = fmaR(a22 * l2, l2, fmaR(R(2) * (fmaR(a02, l0, a12 * l1)), l2, q));
     lags[i] = norm * fexp<R>(R(-0.5) * q);
 }
 
 // ---------------------------------------------------------------------------
-// rows_r2c: real rows along the contiguous axis -> half spectra (P/2 + 1 bins)
+// single-instance entry points of the passes
 // ---------------------------------------------------------------------------
-
-template <int P>
-struct RowShape {
-    static constexpr int T = P / 16;
-    static constexpr int B = (128 / T) >= 1 ? 128 / T : 1;   // lines (row pairs) per workgroup
-    static constexpr int THREADS = T * B;
-};
-
-template <typename R, int D>
-__device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2) {
-    R q = g.a00 * l0 * l0;
-    if constexpr (D >= 2) q += g.a11 * l1 * l1 + R(2) * g.a01 * l0 * l1;
-    if constexpr (D == 3) q += g.a22 * l2 * l2 + R(2) * (g.a02 * l0 * l2 + g.a12 * l1 * l2);
-    return g.norm * fexp<R>(R(-0.5) * q);
-}
-
-// Leading lags of lag-box row r: d = 2 -> (r - L0); d = 3 -> (r / n1 - L0, r % n1 - L1).
-template <typename R, int D>
-__device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, R& l1) {
-    if constexpr (D == 3) {
-        const int64_t n1 = 2 * g.L1 + 1;
-        l0 = static_cast<R>(r / n1 - g.L0);
-        l1 = static_cast<R>(r % n1 - g.L1);
-    } else {
-        l0 = static_cast<R>(r - g.L0);
-        l1 = 0;
-    }
-}
-
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
-__device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
-    using C = cpx<R>;
-    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
-    __shared__ C lds[B * LINE];
-    const void* __restrict__ in_ = gw.in;
-    void* __restrict__ out_ = gw.out;
-    const int64_t nrows = gw.nrows, in_ld = gw.in_ld, out_ld = gw.out_ld;
-    const int len = gw.len;
-    const int b = threadIdx.x / T, t = threadIdx.x - b * T;
-    const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
-    const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
-    C v[16];
-    if constexpr (IN_KIND == kRowCountsU64) {
-        const uint64_t* in = static_cast<const uint64_t*>(in_);
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int p = t + T * m;
-            R x = 0, y = 0;
-            if (p < len) {
-                if (ok0) x = to_real<R>(in[r0 * in_ld + p]);
-                if (ok1) y = to_real<R>(in[r1 * in_ld + p]);
-            }
-            v[m] = C{x, y};
-        }
-    } else {
-        // weights of two lag-box rows; the last-axis lag l sits at position l mod P
-        R a0 = 0, b0 = 0, a1 = 0, b1 = 0;
-        if (D > 1) {
-            row_lags<R, D>(gw, r0, a0, b0);
-            row_lags<R, D>(gw, r1, a1, b1);
-        }
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int p = t + T * m;
-            R x = 0, y = 0;
-            const bool on = p <= len || p >= P - len;
-            const R l = static_cast<R>(p <= len ? p : p - P);
-            if (on) {
-                if constexpr (D == 1) {
-                    if (ok0) x = gauss_weight<R, 1>(gw, l, R(0), R(0));
-                } else if constexpr (D == 2) {
-                    if (ok0) x = gauss_weight<R, 2>(gw, a0, l, R(0));
-                    if (ok1) y = gauss_weight<R, 2>(gw, a1, l, R(0));
-                } else {
-                    if (ok0) x = gauss_weight<R, 3>(gw, a0, b0, l);
-                    if (ok1) y = gauss_weight<R, 3>(gw, a1, b1, l);
-                }
-            }
-            v[m] = C{x, y};
-        }
-    }
-    C* line = lds + b * LINE;
-    fft_line<R, P, 1>(v, line, t);
-    // split Z = X + iY of two real rows: X_k = (Z_k + conj Z_-k)/2, Y_k = (Z_k - conj Z_-k)/(2i)
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 16; ++m) line[padi(t + T * m)] = v[m];
-    __syncthreads();
-    const R h = R(0.5);
-    for (int k = t; k <= P / 2; k += T) {
-        const C zk = line[padi(k)], zn = line[padi((P - k) & (P - 1))];
-        const C X{(zk.re + zn.re) * h, (zk.im - zn.im) * h};
-        const C Y{(zk.im + zn.im) * h, (zn.re - zk.re) * h};
-        if constexpr (OUT_REAL) {
-            R* out = static_cast<R*>(out_);
-            if (ok0) out[r0 * out_ld + k] = X.re;
-            if (ok1) out[r1 * out_ld + k] = Y.re;
-        } else {
-            C* out = static_cast<C*>(out_);
-            if (ok0) out[r0 * out_ld + k] = X;
-            if (ok1) out[r1 * out_ld + k] = Y;
-        }
-    }
-}
 
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
 __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
     rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(a, blockIdx.x);
-}
-
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_batch(const RowArgs<R>* __restrict__ tab) {
-    const RowArgs<R>& a = tab[blockIdx.z];
-    if (2 * static_cast<int64_t>(blockIdx.x) * RowShape<P>::B >= a.nrows) return;
-    rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(a, blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// rows_c2r: half spectra -> real rows, scaled, window [0, mout)
-// ---------------------------------------------------------------------------
-
-template <typename R, int P, bool MULT>
-__device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk) {
-    using C = cpx<R>;
-    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
-    __shared__ C lds[B * LINE];
-    const C* __restrict__ in = static_cast<const C*>(a.in);
-    const R* __restrict__ mult = static_cast<const R*>(a.mult);
-    R* __restrict__ out = static_cast<R*>(a.out);
-    const int64_t nrows = a.nrows, in_ld = a.in_ld, out_ld = a.out_ld;
-    const int mout = a.mout;
-    const R scale = a.scale;
-    const int b = threadIdx.x / T, t = threadIdx.x - b * T;
-    const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
-    const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
-    C v[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int p = t + T * m;
-        const bool upper = p > P / 2;
-        const int src = upper ? P - p : p;
-        C X{0, 0}, Y{0, 0};
-        if (ok0) X = in[r0 * in_ld + src];
-        if (ok1) Y = in[r1 * in_ld + src];
-        if (upper) {
-            X = conj(X);
-            Y = conj(Y);
-        }
-        if constexpr (MULT) {
-            const R kk = mult[src];
-            X = scal(X, kk);
-            Y = scal(Y, kk);
-        }
-        v[m] = C{X.re - Y.im, X.im + Y.re};   // Z = X + iY
-    }
-    ifft_line<R, P, 1>(v, lds + b * LINE, t);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int p = t + T * m;
-        if (p < mout) {
-            if (ok0) out[r0 * out_ld + p] = v[m].re * scale;
-            if (ok1) out[r1 * out_ld + p] = v[m].im * scale;
-        }
-    }
 }
 
 template <typename R, int P, bool MULT>
@@ -549,109 +78,14 @@ __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(C2RArg
     rows_c2r_body<R, P, MULT>(a, blockIdx.x);
 }
 
-template <typename R, int P, bool MULT>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_batch(const C2RArgs<R>* __restrict__ tab) {
-    const C2RArgs<R>& a = tab[blockIdx.z];
-    if (2 * static_cast<int64_t>(blockIdx.x) * RowShape<P>::B >= a.nrows) return;
-    rows_c2r_body<R, P, MULT>(a, blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// cols: transforms along a strided axis, B adjacent lines per workgroup
-// ---------------------------------------------------------------------------
-
-// B adjacent lines per workgroup: the widest that fits 72 KiB of LDS and 1024
-// threads (up to 16), or 4 for launches that would otherwise leave CUs idle.
-template <typename R, int P, bool NARROW>
-struct ColShape {
-    static constexpr int T = P / 16;
-    static constexpr int kLineBytes = LineShape<P>::LDS * static_cast<int>(sizeof(cpx<R>));
-    static constexpr int kCap = 73728 / kLineBytes;                 // at most 72 KiB of LDS
-    static constexpr int kThr = 1024 / T;
-    static constexpr int kRaw = kCap < kThr ? (kCap < 16 ? kCap : 16) : (kThr < 16 ? kThr : 16);
-    static constexpr int kWide = kRaw >= 16 ? 16 : kRaw >= 8 ? 8 : kRaw >= 4 ? 4 : kRaw >= 2 ? 2 : 1;
-    static constexpr int B = NARROW ? (kWide < 4 ? kWide : 4) : kWide;
-    static constexpr int THREADS = T * B;
-};
-
-template <typename R, int P, int MODE, bool NARROW>
-__device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_t by) {
-    using C = cpx<R>;
-    constexpr int T = ColShape<R, P, NARROW>::T, B = ColShape<R, P, NARROW>::B;
-    __shared__ C lds[B * LineShape<P>::LDS];
-    const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
-    const int64_t w = static_cast<int64_t>(bx) * B + b;
-    const int64_t o = by;
-    const bool act = w < a.W;
-    const C* in = static_cast<const C*>(a.in) + o * a.in_os + w;
-    C v[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const int p = t + T * m;
-        C x{0, 0};
-        if constexpr (MODE == kColFwdPrefix || MODE == kColConvLag) {
-            if (act && p < a.len) x = in[p * a.in_ps];
-        } else if constexpr (MODE == kColFwdCirc) {
-            const int idx = p <= a.len ? p + a.len : (p >= P - a.len ? p - P + a.len : -1);
-            if (act && idx >= 0) x = in[idx * a.in_ps];
-        } else {   // kColInvPrefix
-            if (act) x = in[p * a.in_ps];
-        }
-        v[m] = x;
-    }
-    if constexpr (MODE == kColConvLag) {
-        // the spectrum of this line: transform of the lag column, placed circularly
-        // (it is real because the lag box is centrally symmetric)
-        const C* kin = static_cast<const C*>(a.kt) + o * a.kt_os + w;
-        C kv[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int p = t + T * m;
-            const int idx = p <= a.kt_len ? p + a.kt_len : (p >= P - a.kt_len ? p - P + a.kt_len : -1);
-            kv[m] = (act && idx >= 0) ? kin[idx * a.kt_ps] : C{0, 0};
-        }
-        fft_line<R, P, B>(kv, lds + b, t);
-        fft_line<R, P, B>(v, lds + b, t);
-#pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = scal(v[m], kv[m].re);
-        ifft_line<R, P, B>(v, lds + b, t);
-    } else if constexpr (MODE == kColInvPrefix) {
-        ifft_line<R, P, B>(v, lds + b, t);
-    } else {
-        fft_line<R, P, B>(v, lds + b, t);
-    }
-    if (!act) return;
-    if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
-        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m];
-    } else {   // kColConvLag (in place) and kColInvPrefix: keep [0, mout)
-        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int p = t + T * m;
-            if (p < a.mout) out[p * a.out_ps] = v[m];
-        }
-    }
-}
-
 template <typename R, int P, int MODE, bool NARROW>
 __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
-    cols_body<R, P, MODE, NARROW>(a, blockIdx.x, blockIdx.y);
-}
-
-template <typename R, int P, int MODE, bool NARROW>
-__global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_batch(const ColArgs* __restrict__ tab) {
-    const ColArgs& a = tab[blockIdx.z];
-    if (static_cast<int64_t>(blockIdx.x) * ColShape<R, P, NARROW>::B >= a.W || blockIdx.y >= a.outer) return;
     cols_body<R, P, MODE, NARROW>(a, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <typename R, int D>
 hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* lags, hipStream_t s) {
@@ -667,86 +101,28 @@ hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* la
 }
 
 template <typename R, int P>
-hipError_t rows_r2c_launch(int kind, const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len,
-                           void* out, int64_t out_ld, bool out_real, hipStream_t s) {
-    const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
-    RowArgs<R> a{};
-    a.in = in;
-    a.nrows = nrows;
-    a.in_ld = in_ld;
-    a.len = len;
-    a.out = out;
-    a.out_ld = out_ld;
-    if (kind == kRowCountsU64) {
+hipError_t rows_r2c_launch(int kind, int d, const void* args, hipStream_t s) {
+    const RowArgs<R>& a = *static_cast<const RowArgs<R>*>(args);
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B))), blk(RowShape<P>::THREADS);
+    if (kind == kRowCountsU64)
         hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, a);
-        return hipGetLastError();
-    }
-    a.a00 = static_cast<R>(gauss->A[0]);
-    a.a01 = static_cast<R>(gauss->A[1]);
-    a.a02 = static_cast<R>(gauss->A[2]);
-    a.a11 = static_cast<R>(gauss->A[4]);
-    a.a12 = static_cast<R>(gauss->A[5]);
-    a.a22 = static_cast<R>(gauss->A[8]);
-    a.norm = static_cast<R>(gauss->norm);
-    a.L0 = gauss->L[0];
-    a.L1 = gauss->L[1];
-    if (gauss->d == 1)
+    else if (d == 1)
         hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, a);
-    else if (gauss->d == 2)
+    else if (d == 2)
         hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, a);
     else
         hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, a);
-    (void)out_real;
     return hipGetLastError();
 }
 
 template <typename R, int P>
-hipError_t rows_r2c_batch_launch(int kind, int d, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
-    const int64_t blocks = ceil_div(ceil_div(max_nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks), 1, static_cast<unsigned>(count)), blk(RowShape<P>::THREADS);
-    const auto* t = static_cast<const RowArgs<R>*>(tab);
-    if (kind == kRowCountsU64)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, t);
-    else if (d == 1)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, t);
-    else if (d == 2)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, t);
-    else
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, t);
-    return hipGetLastError();
-}
-
-template <typename R, int P>
-hipError_t rows_c2r_launch(const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
-                           int64_t out_ld, int mout, double scale, hipStream_t s) {
-    const int64_t blocks = ceil_div(ceil_div(nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks)), blk(RowShape<P>::THREADS);
-    C2RArgs<R> a{};
-    a.in = in;
-    a.nrows = nrows;
-    a.in_ld = in_ld;
-    a.mult = mult;
-    a.out = out;
-    a.out_ld = out_ld;
-    a.mout = mout;
-    a.scale = static_cast<R>(scale);
-    if (mult)
+hipError_t rows_c2r_launch(const void* args, hipStream_t s) {
+    const C2RArgs<R>& a = *static_cast<const C2RArgs<R>*>(args);
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B))), blk(RowShape<P>::THREADS);
+    if (a.mult)
         hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, a);
     else
         hipLaunchKernelGGL((rows_c2r_kernel<R, P, false>), g, blk, 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename R, int P>
-hipError_t rows_c2r_batch_launch(bool mult, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
-    const int64_t blocks = ceil_div(ceil_div(max_nrows, 2), RowShape<P>::B);
-    const dim3 g(static_cast<unsigned>(blocks), 1, static_cast<unsigned>(count)), blk(RowShape<P>::THREADS);
-    const auto* t = static_cast<const C2RArgs<R>*>(tab);
-    if (mult)
-        hipLaunchKernelGGL((rows_c2r_batch<R, P, true>), g, blk, 0, s, t);
-    else
-        hipLaunchKernelGGL((rows_c2r_batch<R, P, false>), g, blk, 0, s, t);
     return hipGetLastError();
 }
 
@@ -766,37 +142,18 @@ hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
 }
 
 template <typename R, int P>
-hipError_t cols_batch_launch(int mode, const ColArgs* tab, int count, int64_t max_W, int64_t max_outer,
-                             hipStream_t s) {
-    constexpr int B = ColShape<R, P, false>::B;
-    const dim3 g(static_cast<unsigned>(ceil_div(max_W, B)), static_cast<unsigned>(max_outer),
-                 static_cast<unsigned>(count));
-    const dim3 blk(ColShape<R, P, false>::THREADS);
-    switch (mode) {
-        case kColFwdPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColFwdPrefix, false>), g, blk, 0, s, tab); break;
-        case kColFwdCirc: hipLaunchKernelGGL((cols_batch<R, P, kColFwdCirc, false>), g, blk, 0, s, tab); break;
-        case kColInvPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColInvPrefix, false>), g, blk, 0, s, tab); break;
-        case kColConvLag: hipLaunchKernelGGL((cols_batch<R, P, kColConvLag, false>), g, blk, 0, s, tab); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R, int P>
-hipError_t cols_launch(int mode, const ColArgs& a, hipStream_t s) {
+hipError_t cols_launch(int mode, int narrow, const ColArgs& a, hipStream_t s) {
     // far fewer workgroups than CUs with the wide shape: use four lines per workgroup
-    if (ceil_div(a.W, ColShape<R, P, false>::B) * a.outer < 128) return cols_launch_b<R, P, true>(mode, a, s);
+    if (narrow < 0) narrow = ceil_div(a.W, ColShape<R, P, false>::B) * a.outer < 128 ? 1 : 0;
+    if (narrow) return cols_launch_b<R, P, true>(mode, a, s);
     return cols_launch_b<R, P, false>(mode, a, s);
 }
 
-#define KDE_FOR_EACH_P(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
-
 template <typename R>
-hipError_t rows_r2c_any(int P, int kind, const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len,
-                        void* out, int64_t out_ld, bool out_real, hipStream_t s) {
+hipError_t rows_r2c_any(int P, int kind, int d, const void* args, hipStream_t s) {
     switch (P) {
 #define KDE_CASE(PP) \
-    case PP: return rows_r2c_launch<R, PP>(kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
+    case PP: return rows_r2c_launch<R, PP>(kind, d, args, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -804,11 +161,10 @@ hipError_t rows_r2c_any(int P, int kind, const void* in, const GaussLag* gauss, 
 }
 
 template <typename R>
-hipError_t rows_c2r_any(int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out,
-                        int64_t out_ld, int mout, double scale, hipStream_t s) {
+hipError_t rows_c2r_any(int P, const void* args, hipStream_t s) {
     switch (P) {
 #define KDE_CASE(PP) \
-    case PP: return rows_c2r_launch<R, PP>(in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+    case PP: return rows_c2r_launch<R, PP>(args, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -816,44 +172,10 @@ hipError_t rows_c2r_any(int P, const void* in, int64_t nrows, int64_t in_ld, con
 }
 
 template <typename R>
-hipError_t rows_r2c_batch_any(int P, int kind, int d, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
+hipError_t cols_any(int P, int mode, int narrow, const ColArgs& a, hipStream_t s) {
     switch (P) {
 #define KDE_CASE(PP) \
-    case PP: return rows_r2c_batch_launch<R, PP>(kind, d, tab, count, max_nrows, s);
-        KDE_FOR_EACH_P(KDE_CASE)
-#undef KDE_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t rows_c2r_batch_any(int P, bool mult, const void* tab, int count, int64_t max_nrows, hipStream_t s) {
-    switch (P) {
-#define KDE_CASE(PP) \
-    case PP: return rows_c2r_batch_launch<R, PP>(mult, tab, count, max_nrows, s);
-        KDE_FOR_EACH_P(KDE_CASE)
-#undef KDE_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t cols_batch_any(int P, int mode, const ColArgs* tab, int count, int64_t max_W, int64_t max_outer,
-                          hipStream_t s) {
-    switch (P) {
-#define KDE_CASE(PP) \
-    case PP: return cols_batch_launch<R, PP>(mode, tab, count, max_W, max_outer, s);
-        KDE_FOR_EACH_P(KDE_CASE)
-#undef KDE_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename R>
-hipError_t cols_any(int P, int mode, const ColArgs& a, hipStream_t s) {
-    switch (P) {
-#define KDE_CASE(PP) \
-    case PP: return cols_launch<R, PP>(mode, a, s);
+    case PP: return cols_launch<R, PP>(mode, narrow, a, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -874,43 +196,19 @@ hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], doub
     return kfill_launch<float, 3>(L, A, norm, lags, s);
 }
 
-hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, const GaussLag* gauss, int64_t nrows,
-                           int64_t in_ld, int len, void* out, int64_t out_ld, bool out_real, hipStream_t s) {
-    if (prec == 2)
-        return rows_r2c_any<double>(P, input_kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
-    return rows_r2c_any<float>(P, input_kind, in, gauss, nrows, in_ld, len, out, out_ld, out_real, s);
+hipError_t launch_rows_r2c(int prec, int P, int input_kind, int d, const void* args, hipStream_t s) {
+    if (prec == 2) return rows_r2c_any<double>(P, input_kind, d, args, s);
+    return rows_r2c_any<float>(P, input_kind, d, args, s);
 }
 
-hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64_t in_ld, const void* mult,
-                           void* out, int64_t out_ld, int mout, double scale, hipStream_t s) {
-    if (prec == 2) return rows_c2r_any<double>(P, in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
-    return rows_c2r_any<float>(P, in, nrows, in_ld, mult, out, out_ld, mout, scale, s);
+hipError_t launch_rows_c2r(int prec, int P, const void* args, hipStream_t s) {
+    if (prec == 2) return rows_c2r_any<double>(P, args, s);
+    return rows_c2r_any<float>(P, args, s);
 }
 
-hipError_t launch_cols(int prec, int P, int mode, const ColArgs& a, hipStream_t s) {
-    if (prec == 2) return cols_any<double>(P, mode, a, s);
-    return cols_any<float>(P, mode, a, s);
-}
-
-hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const void* tab, int count,
-                                 int64_t max_nrows, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    if (prec == 2) return rows_r2c_batch_any<double>(P, input_kind, d, tab, count, max_nrows, s);
-    return rows_r2c_batch_any<float>(P, input_kind, d, tab, count, max_nrows, s);
-}
-
-hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const void* tab, int count, int64_t max_nrows,
-                                 hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    if (prec == 2) return rows_c2r_batch_any<double>(P, mult, tab, count, max_nrows, s);
-    return rows_c2r_batch_any<float>(P, mult, tab, count, max_nrows, s);
-}
-
-hipError_t launch_cols_batch(int prec, int P, int mode, const ColArgs* tab, int count, int64_t max_W,
-                             int64_t max_outer, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    if (prec == 2) return cols_batch_any<double>(P, mode, tab, count, max_W, max_outer, s);
-    return cols_batch_any<float>(P, mode, tab, count, max_W, max_outer, s);
+hipError_t launch_cols(int prec, int P, int mode, int narrow, const ColArgs& a, hipStream_t s) {
+    if (prec == 2) return cols_any<double>(P, mode, narrow, a, s);
+    return cols_any<float>(P, mode, narrow, a, s);
 }
 
 }  // namespace kde

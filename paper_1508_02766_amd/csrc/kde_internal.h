@@ -68,14 +68,9 @@ struct BinArgs {
 
 enum BinStage : int { kBinHist = 0, kBinScan = 1, kBinScatter = 2, kBinAccum = 3, kBinReduce = 4 };
 
-// One stage of the tiled binning for one instance...
+// One stage of the tiled binning for one instance; bin_stage_lds is the
+// dynamic LDS a stage needs for the geometry g.
 hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s);
-// ...or for `count` instances of dimension d whose BinArgs are the device array
-// `tab`; `ext` is the largest per-instance grid size of the stage and `lds`
-// the largest per-instance LDS size (bin_stage_extent / bin_stage_lds).
-hipError_t launch_bin_stage_batch(int stage, int d, const BinArgs* tab, int count, int64_t ext, size_t lds,
-                                  hipStream_t s);
-int64_t bin_stage_extent(int stage, const TileGeom& g);
 size_t bin_stage_lds(int stage, const TileGeom& g);
 
 // Input kinds of the row (contiguous-axis) real-to-complex pass.
@@ -142,6 +137,46 @@ struct ColArgs {
     int kt_len;             // their half width L (2 L + 1 entries per column)
 };
 
+// Argument structs of the passes, filled on the host.
+template <typename R>
+RowArgs<R> make_row_args(const void* in, const GaussLag* gauss, int64_t nrows, int64_t in_ld, int len, void* out,
+                         int64_t out_ld) {
+    RowArgs<R> a{};
+    a.in = in;
+    a.nrows = nrows;
+    a.in_ld = in_ld;
+    a.len = len;
+    a.out = out;
+    a.out_ld = out_ld;
+    if (gauss) {
+        a.a00 = static_cast<R>(gauss->A[0]);
+        a.a01 = static_cast<R>(gauss->A[1]);
+        a.a02 = static_cast<R>(gauss->A[2]);
+        a.a11 = static_cast<R>(gauss->A[4]);
+        a.a12 = static_cast<R>(gauss->A[5]);
+        a.a22 = static_cast<R>(gauss->A[8]);
+        a.norm = static_cast<R>(gauss->norm);
+        a.L0 = gauss->L[0];
+        a.L1 = gauss->L[1];
+    }
+    return a;
+}
+
+template <typename R>
+C2RArgs<R> make_c2r_args(const void* in, int64_t nrows, int64_t in_ld, const void* mult, void* out, int64_t out_ld,
+                         int mout, double scale) {
+    C2RArgs<R> a{};
+    a.in = in;
+    a.nrows = nrows;
+    a.in_ld = in_ld;
+    a.mult = mult;
+    a.out = out;
+    a.out_ld = out_ld;
+    a.mout = mout;
+    a.scale = static_cast<R>(scale);
+    return a;
+}
+
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s);
 hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* counts,
@@ -149,23 +184,37 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
 // k_l = norm exp(-0.5 l'Al) on the lag box; A is d x d row-major, in FP64 from the host.
 hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], double norm,
                         void* lags, hipStream_t s);
-hipError_t launch_rows_r2c(int prec, int P, int input_kind, const void* in, const GaussLag* gauss,
-                           int64_t nrows, int64_t in_ld, int len, void* out, int64_t out_ld, bool out_real,
-                           hipStream_t s);
-hipError_t launch_rows_c2r(int prec, int P, const void* in, int64_t nrows, int64_t in_ld,
-                           const void* mult, void* out, int64_t out_ld, int mout, double scale,
-                           hipStream_t s);
-hipError_t launch_cols(int prec, int P, int mode, const ColArgs& a, hipStream_t s);
+// Row passes: `args` points to RowArgs<R> / C2RArgs<R> of the precision prec
+// (1: float, 2: double); d is the lag-box dimension of kRowGaussCirc inputs.
+hipError_t launch_rows_r2c(int prec, int P, int input_kind, int d, const void* args, hipStream_t s);
+hipError_t launch_rows_c2r(int prec, int P, const void* args, hipStream_t s);
+// narrow: 1 four lines per workgroup, 0 the widest shape, -1 chosen from the
+// launch size.
+hipError_t launch_cols(int prec, int P, int mode, int narrow, const ColArgs& a, hipStream_t s);
 
-// Batched forms: `tab` is a device array of `count` argument structs
-// (RowArgs<R> / C2RArgs<R> / ColArgs) of instances with the same P; blockIdx.z
-// selects the instance and blocks past an instance's own extent return early.
-// max_* are the largest per-instance extents.
-hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const void* tab, int count,
-                                 int64_t max_nrows, hipStream_t s);
-hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const void* tab, int count, int64_t max_nrows,
-                                 hipStream_t s);
-hipError_t launch_cols_batch(int prec, int P, int mode, const ColArgs* tab, int count, int64_t max_W,
-                             int64_t max_outer, hipStream_t s);
+// Batched passes: one launch runs the same pass (same kernel template) for
+// `count` instances. `tab` is a device array of their argument structs
+// (BinArgs, RowArgs<R>, C2RArgs<R> or ColArgs), `start` a device array of
+// count + 1 workgroup offsets (start[0] = 0, start[count] = blocks) and
+// `owner` a device array giving for each of the `blocks` workgroups its
+// instance: workgroup b runs as workgroup b - start[owner[b]] of instance
+// owner[b]. Instances with no workgroups are allowed.
+struct BatchMap {
+    const void* tab;
+    const uint32_t* start;
+    const uint32_t* owner;
+    int count;
+    uint32_t blocks;
+};
+
+// Workgroups one instance needs in a batched launch of each pass.
+int64_t bin_stage_batch_blocks(int stage, const TileGeom& g);
+int64_t rows_pass_blocks(int P, int64_t nrows);
+int64_t cols_pass_blocks(int prec, int P, bool narrow, int64_t W, int64_t outer);
+
+hipError_t launch_bin_stage_batch(int stage, int d, const BatchMap& m, size_t lds, hipStream_t s);
+hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const BatchMap& m, hipStream_t s);
+hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const BatchMap& m, hipStream_t s);
+hipError_t launch_cols_batch(int prec, int P, int mode, bool narrow, const BatchMap& m, hipStream_t s);
 
 }  // namespace kde

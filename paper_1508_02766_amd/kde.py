@@ -9,11 +9,12 @@ The names and semantics follow include/kde.h:
     kde_kernel_grid(H, n, grid, **opts)         -> lag-box weights
     kde_conv(counts, n, H, grid, **opts)        -> density from counts
     kde_eval(X, H, grid, **opts)                -> (density, n_dropped)
+    KdeBatch(items, **opts)                     -> kde_batch_create / _bind / _eval / _tune
     kde_strerror(code)                          -> str
 
 ``grid`` is ``(lo, hi, M)`` (per-axis sequences) or a ``KdeGrid``. Options:
 ``prec`` ("f32" default, or "f64"), ``tau``, ``L`` (per-axis override),
-``Q`` (fixed-point bits), ``trace_events`` (list of raw hipEvent_t handles
+``Q`` (fixed-point bits), ``tile`` (binning tile per axis), ``trace_events`` (list of raw hipEvent_t handles
 as ints) with ``trace`` (a dict that receives ``count`` and ``names``).
 """
 from __future__ import annotations
@@ -44,7 +45,7 @@ class KdeGrid(ctypes.Structure):
 
 class KdeParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * 3), ("Q", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("trace_capacity", ctypes.c_int32),
                 ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
                 ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
 
@@ -58,8 +59,20 @@ class KdePlan(ctypes.Structure):
                 ("density_bytes", ctypes.c_size_t), ("bin_ws_bytes", ctypes.c_size_t)]
 
 
+class KdeBatchItem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * 9), ("grid", KdeGrid),
+                ("density", ctypes.c_void_p), ("n_dropped", ctypes.c_void_p)]
+
+
+class KdeBatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("launches", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t),
+                ("tile", ctypes.c_int32 * 3), ("narrow_mask", ctypes.c_int32)]
+
+
 _lib = None
-EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_strerror")
+EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_batch_create",
+           "kde_batch_query", "kde_batch_bind", "kde_batch_eval", "kde_batch_tune", "kde_batch_destroy",
+           "kde_strerror")
 
 
 def library_path() -> str:
@@ -81,10 +94,18 @@ def lib() -> ctypes.CDLL:
         L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
         L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
+        L.kde_batch_create.argtypes = [ctypes.POINTER(KdeBatchItem), ctypes.c_int32, Pp, ctypes.POINTER(vp)]
+        L.kde_batch_query.argtypes = [vp, ctypes.POINTER(KdeBatchInfo)]
+        L.kde_batch_bind.argtypes = [vp, vp, sz, vp]
+        L.kde_batch_eval.argtypes = [vp, vp]
+        L.kde_batch_tune.argtypes = [vp, ctypes.c_int32, vp]
+        L.kde_batch_destroy.argtypes = [vp]
+        L.kde_batch_destroy.restype = None
         L.kde_strerror.argtypes = [ctypes.c_int]
         L.kde_strerror.restype = ctypes.c_char_p
-        for name in EXPORTS[:-1]:
-            getattr(L, name).restype = ctypes.c_int
+        for name in EXPORTS:
+            if name not in ("kde_strerror", "kde_batch_destroy"):
+                getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -119,8 +140,11 @@ def _grid_shape(g: KdeGrid):
     return tuple(int(g.M[k]) for k in range(g.d))
 
 
-def _params(prec=None, tau=None, L=None, Q=None, trace_events=None, trace=None):
+def _params(prec=None, tau=None, L=None, Q=None, tile=None, trace_events=None, trace=None):
     p = KdeParams()
+    if tile is not None:
+        for k, v in enumerate(tile):
+            p.tile[k] = int(v)
     p.prec = _PREC.get(prec, prec)
     if tau is not None:
         p.tau = float(tau)
@@ -197,6 +221,9 @@ def kde_plan_query(H, n: int, grid, **opts) -> dict:
     }
 
 
+_PLAN_OPTS = ("prec", "tau", "L", "Q", "tile")
+
+
 def _workspace(nbytes: int, device, ws=None) -> torch.Tensor:
     if ws is None:
         ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
@@ -216,7 +243,7 @@ def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, ws=None, **opts)
         counts = torch.empty(_grid_shape(g), dtype=torch.uint64, device=dev)
     if n_dropped is None:
         n_dropped = torch.empty(1, dtype=torch.uint64, device=dev)
-    need = kde_plan_query(None, X.shape[0], g, **{k: v for k, v in opts.items() if k in ("Q",)})["bin_ws_bytes"]
+    need = kde_plan_query(None, X.shape[0], g, **{k: v for k, v in opts.items() if k in ("Q", "tile")})["bin_ws_bytes"]
     ws = _workspace(need, dev, ws) if need else ws
     p, keep = _params(**opts)
     _check(lib().kde_bin(_ptr(X), X.shape[0], ctypes.byref(g), ctypes.byref(p), _ptr(counts), _ptr(n_dropped),
@@ -227,7 +254,7 @@ def kde_bin(X: torch.Tensor, grid, counts=None, n_dropped=None, ws=None, **opts)
 
 def kde_kernel_grid(H, n: int, grid, out=None, device="cuda", **opts) -> torch.Tensor:
     g = _grid(grid)
-    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in _PLAN_OPTS})
     shape = tuple(2 * L + 1 for L in plan["L"])
     dt = _TDTYPE[plan["prec"]]
     if out is None:
@@ -245,7 +272,7 @@ def kde_conv(counts: torch.Tensor, n: int, H, grid, out=None, ws=None, **opts) -
     g = _grid(grid)
     if not (counts.is_cuda and counts.dtype in (torch.uint64, torch.int64) and counts.is_contiguous()):
         raise TypeError("counts must be a contiguous uint64 CUDA tensor")
-    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in _PLAN_OPTS})
     dt = _TDTYPE[plan["prec"]]
     dev = counts.device
     if out is None:
@@ -267,7 +294,7 @@ def kde_eval(X: torch.Tensor, H, grid, out=None, ws=None, n_dropped=None, **opts
     if X.dim() != 2 or X.shape[1] != g.d:
         raise ValueError("X must be (n, d)")
     n = X.shape[0]
-    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in ("prec", "tau", "L", "Q")})
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in _PLAN_OPTS})
     dt = _TDTYPE[plan["prec"]]
     dev = X.device
     if out is None:
@@ -336,3 +363,89 @@ class _Prepared(PreparedCall):
     def __init__(self, fn, args, keep, owned, name):
         super().__init__(fn, args, keep, name)
         self._owned = owned          # keeps the ctypes structs and H alive
+
+
+class KdeBatch:
+    """Many independent estimates in one batched pipeline (kde_batch_*).
+
+    ``items`` is a sequence of ``(X, H, grid)`` with X a contiguous (n, d)
+    float64 CUDA tensor. The densities (``self.densities``, one tensor per
+    item) and the workspace are allocated here with torch; the batch is bound
+    on the current stream. ``eval()`` enqueues the whole batch (capturable in
+    a CUDA/HIP graph), ``tune(reps)`` runs the library's autotuner.
+    """
+
+    def __init__(self, items, n_dropped: bool = False, **opts):
+        self._X = []
+        self._H = []
+        arr = (KdeBatchItem * len(items))()
+        dev = None
+        p, keep = _params(**opts)
+        prec = _PREC.get(opts.get("prec"), opts.get("prec"))
+        dt = _TDTYPE[prec]
+        self.densities = []
+        self.n_dropped = []
+        for i, (X, H, grid) in enumerate(items):
+            g = _grid(grid)
+            _need_cuda(X, torch.float64, "X")
+            if X.dim() != 2 or X.shape[1] != g.d:
+                raise ValueError("X must be (n, d)")
+            dev = X.device if dev is None else dev
+            Hn = np.asarray(H, dtype=np.float64).reshape(g.d, g.d)
+            it = arr[i]
+            it.X = X.data_ptr()
+            it.n = X.shape[0]
+            for a in range(g.d):
+                for b in range(g.d):
+                    it.H[a * g.d + b] = float(Hn[a, b])
+            it.grid = g
+            out = torch.empty(_grid_shape(g), dtype=dt, device=dev)
+            it.density = out.data_ptr()
+            self.densities.append(out)
+            if n_dropped:
+                nd = torch.empty(1, dtype=torch.uint64, device=dev)
+                it.n_dropped = nd.data_ptr()
+                self.n_dropped.append(nd)
+            self._X.append(X)
+        self.device = dev
+        self._params, self._keep = p, keep
+        self._items = arr
+        h = ctypes.c_void_p(0)
+        _check(lib().kde_batch_create(arr, len(items), ctypes.byref(p), ctypes.byref(h)), "kde_batch_create")
+        self._h = h
+        self.ws = torch.empty(max(self.info()["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+        if self.ws.data_ptr() % 256:
+            raise RuntimeError("workspace not 256-byte aligned")
+        _check(lib().kde_batch_bind(self._h, _ptr(self.ws), self.ws.numel(), _stream(dev)), "kde_batch_bind")
+        self._stream = _stream(dev)
+
+    def info(self) -> dict:
+        inf = KdeBatchInfo()
+        _check(lib().kde_batch_query(self._h, ctypes.byref(inf)), "kde_batch_query")
+        return {"count": inf.count, "launches": inf.launches, "ws_bytes": inf.ws_bytes, "tile": tuple(inf.tile),
+                "narrow_mask": inf.narrow_mask}
+
+    def eval(self):
+        _check(lib().kde_batch_eval(self._h, _stream(self.device)), "kde_batch_eval")
+
+    def tune(self, reps: int = 3) -> dict:
+        _check(lib().kde_batch_tune(self._h, int(reps), _stream(self.device)), "kde_batch_tune")
+        return self.info()
+
+    def trace(self) -> dict:
+        out = {}
+        if self._keep:
+            arr, cnt, names, _ = self._keep
+            _finish_trace([arr, cnt, names, out])
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().kde_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

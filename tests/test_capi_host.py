@@ -146,3 +146,91 @@ def test_device_entry_points_reject_before_enqueue():
     assert lib.kde_conv(ctypes.c_void_p(8), 10, Hp, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8),
                         ctypes.c_void_p(100), 1 << 30, null) == -1            # misaligned workspace
     assert lib.kde_kernel_grid(Hp, 10, ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(8), 4, null) == -4
+
+
+# --------------------------------------------------------------------------
+# batched planning (kde_batch_create / _query / _destroy do no device work)
+# --------------------------------------------------------------------------
+
+def _batch_items(probs):
+    """ctypes items with placeholder device addresses (never dereferenced on the host)."""
+    arr = (KB.KdeBatchItem * len(probs))()
+    for i, (n, H, grid) in enumerate(probs):
+        g = KB.make_grid(*grid)
+        arr[i].X = 0x10000 + i * 0x1000
+        arr[i].n = n
+        Hn = np.asarray(H, dtype=np.float64).reshape(g.d, g.d)
+        for a in range(g.d):
+            for b in range(g.d):
+                arr[i].H[a * g.d + b] = Hn[a, b]
+        arr[i].grid = g
+        arr[i].density = 0x90000 + i * 0x1000
+    return arr
+
+
+def _batch_info(arr, params=None):
+    lib = K.lib()
+    h = ctypes.c_void_p()
+    rc = lib.kde_batch_create(arr, len(arr), ctypes.byref(params) if params is not None else None, ctypes.byref(h))
+    if rc != 0:
+        return rc, None
+    info = KB.KdeBatchInfo()
+    assert lib.kde_batch_query(h, ctypes.byref(info)) == 0
+    assert lib.kde_batch_eval(h, None) == -1          # not bound: rejected before any HIP call
+    lib.kde_batch_destroy(h)
+    return 0, info
+
+
+def test_batch_plan_sizes_and_launch_count():
+    H2 = [[0.09, 0.06], [0.06, 0.08]]
+    probs = [(1000, H2, ((-3, -3), (3, 3), (64, 64))), (250_000, H2, ((-3, -3), (3, 3), (64, 64))),
+             (40_000, H2, ((-4, -3), (4, 3), (128, 128)))]
+    rc, info = _batch_info(_batch_items(probs))
+    assert rc == 0 and info.count == 3
+    need = sum(K.kde_plan_query(H, n, g)["eval_ws_bytes"] for n, H, g in probs)
+    assert info.ws_bytes >= need
+    assert info.launches == 5 + 4 * 2                 # two padded lengths (128, 256)
+    # d = 1, 2, 3 together: one launch per (pass, template) group
+    probs = [(5000, [[0.2]], ((-3,), (3,), (300,))), (5000, H2, ((-3, -3), (3, 3), (64, 64))),
+             (5000, np.eye(3) * 0.3, ((-3,) * 3, (3,) * 3, (20, 20, 20)))]
+    rc, info = _batch_info(_batch_items(probs))
+    assert rc == 0
+    # binning 5 per d; d=1: kspec, counts, product; d=2: kspec, counts, conv, c2r;
+    # d=3: kspec_r2c, kspec_col2, counts_r2c, counts_col2, conv_col1, inv_col2, c2r
+    assert info.launches == 15 + 3 + 4 + 7
+
+
+def test_batch_plan_errors():
+    H2 = [[0.09, 0.06], [0.06, 0.08]]
+    lib = K.lib()
+    h = ctypes.c_void_p()
+    ok = _batch_items([(1000, H2, ((-3, -3), (3, 3), (64, 64)))])
+    assert lib.kde_batch_create(ok, 0, None, ctypes.byref(h)) == -1
+    assert lib.kde_batch_create(None, 1, None, ctypes.byref(h)) == -1
+    assert lib.kde_batch_create(ok, 1, None, None) == -1
+    bad = _batch_items([(1000, H2, ((-3, -3), (3, 3), (64, 64))), (1000, [[1, 2], [2, 1]], ((-3, -3), (3, 3), (64, 64)))])
+    assert _batch_info(bad)[0] == -2
+    noX = _batch_items([(1000, H2, ((-3, -3), (3, 3), (64, 64)))])
+    noX[0].X = 0
+    assert _batch_info(noX)[0] == -1
+    zero_n = _batch_items([(0, H2, ((-3, -3), (3, 3), (64, 64)))])
+    assert _batch_info(zero_n)[0] == -1
+    p = KB.KdeParams()
+    p.tile[0], p.tile[1] = 48, 32                     # not a power of two
+    assert _batch_info(ok, p)[0] == -1
+    p.tile[0], p.tile[1] = 128, 64                    # 8192 cells
+    assert _batch_info(ok, p)[0] == -1
+    p.tile[0], p.tile[1] = 16, 64
+    rc, info = _batch_info(ok, p)
+    assert rc == 0 and tuple(info.tile) == (16, 64, 0)
+    assert lib.kde_batch_query(None, ctypes.byref(KB.KdeBatchInfo())) == -1
+
+
+def test_tile_override_in_plan():
+    H2 = [[0.09, 0.06], [0.06, 0.08]]
+    g = ((-3, -3), (3, 3), (512, 512))
+    base = K.kde_plan_query(None, 100_000, g)["bin_ws_bytes"]
+    wide = K.kde_plan_query(None, 100_000, g, tile=(64, 64))["bin_ws_bytes"]
+    assert base > 0 and wide > 0 and wide != base
+    with pytest.raises(K.KdeError):
+        K.kde_plan_query(H2, 1000, g, tile=(3, 32))

@@ -18,6 +18,11 @@ Workloads (named by what they are):
 * ``mix3d_128``     d=3, n=1,000,000, 4-component mixture with means in
   [-4,4]^3, random rotations, eigenvalue ratio up to 20; H is the full
   normal-scale matrix; 128x128x128 grid.
+* ``batch2d``       many independent 2-D problems (256 by default): each with
+  n log-uniform in [1e3, 1e6] drawn from a 2-5 component mixture, grid side
+  drawn from {64, 128, 256, 512}, and H a random SPD matrix (random rotation,
+  eigenvalue ratio up to 20) whose determinant matches the normal-scale
+  matrix of its sample.
 
 The grid box of every workload is the data range widened by three marginal
 bandwidth standard deviations sqrt(H_kk) on each side.
@@ -139,6 +144,28 @@ def mix3d_128(n: int = 1_000_000, M: int = 128, seed_offset: int = 0) -> Workloa
     H = normal_scale_H(X)
     lo, hi = grid_box(X, H)
     return Workload("mix3d_128", X, H, lo, hi, (M, M, M))
+
+
+def batch2d(count: int = 256, seed_offset: int = 0, n_range=(1e3, 1e6), sides=(64, 128, 256, 512),
+            ratio_max: float = 20.0) -> list:
+    rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
+    out = []
+    for i in range(count):
+        k = int(rng.integers(2, 6))
+        means = rng.uniform(-4.0, 4.0, size=(k, 2))
+        covs = [random_spd(rng, 2, ratio=(1.0, 10.0)) for _ in range(k)]
+        n = int(round(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        M = int(rng.choice(np.asarray(sides)))
+        X = sample_mixture(rng, n, means, covs)
+        g = np.sqrt(np.linalg.det(normal_scale_H(X)))       # geometric mean of its eigenvalues
+        r = rng.uniform(1.0, ratio_max)
+        Q = random_rotation(rng, 2)
+        lams = g * np.array([1.0 / np.sqrt(r), np.sqrt(r)])
+        H = (Q * lams) @ Q.T
+        H = 0.5 * (H + H.T)
+        lo, hi = grid_box(X, H)
+        out.append(Workload(f"batch2d_{i}", X, H, lo, hi, (M, M)))
+    return out
 
 
 WORKLOADS = {
