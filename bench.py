@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--workload", default="mix2d_512", choices=["mix2d_512", "mix3d_128"])
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / FP64 / batched side measurements")
+    ap.add_argument("--variants", default="mix2d_512_f64,mix3d_128_f32,mix3d_128_f64,batch",
+                    help="comma-separated side measurements to run")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched measurement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-reps", type=int, default=3)
@@ -340,14 +342,15 @@ def main():
     main_run = measure(K, W, hip, a.workload, a.prec, a.steps, a.warmup)
     variants = {}
     if not a.no_variants:
+        chosen = set(a.variants.split(","))
         for name, prec in (("mix2d_512", "f64"), ("mix3d_128", "f32"), ("mix3d_128", "f64")):
-            if (name, prec) == (a.workload, a.prec):
+            if (name, prec) == (a.workload, a.prec) or f"{name}_{prec}" not in chosen:
                 continue
             v = measure(K, W, hip, name, prec, max(20, a.steps // 4), 5)
             variants[f"{name}_{prec}"] = {k: v[k] for k in ("ms_per_step", "ms_per_step_traced", "samples_per_s",
                                                             "grid_pts_per_s", "conv_us", "conv_grid_pts_per_s",
                                                             "bin_us", "bin_samples_per_s", "kernels")}
-        if a.batch > 0:
+        if a.batch > 0 and "batch" in chosen:
             variants[f"batch2d_{a.batch}_f32"] = measure_batch(K, W, hip, a.batch, max(20, a.steps // 4), 5)
     # roofline of the dominant kernel of the main workload
     kern = main_run["kernels"]

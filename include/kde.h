@@ -109,6 +109,7 @@ typedef struct kde_plan {
                                  convolution workspaces) */
     size_t density_bytes;     /* prod M_k * sizeof(real) */
     size_t bin_ws_bytes;      /* workspace needed by kde_bin (0: none) */
+    size_t lscv_ws_bytes;     /* workspace needed by kde_lscv (0 when n < 2) */
 } kde_plan;
 
 /* Plan one problem on the host (no device work, no HIP call).
@@ -162,6 +163,20 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid,
              const kde_params* params, void* density, void* ws, size_t ws_bytes,
              uint64_t* n_dropped, hipStream_t stream);
 
+/* Least-squares cross-validation objective of H from fixed-point counts
+ * (bandwidth selection, the use of the binned FFT method that Section 5 points
+ * to). With phi_A the N(0, A) density, the objective
+ *     LSCV(H) = n^-2 sum_{i,j} phi_2H(X_i - X_j) - 2 [n (n-1)]^-1 sum_{i != j} phi_H(X_i - X_j)
+ * is evaluated in binned form: each pair sum is sum_j c_j (c * kappa_A)_j with
+ * kappa_A(l) = phi_A(delta l) on the lag box of Eq. (15) for A (Eq. 7 with
+ * weights n * k_l), and the i = j pairs of the second sum are removed as
+ * n phi_H(0). Two convolutions (2H, then H) and two FP64 dot products.
+ * counts: device, prod M_k uint64 as kde_bin writes them; n >= 2 is the sample
+ * count; out: device, 3 doubles = {LSCV, first term, second term}.
+ * ws (device, 256-byte aligned) must hold plan.lscv_ws_bytes. */
+int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid* grid,
+             const kde_params* params, double* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Batched evaluation: many independent estimates (each its own X, n, H and
  * grid; d may differ between items) computed together. Every pass of the
@@ -179,6 +194,13 @@ typedef struct kde_batch_item {
     kde_grid grid;
     void* density;            /* device, prod M_k reals of the batch precision (output) */
     uint64_t* n_dropped;      /* device, may be NULL: samples outside the grid (as kde_bin) */
+    const uint64_t* counts;   /* device, may be NULL. If set, the item starts from these
+                                 fixed-point counts (as kde_bin writes them; kde_conv
+                                 semantics), X and n_dropped are ignored, and n is the
+                                 sample count of Eq. (1) */
+    double* dot;              /* device, may be NULL. If set, receives
+                                 sum_j c_j f_j (c_j the counts in real units, f the
+                                 item's density) in FP64, summed in a fixed order */
 } kde_batch_item;
 
 typedef struct kde_batch kde_batch;   /* opaque; host memory only */

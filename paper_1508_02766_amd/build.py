@@ -32,6 +32,7 @@ SOURCES = {
     # from the same device code rounds identically
     "kde_fft.hip": ["-ffp-contract=off"],
     "kde_fft_batch.hip": ["-ffp-contract=off"],
+    "kde_lscv.hip": ["-ffp-contract=off"],
     "kde_api.cpp": [],
 }
 

@@ -51,6 +51,7 @@ struct BinLayout {
 
 struct Plan {
     kde_plan pub;
+    int64_t M[3];     // grid nodes per axis
     double A[9];      // A_ab = delta_a delta_b (H^-1)_ab
     double tau;
     Layout lay;
@@ -133,6 +134,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     if (d < 1 || d > 3) return KDE_ERR_ARG;
     if (n < n_min) return KDE_ERR_ARG;
     p.d = d;
+    for (int k = 0; k < d; ++k) out->M[k] = g->M[k];
     for (int k = 0; k < d; ++k) {
         if (g->M[k] < 2 || g->M[k] > (int64_t(1) << 24)) return KDE_ERR_ARG;
         if (!std::isfinite(g->lo[k]) || !std::isfinite(g->hi[k]) || !(g->hi[k] > g->lo[k])) return KDE_ERR_ARG;
@@ -359,7 +361,8 @@ struct Tracer {
 // batched launch. The single-instance path launches passes as they are
 // produced; the batched path collects them and launches all passes with the
 // same kernel together.
-enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols };
+enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols, kPassDotPartial,
+                      kPassDotFinal };
 
 struct Pass {
     PassKind kind;
@@ -401,6 +404,10 @@ int exec_pass(const Pass& p, hipStream_t s) {
         case kPassCols:
             e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
             break;
+        case kPassDotPartial:
+        case kPassDotFinal:
+            // the single-problem path runs both stages through launch_dot
+            return KDE_ERR_ARG;
     }
     return e == hipSuccess ? KDE_OK : KDE_ERR_HIP;
 }
@@ -722,6 +729,35 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     return emit(row_c2r_pass(pl, P2, b.z1, M0 * M1, Hp, nullptr, density, M2, static_cast<int>(M2), scale, 22, "c2r"));
 }
 
+// Dot product of the counts with the density (two passes: per-chunk partials,
+// then their sum), for the LSCV objective.
+int run_dot(const Plan& pl, const uint64_t* counts, const void* density, double* partial, double* out, Emit& emit) {
+    int64_t cells = 1;
+    for (int k = 0; k < pl.pub.d; ++k) cells *= pl.M[k];
+    kde::DotArgs a{};
+    a.counts = counts;
+    a.f = density;
+    a.cells = cells;
+    a.scale = std::ldexp(1.0, -pl.pub.d * pl.pub.Q);
+    a.partial = partial;
+    a.nb = kde::dot_blocks(cells);
+    a.out = out;
+    Pass p;
+    p.kind = kPassDotPartial;
+    p.prec = pl.pub.prec;
+    p.order = 30;
+    p.name = "dot_partial";
+    p.blocks = a.nb;
+    p.set_args(a);
+    KDE_CHECK(emit(p));
+    p.kind = kPassDotFinal;
+    p.prec = 0;
+    p.order = 31;
+    p.name = "dot_final";
+    p.blocks = 1;
+    return emit(p);
+}
+
 // A second stream per device on which the kernel spectrum is computed while
 // the caller's stream bins and transforms the counts. Created once (default
 // priority, non-blocking) and kept for the life of the process; the fork /
@@ -792,6 +828,36 @@ struct Group {
     uint32_t blocks = 0;
     size_t lds = 0;
 };
+
+// Workspace of kde_lscv: one density (reused by both convolutions), the two
+// dots, the partial sums, and the larger of the two convolution workspaces.
+struct LscvLayout {
+    size_t density = 0, dots = 0, partial = 0, conv = 0, total = 0;
+};
+
+int lscv_plans(const double* H, int64_t n, const kde_grid* g, const kde_params* prm, Plan* p1, Plan* p2,
+               LscvLayout* L) {
+    if (n < 2 || !H || !g) return KDE_ERR_ARG;
+    KDE_CHECK(make_plan(H, n, 1, true, g, prm, p1));
+    const int d = p1->pub.d;
+    double H2[9] = {};
+    for (int i = 0; i < d * d; ++i) H2[i] = 2.0 * H[i];
+    KDE_CHECK(make_plan(H2, n, 1, true, g, prm, p2));
+    int64_t cells = 1;
+    for (int k = 0; k < d; ++k) cells *= g->M[k];
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L->density = take(p1->pub.density_bytes);
+    L->dots = take(2 * sizeof(double));
+    L->partial = take(static_cast<size_t>(kde::dot_blocks(cells)) * sizeof(double));
+    L->conv = take(std::max(p1->pub.conv_ws_bytes, p2->pub.conv_ws_bytes));
+    L->total = off;
+    return KDE_OK;
+}
 
 bool same_kernel(const Pass& a, const Pass& b) {
     return a.kind == b.kind && a.prec == b.prec && a.P == b.P && a.sub == b.sub && a.d == b.d &&
@@ -868,14 +934,17 @@ int build_groups(kde_batch& b, char* ws, std::vector<Pass>& passes, std::vector<
         const kde_batch_item& it = b.items[i];
         const Plan& pl = b.plans[i];
         char* base = ws + b.inst_off[i];
-        auto* counts = reinterpret_cast<uint64_t*>(base);
+        uint64_t* own_counts = reinterpret_cast<uint64_t*>(base);
+        const uint64_t* counts = it.counts ? it.counts : own_counts;
         char* bin_ws = base + align_up(pl.counts_bytes);
         char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
+        auto* partial = reinterpret_cast<double*>(conv_ws + align_up(pl.pub.conv_ws_bytes));
         Collect c0(ph[0][i]), c1(ph[1][i]), c2(ph[2][i]);
         KDE_CHECK(run_kspec(pl, conv_ws, b.narrow_mask, c0));
-        KDE_CHECK(run_bin(pl, it.X, it.n, &it.grid, counts, it.n_dropped, bin_ws, c1));
+        if (!it.counts) KDE_CHECK(run_bin(pl, it.X, it.n, &it.grid, own_counts, it.n_dropped, bin_ws, c1));
         KDE_CHECK(run_counts_fwd(pl, counts, &it.grid, conv_ws, b.narrow_mask, c1));
         KDE_CHECK(run_product_inv(pl, &it.grid, it.density, conv_ws, b.narrow_mask, c2));
+        if (it.dot) KDE_CHECK(run_dot(pl, counts, it.density, partial, it.dot, c2));
     }
     for (int phase = 0; phase < 3; ++phase) {
         // all (order, kernel) keys of this phase, by order then first appearance
@@ -959,6 +1028,8 @@ int launch_group(const kde_batch& b, const Group& g, hipStream_t s) {
         case kPassRowR2C: e = kde::launch_rows_r2c_batch(k.prec, k.P, k.sub, k.d, m, s); break;
         case kPassRowC2R: e = kde::launch_rows_c2r_batch(k.prec, k.P, k.sub != 0, m, s); break;
         case kPassCols: e = kde::launch_cols_batch(k.prec, k.P, k.sub, k.narrow == 1, m, s); break;
+        case kPassDotPartial: e = kde::launch_dot_batch(k.prec, false, m, s); break;
+        case kPassDotFinal: e = kde::launch_dot_batch(k.prec, true, m, s); break;
         default: return KDE_ERR_ARG;
     }
     return e == hipSuccess ? KDE_OK : KDE_ERR_HIP;
@@ -1005,6 +1076,11 @@ int kde_plan_query(const double* H, int64_t n, const kde_grid* grid, const kde_p
     const int rc = H ? make_plan(H, n, 1, true, grid, params, &pl) : make_plan(nullptr, n, 0, false, grid, params, &pl);
     if (rc != KDE_OK) return rc;
     *out = pl.pub;
+    if (H && n >= 2) {
+        Plan p1, p2;
+        LscvLayout L;
+        if (lscv_plans(H, n, grid, params, &p1, &p2, &L) == KDE_OK) out->lscv_ws_bytes = L.total;
+    }
     return KDE_OK;
 }
 
@@ -1102,6 +1178,61 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     return r;
 }
 
+int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid* grid, const kde_params* params,
+             double* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    Plan p1, p2;
+    LscvLayout L;
+    const int rc = lscv_plans(H, n, grid, params, &p1, &p2, &L);
+    if (rc != KDE_OK) return rc;
+    if (!counts || !out || !ws || reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
+    if (ws_bytes < L.total) return KDE_ERR_WS;
+    char* base = static_cast<char*>(ws);
+    void* density = base + L.density;
+    auto* dots = reinterpret_cast<double*>(base + L.dots);
+    auto* partial = reinterpret_cast<double*>(base + L.partial);
+    char* conv_ws = base + L.conv;
+    int64_t cells = 1;
+    for (int k = 0; k < p1.pub.d; ++k) cells *= grid->M[k];
+    Tracer tr(params, stream);
+    KDE_TRY(tr.start());
+    // first term with 2H, then the second with H; each convolution is followed
+    // by its dot product on the caller's stream
+    const Plan* plans[2] = {&p2, &p1};
+    for (int t = 0; t < 2; ++t) {
+        const Plan& pl = *plans[t];
+        KDE_CHECK(run_phases(
+            stream, tr,
+            [&](hipStream_t s) {
+                Direct e(s, tr);
+                return run_kspec(pl, conv_ws, -1, e);
+            },
+            [&](hipStream_t s) {
+                Direct e(s, tr);
+                return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
+            },
+            [&](hipStream_t s) {
+                Direct e(s, tr);
+                return run_product_inv(pl, grid, density, conv_ws, -1, e);
+            }));
+        kde::DotArgs a{};
+        a.counts = counts;
+        a.f = density;
+        a.cells = cells;
+        a.scale = std::ldexp(1.0, -p1.pub.d * p1.pub.Q);
+        a.partial = partial;
+        a.nb = kde::dot_blocks(cells);
+        a.out = dots + t;
+        KDE_TRY(kde::launch_dot(pl.pub.prec, a, stream));
+        KDE_TRY(tr.mark("dot"));
+    }
+    // phi_H(0) = (2 pi)^-d/2 |H|^-1/2 = n k_0
+    const double phi0 = p1.pub.norm * static_cast<double>(n);
+    KDE_TRY(kde::launch_lscv_combine(dots, static_cast<double>(n), phi0, out, stream));
+    KDE_TRY(tr.mark("lscv_combine"));
+    tr.finish();
+    return KDE_OK;
+}
+
 int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_params* params, kde_batch** out) {
     if (!out) return KDE_ERR_ARG;
     *out = nullptr;
@@ -1114,7 +1245,7 @@ int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_param
         b->has_prm = true;
     }
     for (const auto& it : b->items)
-        if (!it.X || !it.density) {
+        if ((!it.X && !it.counts) || !it.density) {
             delete b;
             return KDE_ERR_ARG;
         }
@@ -1129,7 +1260,14 @@ int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_param
         for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
         rc = layout_batch(*b);
         if (rc != KDE_OK) break;
-        for (int i = 0; i < count; ++i) need[i] = std::max(need[i], b->plans[i].pub.eval_ws_bytes);
+        for (int i = 0; i < count; ++i) {
+            const Plan& pl = b->plans[i];
+            int64_t cells = 1;
+            for (int k = 0; k < pl.pub.d; ++k) cells *= pl.M[k];
+            // eval workspace (counts, binning, convolution) then the dot partials
+            const size_t dot = b->items[i].dot ? static_cast<size_t>(kde::dot_blocks(cells)) * sizeof(double) : 0;
+            need[i] = std::max(need[i], align_up(pl.pub.eval_ws_bytes) + dot);
+        }
     }
     if (rc == KDE_OK) {
         b->inst_off.assign(count, 0);

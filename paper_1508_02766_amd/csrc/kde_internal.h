@@ -217,4 +217,26 @@ hipError_t launch_rows_r2c_batch(int prec, int P, int input_kind, int d, const B
 hipError_t launch_rows_c2r_batch(int prec, int P, bool mult, const BatchMap& m, hipStream_t s);
 hipError_t launch_cols_batch(int prec, int P, int mode, bool narrow, const BatchMap& m, hipStream_t s);
 
+// Dot products of counts and densities (LSCV objective): the partial pass
+// sums cells [b kDotChunk, (b + 1) kDotChunk) per workgroup b into
+// partial[b] (times scale), the final pass writes the sum of the nb partials
+// to out[0]. Both in FP64, in a fixed order.
+constexpr int64_t kDotChunk = 8192;
+
+struct DotArgs {
+    const uint64_t* counts;
+    const void* f;          // density, float or double
+    int64_t cells;
+    double scale;           // 2^-dQ
+    double* partial;        // [nb]
+    int64_t nb;
+    double* out;
+};
+
+int64_t dot_blocks(int64_t cells);
+hipError_t launch_dot(int prec, const DotArgs& a, hipStream_t s);
+hipError_t launch_dot_batch(int prec, bool final_stage, const BatchMap& m, hipStream_t s);
+// out[0..2] = {LSCV, dots[0] / n, 2 (dots[1] - phi0) / (n - 1)}.
+hipError_t launch_lscv_combine(const double* dots, double n, double phi0, double* out, hipStream_t s);
+
 }  // namespace kde

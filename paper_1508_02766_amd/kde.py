@@ -9,6 +9,7 @@ The names and semantics follow include/kde.h:
     kde_kernel_grid(H, n, grid, **opts)         -> lag-box weights
     kde_conv(counts, n, H, grid, **opts)        -> density from counts
     kde_eval(X, H, grid, **opts)                -> (density, n_dropped)
+    kde_lscv(counts, n, H, grid, **opts)        -> LSCV objective and its two terms
     KdeBatch(items, **opts)                     -> kde_batch_create / _bind / _eval / _tune
     kde_strerror(code)                          -> str
 
@@ -56,12 +57,14 @@ class KdePlan(ctypes.Structure):
                 ("delta", ctypes.c_double * 3), ("lambda_max", ctypes.c_double), ("det_H", ctypes.c_double),
                 ("norm", ctypes.c_double), ("lag_count", ctypes.c_int64), ("lag_bytes", ctypes.c_size_t),
                 ("conv_ws_bytes", ctypes.c_size_t), ("eval_ws_bytes", ctypes.c_size_t),
-                ("density_bytes", ctypes.c_size_t), ("bin_ws_bytes", ctypes.c_size_t)]
+                ("density_bytes", ctypes.c_size_t), ("bin_ws_bytes", ctypes.c_size_t),
+                ("lscv_ws_bytes", ctypes.c_size_t)]
 
 
 class KdeBatchItem(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * 9), ("grid", KdeGrid),
-                ("density", ctypes.c_void_p), ("n_dropped", ctypes.c_void_p)]
+                ("density", ctypes.c_void_p), ("n_dropped", ctypes.c_void_p), ("counts", ctypes.c_void_p),
+                ("dot", ctypes.c_void_p)]
 
 
 class KdeBatchInfo(ctypes.Structure):
@@ -70,7 +73,7 @@ class KdeBatchInfo(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_batch_create",
+EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_batch_create",
            "kde_batch_query", "kde_batch_bind", "kde_batch_eval", "kde_batch_tune", "kde_batch_destroy",
            "kde_strerror")
 
@@ -94,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
         L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
+        L.kde_lscv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_batch_create.argtypes = [ctypes.POINTER(KdeBatchItem), ctypes.c_int32, Pp, ctypes.POINTER(vp)]
         L.kde_batch_query.argtypes = [vp, ctypes.POINTER(KdeBatchInfo)]
         L.kde_batch_bind.argtypes = [vp, vp, sz, vp]
@@ -217,7 +221,7 @@ def kde_plan_query(H, n: int, grid, **opts) -> dict:
         "delta": tuple(out.delta[:d]), "lambda_max": out.lambda_max, "det_H": out.det_H, "norm": out.norm,
         "lag_count": out.lag_count, "lag_bytes": out.lag_bytes, "conv_ws_bytes": out.conv_ws_bytes,
         "eval_ws_bytes": out.eval_ws_bytes, "density_bytes": out.density_bytes,
-        "bin_ws_bytes": out.bin_ws_bytes,
+        "bin_ws_bytes": out.bin_ws_bytes, "lscv_ws_bytes": out.lscv_ws_bytes,
     }
 
 
@@ -311,6 +315,27 @@ def kde_eval(X: torch.Tensor, H, grid, out=None, ws=None, n_dropped=None, **opts
     return out, n_dropped
 
 
+def kde_lscv(counts: torch.Tensor, n: int, H, grid, out=None, ws=None, **opts) -> torch.Tensor:
+    """LSCV(H) from fixed-point counts: a float64 CUDA tensor {LSCV, first term, second term}."""
+    g = _grid(grid)
+    if not (counts.is_cuda and counts.dtype in (torch.uint64, torch.int64) and counts.is_contiguous()):
+        raise TypeError("counts must be a contiguous uint64 CUDA tensor")
+    plan = kde_plan_query(H, n, g, **{k: v for k, v in opts.items() if k in _PLAN_OPTS})
+    if plan["lscv_ws_bytes"] == 0:
+        raise ValueError("LSCV needs n >= 2 and padded lengths <= 4096 for 2H")
+    dev = counts.device
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=dev)
+    _need_cuda(out, torch.float64, "out")
+    ws = _workspace(plan["lscv_ws_bytes"], dev, ws)
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    _check(lib().kde_lscv(_ptr(counts), int(n), Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws),
+                          ws.numel(), _stream(dev)), "kde_lscv")
+    _finish_trace(keep)
+    return out
+
+
 class PreparedCall:
     """A library call with every argument marshalled once, for repeated launches
     (benchmarks, serving loops): ``call()`` enqueues the work on the stream that
@@ -369,13 +394,16 @@ class KdeBatch:
     """Many independent estimates in one batched pipeline (kde_batch_*).
 
     ``items`` is a sequence of ``(X, H, grid)`` with X a contiguous (n, d)
-    float64 CUDA tensor. The densities (``self.densities``, one tensor per
-    item) and the workspace are allocated here with torch; the batch is bound
-    on the current stream. ``eval()`` enqueues the whole batch (capturable in
-    a CUDA/HIP graph), ``tune(reps)`` runs the library's autotuner.
+    float64 CUDA tensor, or ``(counts, n, H, grid)`` with fixed-point counts
+    (uint64 CUDA tensor, as kde_bin writes them). The densities
+    (``self.densities``, one tensor per item) and the workspace are allocated
+    here with torch; the batch is bound on the current stream. ``eval()``
+    enqueues the whole batch (capturable in a CUDA/HIP graph), ``tune(reps)``
+    runs the library's autotuner. With ``dots=True``, ``self.dots`` (float64,
+    one entry per item) receives sum_j c_j f_j at every eval.
     """
 
-    def __init__(self, items, n_dropped: bool = False, **opts):
+    def __init__(self, items, n_dropped: bool = False, dots: bool = False, **opts):
         self._X = []
         self._H = []
         arr = (KdeBatchItem * len(items))()
@@ -385,16 +413,30 @@ class KdeBatch:
         dt = _TDTYPE[prec]
         self.densities = []
         self.n_dropped = []
-        for i, (X, H, grid) in enumerate(items):
-            g = _grid(grid)
-            _need_cuda(X, torch.float64, "X")
-            if X.dim() != 2 or X.shape[1] != g.d:
-                raise ValueError("X must be (n, d)")
+        first = items[0][0]
+        self.dots = torch.zeros(len(items), dtype=torch.float64, device=first.device) if dots else None
+        for i, item in enumerate(items):
+            it = arr[i]
+            if len(item) == 4:
+                C, n, H, grid = item
+                g = _grid(grid)
+                if not (C.is_cuda and C.dtype in (torch.uint64, torch.int64) and C.is_contiguous()):
+                    raise TypeError("counts must be a contiguous uint64 CUDA tensor")
+                it.counts = C.data_ptr()
+                it.n = int(n)
+                X = C
+            else:
+                X, H, grid = item
+                g = _grid(grid)
+                _need_cuda(X, torch.float64, "X")
+                if X.dim() != 2 or X.shape[1] != g.d:
+                    raise ValueError("X must be (n, d)")
+                it.X = X.data_ptr()
+                it.n = X.shape[0]
             dev = X.device if dev is None else dev
             Hn = np.asarray(H, dtype=np.float64).reshape(g.d, g.d)
-            it = arr[i]
-            it.X = X.data_ptr()
-            it.n = X.shape[0]
+            if dots:
+                it.dot = self.dots.data_ptr() + 8 * i
             for a in range(g.d):
                 for b in range(g.d):
                     it.H[a * g.d + b] = float(Hn[a, b])

@@ -234,3 +234,44 @@ def test_tile_override_in_plan():
     assert base > 0 and wide > 0 and wide != base
     with pytest.raises(K.KdeError):
         K.kde_plan_query(H2, 1000, g, tile=(3, 32))
+
+
+def test_lscv_plan_and_rejections():
+    lib = K.lib()
+    H2 = [[0.09, 0.06], [0.06, 0.08]]
+    g = ((-3, -3), (3, 3), (64, 64))
+    p = K.kde_plan_query(H2, 1000, g)
+    assert p["lscv_ws_bytes"] > p["density_bytes"]
+    assert K.kde_plan_query(H2, 1, g)["lscv_ws_bytes"] == 0
+    grid = KB.make_grid(*g)
+    Hn = np.ascontiguousarray(np.array(H2, dtype=np.float64))
+    Hp = Hn.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(0x100000)
+    ws = ctypes.c_void_p(0x200000)
+    need = p["lscv_ws_bytes"]
+    call = lambda counts, n, H, out, wsp, nbytes: lib.kde_lscv(counts, n, H, ctypes.byref(grid), None, out, wsp,
+                                                                nbytes, None)
+    assert call(fake, 1, Hp, fake, ws, need) == -1           # n < 2
+    assert call(None, 1000, Hp, fake, ws, need) == -1        # no counts
+    assert call(fake, 1000, Hp, None, ws, need) == -1        # no output
+    assert call(fake, 1000, Hp, fake, ctypes.c_void_p(0x200010), need) == -1   # misaligned workspace
+    assert call(fake, 1000, Hp, fake, ws, need - 1) == -4    # workspace too small
+    bad = np.ascontiguousarray(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    assert call(fake, 1000, bad.ctypes.data_as(ctypes.c_void_p), fake, ws, need) == -2
+
+
+def test_search_helpers_on_host():
+    from paper_1508_02766_amd import lscv as S
+    rng = np.random.default_rng(3)
+    for d in (1, 2, 3):
+        H = W.random_spd(rng, d)
+        assert np.allclose(S.from_theta(S.to_theta(H), d), H, rtol=1e-13, atol=1e-15)
+    a = np.array([0.5, -0.7, 1.5])
+    gen = S.nelder_mead(np.zeros(3), iters=400, tol=1e-15)
+    x = next(gen)
+    try:
+        while True:
+            x = gen.send(float(np.sum((x - a) ** 2)) + 2.0)
+    except StopIteration as stop:
+        xb, vb, evals = stop.value
+    assert np.allclose(xb, a, atol=1e-5) and abs(vb - 2.0) < 1e-9 and evals > 10
