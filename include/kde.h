@@ -178,6 +178,48 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
              const kde_params* params, double* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Learned bandwidth proposal: a perceptron 24 -> 128 -> 128 -> 128 -> 3 (ReLU)
+ * mapping summary features of a sample to Cholesky coordinates of H, trained
+ * by mean squared error against LSCV-optimal bandwidths (kde_lscv), with the
+ * plain LSCV search kept as fallback and judge. Products on the matrix cores
+ * in BF16 with FP32 accumulation; FP32 master parameters and Adam state.
+ * State (device, state_bytes, 256-byte aligned, caller-owned) holds the FP32
+ * parameters, the Adam moments and the BF16 weight copies. Parameter vector
+ * (FP32, n_params): W1 (32 x 128, rows >= 24 zero), b1 (128), W2 (128 x 128),
+ * b2, W3, b3, W4 (128 x 16, columns >= 3 zero), b4 (16, entries >= 3 zero),
+ * each W stored input-major (W[k][n] at k * n_out + n).
+ * ------------------------------------------------------------------------- */
+
+typedef struct kde_mlp_info {
+    int32_t n_in, n_hidden, n_out;
+    int32_t rows_per_group;   /* rows per workgroup */
+    int64_t n_params;
+    size_t state_bytes;
+    size_t ws_bytes;          /* workspace for a batch of `batch` rows (kde_mlp_query) */
+} kde_mlp_info;
+
+int kde_mlp_query(int64_t batch, kde_mlp_info* info);
+
+/* Load params (device, n_params FP32) into state, zero the Adam moments. */
+int kde_mlp_load(void* state, const float* params, hipStream_t stream);
+
+/* Y (device, B x 3 FP32) = network(X) for X (device, B x 24 FP32). */
+int kde_mlp_forward(const void* state, const float* X, int64_t B, float* Y, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* Gradient of the loss mean_rows sum_k (Y_k - T_k)^2 w.r.t. the parameter
+ * vector (device, n_params FP32) and the loss (device, 1 FP32; may be NULL);
+ * Y (device, B x 3) receives the outputs. T: device, B x 3 FP32. */
+int kde_mlp_grad(const void* state, const float* X, const float* T, int64_t B, float* Y, float* grad, float* loss,
+                 void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * on the batch (X, T); loss (device, 1 FP32, may be NULL) receives the batch
+ * loss before the step. */
+int kde_mlp_train_step(void* state, const float* X, const float* T, int64_t B, float lr, int32_t step, float* loss,
+                       void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Batched evaluation: many independent estimates (each its own X, n, H and
  * grid; d may differ between items) computed together. Every pass of the
  * pipeline runs as one launch for all items that share its kernel template

@@ -33,6 +33,7 @@ SOURCES = {
     "kde_fft.hip": ["-ffp-contract=off"],
     "kde_fft_batch.hip": ["-ffp-contract=off"],
     "kde_lscv.hip": ["-ffp-contract=off"],
+    "kde_mlp.hip": ["-ffp-contract=off"],
     "kde_api.cpp": [],
 }
 

@@ -1233,6 +1233,155 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     return KDE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device layouts of the network state and workspace.
+struct MlpState {
+    size_t P = 0, m = 0, v = 0, Wk = 0, Wt = 0, total = 0;
+};
+MlpState mlp_state() {
+    MlpState L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.P = take(kde::kMlpParams * sizeof(float));
+    L.m = take(kde::kMlpParams * sizeof(float));
+    L.v = take(kde::kMlpParams * sizeof(float));
+    L.Wk = take(kde::kMlpWeights * sizeof(uint16_t));
+    L.Wt = take(kde::kMlpWeights * sizeof(uint16_t));
+    L.total = off;
+    return L;
+}
+struct MlpWs {
+    size_t acts = 0, Y = 0, partial = 0, lossp = 0, grad = 0, loss = 0, total = 0;
+};
+MlpWs mlp_ws(int64_t B) {
+    MlpWs L;
+    const int64_t groups = (B + kde::kMlpRows - 1) / kde::kMlpRows;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.acts = take(static_cast<size_t>(B) * (kde::kMlpInPad + 3 * kde::kMlpHid) * sizeof(uint16_t));
+    L.Y = take(static_cast<size_t>(B) * kde::kMlpOut * sizeof(float));
+    L.partial = take(static_cast<size_t>(groups) * kde::kMlpParams * sizeof(float));
+    L.lossp = take(static_cast<size_t>(groups) * sizeof(float));
+    L.grad = take(kde::kMlpParams * sizeof(float));
+    L.loss = take(sizeof(float));
+    L.total = off;
+    return L;
+}
+kde::MlpArgs mlp_args(const void* state, int64_t B, char* ws) {
+    const MlpState S = mlp_state();
+    char* st = static_cast<char*>(const_cast<void*>(state));
+    kde::MlpArgs a{};
+    a.P = reinterpret_cast<const float*>(st + S.P);
+    a.Pw = reinterpret_cast<float*>(st + S.P);
+    a.m = reinterpret_cast<float*>(st + S.m);
+    a.v = reinterpret_cast<float*>(st + S.v);
+    a.Wk = reinterpret_cast<const uint16_t*>(st + S.Wk);
+    a.Wt = reinterpret_cast<const uint16_t*>(st + S.Wt);
+    a.Wkw = reinterpret_cast<uint16_t*>(st + S.Wk);
+    a.Wtw = reinterpret_cast<uint16_t*>(st + S.Wt);
+    a.B = B;
+    a.groups = (B + kde::kMlpRows - 1) / kde::kMlpRows;
+    if (ws) {
+        const MlpWs W = mlp_ws(B);
+        a.acts = reinterpret_cast<uint16_t*>(ws + W.acts);
+        a.partial = reinterpret_cast<float*>(ws + W.partial);
+        a.loss_partial = reinterpret_cast<float*>(ws + W.lossp);
+        a.grad = reinterpret_cast<float*>(ws + W.grad);
+        a.loss = reinterpret_cast<float*>(ws + W.loss);
+        a.Y = reinterpret_cast<float*>(ws + W.Y);
+    }
+    return a;
+}
+bool aligned(const void* p) { return reinterpret_cast<uintptr_t>(p) % kAlign == 0; }
+
+// forward with saved layer inputs, then the per-group and summed gradients
+int mlp_grad_pass(kde::MlpArgs& a, hipStream_t s) {
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpForward, a, nullptr, s));
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpBackward, a, nullptr, s));
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpReduce, a, nullptr, s));
+    return KDE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kde_mlp_query(int64_t batch, kde_mlp_info* info) {
+    if (!info || batch < 0) return KDE_ERR_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_in = kde::kMlpIn;
+    info->n_hidden = kde::kMlpHid;
+    info->n_out = kde::kMlpOut;
+    info->rows_per_group = kde::kMlpRows;
+    info->n_params = kde::kMlpParams;
+    info->state_bytes = mlp_state().total;
+    info->ws_bytes = batch > 0 ? mlp_ws(batch).total : 0;
+    return KDE_OK;
+}
+
+int kde_mlp_load(void* state, const float* params, hipStream_t stream) {
+    if (!state || !params || !aligned(state)) return KDE_ERR_ARG;
+    kde::MlpArgs a = mlp_args(state, 0, nullptr);
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpLoad, a, params, stream));
+    return KDE_OK;
+}
+
+int kde_mlp_forward(const void* state, const float* X, int64_t B, float* Y, void* ws, size_t ws_bytes,
+                    hipStream_t stream) {
+    if (!state || !X || !Y || B < 1 || !aligned(state)) return KDE_ERR_ARG;
+    (void)ws;
+    (void)ws_bytes;
+    kde::MlpArgs a = mlp_args(state, B, nullptr);
+    a.X = X;
+    a.Y = Y;
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpForward, a, nullptr, stream));
+    return KDE_OK;
+}
+
+int kde_mlp_grad(const void* state, const float* X, const float* T, int64_t B, float* Y, float* grad, float* loss,
+                 void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!state || !X || !T || !grad || B < 1 || !ws || !aligned(state) || !aligned(ws)) return KDE_ERR_ARG;
+    if (ws_bytes < mlp_ws(B).total) return KDE_ERR_WS;
+    kde::MlpArgs a = mlp_args(state, B, static_cast<char*>(ws));
+    a.X = X;
+    a.T = T;
+    if (Y) a.Y = Y;
+    a.grad = grad;
+    a.loss = loss;
+    return mlp_grad_pass(a, stream);
+}
+
+int kde_mlp_train_step(void* state, const float* X, const float* T, int64_t B, float lr, int32_t step, float* loss,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!state || !X || !T || B < 1 || step < 1 || !ws || !aligned(state) || !aligned(ws)) return KDE_ERR_ARG;
+    if (!(lr > 0.f) || !std::isfinite(lr)) return KDE_ERR_ARG;
+    if (ws_bytes < mlp_ws(B).total) return KDE_ERR_WS;
+    kde::MlpArgs a = mlp_args(state, B, static_cast<char*>(ws));
+    a.X = X;
+    a.T = T;
+    if (loss) a.loss = loss;
+    KDE_CHECK(mlp_grad_pass(a, stream));
+    a.lr = lr;
+    a.b1 = 0.9f;
+    a.b2 = 0.999f;
+    a.eps = 1e-8f;
+    a.c1 = static_cast<float>(1.0 - std::pow(0.9, step));
+    a.c2 = static_cast<float>(1.0 - std::pow(0.999, step));
+    KDE_TRY(kde::launch_mlp(kde::kMlpOpAdam, a, nullptr, stream));
+    return KDE_OK;
+}
+
 int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_params* params, kde_batch** out) {
     if (!out) return KDE_ERR_ARG;
     *out = nullptr;

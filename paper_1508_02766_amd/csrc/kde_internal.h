@@ -239,4 +239,43 @@ hipError_t launch_dot_batch(int prec, bool final_stage, const BatchMap& m, hipSt
 // out[0..2] = {LSCV, dots[0] / n, 2 (dots[1] - phi0) / (n - 1)}.
 hipError_t launch_lscv_combine(const double* dots, double n, double phi0, double* out, hipStream_t s);
 
+// Learned bandwidth proposal network (kde_mlp.hip): 32 -> 128 -> 128 -> 128 -> 16.
+constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 3, kMlpOutPad = 16, kMlpRows = 64;
+// FP32 parameter vector: W1 (k-major, 32 x 128), b1, W2, b2, W3, b3, W4 (128 x 16), b4
+constexpr int64_t kMlpW1 = 0, kMlpB1 = kMlpW1 + kMlpInPad * kMlpHid;
+constexpr int64_t kMlpW2 = kMlpB1 + kMlpHid, kMlpB2 = kMlpW2 + kMlpHid * kMlpHid;
+constexpr int64_t kMlpW3 = kMlpB2 + kMlpHid, kMlpB3 = kMlpW3 + kMlpHid * kMlpHid;
+constexpr int64_t kMlpW4 = kMlpB3 + kMlpHid, kMlpB4 = kMlpW4 + kMlpHid * kMlpOutPad;
+constexpr int64_t kMlpParams = kMlpB4 + kMlpOutPad;
+// BF16 weight copies, same offsets in the k-major (Wk[k][n]) and n-major (Wt[n][k]) arrays
+constexpr int64_t kMlpWk1 = 0, kMlpWk2 = kMlpWk1 + kMlpInPad * kMlpHid, kMlpWk3 = kMlpWk2 + kMlpHid * kMlpHid;
+constexpr int64_t kMlpWk4 = kMlpWk3 + kMlpHid * kMlpHid, kMlpWeights = kMlpWk4 + kMlpHid * kMlpOutPad;
+constexpr int64_t kMlpWt1 = kMlpWk1, kMlpWt2 = kMlpWk2, kMlpWt3 = kMlpWk3, kMlpWt4 = kMlpWk4;
+
+enum MlpOp : int { kMlpOpLoad = 0, kMlpOpForward = 1, kMlpOpBackward = 2, kMlpOpReduce = 3, kMlpOpAdam = 4 };
+
+struct MlpArgs {
+    const float* P;             // master parameters (read)
+    float* Pw;                  // the same, written by load / Adam
+    float* m;                   // Adam moments
+    float* v;
+    const uint16_t* Wk;         // BF16 weights, k-major
+    const uint16_t* Wt;         // BF16 weights, n-major
+    uint16_t* Wkw;
+    uint16_t* Wtw;
+    const float* X;             // [B][24] features
+    const float* T;             // [B][3] targets
+    float* Y;                   // [B][3] outputs
+    int64_t B;
+    int64_t groups;             // ceil(B / 64)
+    uint16_t* acts;             // layer inputs: [B][32], then 3 x [B][128] (BF16)
+    float* partial;             // [groups][kMlpParams]
+    float* loss_partial;        // [groups]
+    float* grad;                // [kMlpParams]
+    float* loss;                // [1] or null
+    float lr, b1, b2, eps, c1, c2;   // Adam; c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+hipError_t launch_mlp(int op, const MlpArgs& a, const float* params, hipStream_t s);
+
 }  // namespace kde

@@ -72,8 +72,15 @@ class KdeBatchInfo(ctypes.Structure):
                 ("tile", ctypes.c_int32 * 3), ("narrow_mask", ctypes.c_int32)]
 
 
+class KdeMlpInfo(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("rows_per_group", ctypes.c_int32), ("n_params", ctypes.c_int64), ("state_bytes", ctypes.c_size_t),
+                ("ws_bytes", ctypes.c_size_t)]
+
+
 _lib = None
-EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_batch_create",
+EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_mlp_query", "kde_mlp_load", "kde_mlp_forward",
+           "kde_mlp_grad", "kde_mlp_train_step", "kde_batch_create",
            "kde_batch_query", "kde_batch_bind", "kde_batch_eval", "kde_batch_tune", "kde_batch_destroy",
            "kde_strerror")
 
@@ -98,6 +105,11 @@ def lib() -> ctypes.CDLL:
         L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
         L.kde_lscv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
+        L.kde_mlp_query.argtypes = [i64, ctypes.POINTER(KdeMlpInfo)]
+        L.kde_mlp_load.argtypes = [vp, vp, vp]
+        L.kde_mlp_forward.argtypes = [vp, vp, i64, vp, vp, sz, vp]
+        L.kde_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
+        L.kde_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, ctypes.c_int32, vp, vp, sz, vp]
         L.kde_batch_create.argtypes = [ctypes.POINTER(KdeBatchItem), ctypes.c_int32, Pp, ctypes.POINTER(vp)]
         L.kde_batch_query.argtypes = [vp, ctypes.POINTER(KdeBatchInfo)]
         L.kde_batch_bind.argtypes = [vp, vp, sz, vp]
@@ -491,3 +503,66 @@ class KdeBatch:
             self.close()
         except Exception:
             pass
+
+
+def mlp_query(batch: int = 0) -> dict:
+    inf = KdeMlpInfo()
+    _check(lib().kde_mlp_query(int(batch), ctypes.byref(inf)), "kde_mlp_query")
+    return {"n_in": inf.n_in, "n_hidden": inf.n_hidden, "n_out": inf.n_out, "rows_per_group": inf.rows_per_group,
+            "n_params": inf.n_params, "state_bytes": inf.state_bytes, "ws_bytes": inf.ws_bytes}
+
+
+class MlpNet:
+    """The learned-bandwidth network (kde_mlp_*): device state allocated with torch."""
+
+    def __init__(self, params, device="cuda:0"):
+        info = mlp_query()
+        self.n_params = info["n_params"]
+        self.device = device
+        self.state = torch.empty(info["state_bytes"], dtype=torch.uint8, device=device)
+        self._ws = torch.empty(1, dtype=torch.uint8, device=device)
+        self.load(params)
+
+    def load(self, params):
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32), device=self.device).contiguous()
+        if p.numel() != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters")
+        _check(lib().kde_mlp_load(_ptr(self.state), _ptr(p), _stream(self.device)), "kde_mlp_load")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def params(self) -> np.ndarray:
+        return self.state[: self.n_params * 4].view(torch.float32).cpu().numpy().astype(np.float64)
+
+    def _ws_for(self, B):
+        need = mlp_query(B)["ws_bytes"]
+        if self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def forward(self, X: torch.Tensor, Y=None) -> torch.Tensor:
+        _need_cuda(X, torch.float32, "X")
+        B = X.shape[0]
+        if Y is None:
+            Y = torch.empty(B, 3, dtype=torch.float32, device=self.device)
+        _check(lib().kde_mlp_forward(_ptr(self.state), _ptr(X), B, _ptr(Y), None, 0, _stream(self.device)),
+               "kde_mlp_forward")
+        return Y
+
+    def grad(self, X: torch.Tensor, T: torch.Tensor):
+        _need_cuda(X, torch.float32, "X")
+        _need_cuda(T, torch.float32, "T")
+        B = X.shape[0]
+        ws = self._ws_for(B)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        Y = torch.empty(B, 3, dtype=torch.float32, device=self.device)
+        _check(lib().kde_mlp_grad(_ptr(self.state), _ptr(X), _ptr(T), B, _ptr(Y), _ptr(g), _ptr(loss), _ptr(ws),
+                                  ws.numel(), _stream(self.device)), "kde_mlp_grad")
+        return g, loss, Y
+
+    def train_step(self, X: torch.Tensor, T: torch.Tensor, lr: float, step: int, loss=None):
+        B = X.shape[0]
+        ws = self._ws_for(B)
+        _check(lib().kde_mlp_train_step(_ptr(self.state), _ptr(X), _ptr(T), B, float(lr), int(step), _ptr(loss),
+                                        _ptr(ws), ws.numel(), _stream(self.device)), "kde_mlp_train_step")
+        return loss
