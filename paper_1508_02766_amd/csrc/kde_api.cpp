@@ -901,15 +901,18 @@ int plan_item(const kde_batch& b, const kde_batch_item& it, const int tile[3], P
 }
 
 // Binning tile shapes the autotuner tries, the first being the one in use at
-// creation: the caller's shape alone if params set one or the items differ in
-// d; otherwise the default and the alternatives for that d.
+// creation: the caller's shape alone if params set one, the items differ in d
+// or none of them bins; otherwise the default and the alternatives for that d.
 std::vector<std::array<int, 3>> tile_candidates(const kde_batch& b) {
     std::vector<std::array<int, 3>> c;
     const bool fixed = b.has_prm && (b.prm.tile[0] || b.prm.tile[1] || b.prm.tile[2]);
     int d = b.items[0].grid.d;
-    for (const auto& it : b.items)
+    bool bins = false;
+    for (const auto& it : b.items) {
         if (it.grid.d != d) d = 0;
-    if (fixed || d == 0) {
+        bins = bins || !it.counts;
+    }
+    if (fixed || d == 0 || !bins) {   // caller's shape, mixed d, or nothing to bin
         c.push_back({b.has_prm ? b.prm.tile[0] : 0, b.has_prm ? b.prm.tile[1] : 0, b.has_prm ? b.prm.tile[2] : 0});
         return c;
     }

@@ -96,6 +96,16 @@ def _phi0(H, n, grid, opts) -> float:
     return K.kde_plan_query(H, n, grid, **{k: v for k, v in opts.items() if k in K._PLAN_OPTS})["norm"] * n
 
 
+def project(H, grid, min_bins: float = 1.0, margin: float = 1.01) -> np.ndarray:
+    """The nearest H (same eigenvectors) whose eigenvalues respect the search domain's floor."""
+    g = K._grid(grid)
+    dmax = max((g.hi[k] - g.lo[k]) / (g.M[k] - 1) for k in range(g.d))
+    lam, V = np.linalg.eigh(np.asarray(H, dtype=np.float64))
+    lam = np.maximum(lam, margin * (min_bins * dmax) ** 2)
+    Hp = (V * lam) @ V.T
+    return 0.5 * (Hp + Hp.T)
+
+
 def _admissible(H, n, grid, opts, min_bins: float = 1.0) -> bool:
     g = K._grid(grid)
     dmax = max((g.hi[k] - g.lo[k]) / (g.M[k] - 1) for k in range(g.d))
