@@ -173,6 +173,39 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         plain()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same step captured once in a HIP graph and replayed K times (no host launch
+    # cost inside the timed region)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        K.prepare_eval(X, w.H, grid, out, ws, nd, prec=prec)()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        K.prepare_eval(X, w.H, grid, out, ws, nd, prec=prec)()
+    for _ in range(3):
+        graph.replay()
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    del graph
+    # cold steps: a 512 MiB write before each step evicts the last-level cache, so the
+    # step reads its inputs from HBM; each step is bracketed by events on the stream
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    cold = []
+    for _ in range(10):
+        flush.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plain()
+        e1.record()
+        e1.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    del flush
     # traced region: the same K steps with an event after every kernel; tracing
     # keeps all kernels on one stream so each interval times one kernel
     events = [[hip.event() for _ in range(cap)] for _ in range(steps)]
@@ -209,6 +242,7 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     return {
         "workload": name, "prec": prec, "n": w.n, "M": list(w.M), "L": list(plan["L"]), "P": list(plan["P"]),
         "ms_per_step": ms_step, "ms_per_step_traced": (u1 - u0) * 1e3 / steps, "gpu_ms_per_step_traced": gpu_step_ms,
+        "ms_per_step_cold": float(np.median(cold)), "ms_per_step_graph": (g1 - g0) * 1e3 / steps,
         "samples_per_s": w.n / (ms_step * 1e-3), "grid_pts_per_s": cells / (ms_step * 1e-3),
         "conv_us": round(conv_us, 3), "conv_grid_pts_per_s": cells / (conv_us * 1e-6),
         "bin_us": round(bin_us, 3), "bin_samples_per_s": w.n / (bin_us * 1e-6), "kernels": kern,
@@ -347,7 +381,9 @@ def main():
             if (name, prec) == (a.workload, a.prec) or f"{name}_{prec}" not in chosen:
                 continue
             v = measure(K, W, hip, name, prec, max(20, a.steps // 4), 5)
-            variants[f"{name}_{prec}"] = {k: v[k] for k in ("ms_per_step", "ms_per_step_traced", "samples_per_s",
+            variants[f"{name}_{prec}"] = {k: v[k] for k in ("ms_per_step", "ms_per_step_traced", "ms_per_step_cold",
+                                                            "ms_per_step_graph",
+                                                            "samples_per_s",
                                                             "grid_pts_per_s", "conv_us", "conv_grid_pts_per_s",
                                                             "bin_us", "bin_samples_per_s", "kernels")}
         if a.batch > 0 and "batch" in chosen:
@@ -379,6 +415,8 @@ def main():
         "conv_grid_pts_per_s": round(main_run["conv_grid_pts_per_s"], 1),
         "bin_samples_per_s": round(main_run["bin_samples_per_s"], 1),
         "ms_per_step_traced": round(main_run["ms_per_step_traced"], 5),
+        "ms_per_step_cold": round(main_run["ms_per_step_cold"], 5),
+        "ms_per_step_graph": round(main_run["ms_per_step_graph"], 5),
         "gpu_ms_per_step_traced": round(main_run["gpu_ms_per_step_traced"], 5),
         "kernels": kern, "roofline": roof, "cpu_baseline": cpu, "variants": variants,
     }

@@ -80,6 +80,11 @@ typedef struct kde_params {
                                  axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 16;
                                  the product must stay <= 4096. Changes speed and workspace
                                  size, never the counts */
+    int32_t extent;           /* lag-box half widths: 0 (default) Eq. (15), tau sqrt(lambda_max)
+                                 on every axis; 1: tau sqrt(H_kk) on axis k, the half width of
+                                 the ellipsoid u' H^-1 u <= tau^2 along that axis (a tighter
+                                 box around the same ellipsoid; every lag left out lies outside
+                                 it, as with Eq. (15)). Both capped at M_k - 1 */
     int32_t trace_capacity;   /* optional per-kernel timing, see below */
     hipEvent_t* trace_events; /* if non-NULL: events[0] is recorded before the first kernel
                                  and events[i] after the i-th kernel, on `stream`, up to
@@ -94,7 +99,8 @@ typedef struct kde_plan {
     int32_t d;
     int32_t Q;                /* fixed-point bits; counts are in units of 2^-(d Q) */
     int32_t prec;
-    int32_t L[3];             /* truncation per axis, Eq. (15) or the override */
+    int32_t L[3];             /* truncation per axis: Eq. (15), the marginal extent, or the
+                                 override */
     int32_t P[3];             /* padded FFT length per axis: smallest power of two
                                  >= max(16, M_k + L_k) */
     int32_t reserved;

@@ -144,10 +144,16 @@ def lambda_max(H) -> float:
     return float(np.linalg.eigvalsh(np.asarray(H, dtype=np.float64))[-1])
 
 
-def truncation_L(H, delta, M, tau: float = TAU_DEFAULT):
-    """L_k = min(M_k - 1, ceil(tau sqrt(|lambda|) / delta_k)), Eq. (15)."""
+def truncation_L(H, delta, M, tau: float = TAU_DEFAULT, extent: str = "eigen"):
+    """L_k = min(M_k - 1, ceil(tau sqrt(|lambda|) / delta_k)), Eq. (15).
+
+    extent = "marginal": tau sqrt(H_kk) instead of tau sqrt(|lambda|), the
+    half width along axis k of the ellipsoid u' H^-1 u <= tau^2.
+    """
+    H = np.asarray(H, dtype=np.float64)
     lam = lambda_max(H)
-    return tuple(int(min(int(M[k]) - 1, math.ceil(tau * math.sqrt(abs(lam)) / float(delta[k]))))
+    half = [math.sqrt(H[k, k]) if extent == "marginal" else math.sqrt(abs(lam)) for k in range(len(M))]
+    return tuple(int(min(int(M[k]) - 1, math.ceil(tau * half[k] / float(delta[k]))))
                  for k in range(len(M)))
 
 
@@ -314,7 +320,7 @@ def bkde_double_sum(c, H, lo, hi, n: int) -> np.ndarray:
 # the whole path
 # --------------------------------------------------------------------------
 
-def plan(H, lo, hi, M, n, tau: float = TAU_DEFAULT, L=None, Q=None):
+def plan(H, lo, hi, M, n, tau: float = TAU_DEFAULT, L=None, Q=None, extent: str = "eigen"):
     """Grid spacing, truncation and fixed-point scale for one problem."""
     H = check_bandwidth(H)
     d = H.shape[0]
@@ -327,14 +333,15 @@ def plan(H, lo, hi, M, n, tau: float = TAU_DEFAULT, L=None, Q=None):
         raise ValueError("need hi_k > lo_k")
     delta = bin_width(lo, hi, M)
     if L is None:
-        L = truncation_L(H, delta, M, tau)
+        L = truncation_L(H, delta, M, tau, extent)
     L = tuple(int(x) for x in L)
     if Q is None:
         Q = default_Q(d)
     return {"d": d, "M": M, "delta": delta, "L": L, "Q": Q, "n": int(n)}
 
 
-def kde_binned(X, H, lo, hi, M, tau: float = TAU_DEFAULT, L=None, Q=None, method: str = "direct"):
+def kde_binned(X, H, lo, hi, M, tau: float = TAU_DEFAULT, L=None, Q=None, method: str = "direct",
+               extent: str = "eigen"):
     """Binned estimate on the grid: linear binning, weights on the lag box, Eq. (7).
 
     Returns (density, info) where info carries counts, n_dropped, L, delta.
@@ -343,7 +350,7 @@ def kde_binned(X, H, lo, hi, M, tau: float = TAU_DEFAULT, L=None, Q=None, method
     n = X.shape[0]
     if n == 0:
         raise ValueError("the estimate needs n >= 1 (Eq. 1 divides by n)")
-    p = plan(H, lo, hi, M, n, tau=tau, L=L, Q=Q)
+    p = plan(H, lo, hi, M, n, tau=tau, L=L, Q=Q, extent=extent)
     counts, n_dropped = bin_fixed(X, lo, hi, p["M"], p["Q"])
     c = counts_to_c(counts, p["d"], p["Q"])
     k = lag_weights(H, p["delta"], p["L"], n)

@@ -6,6 +6,7 @@
 //   H = R R' (Cholesky), |H| = prod R_kk^2, H^-1 = R^-T R^-1  (K_H of Eq. 1)
 //   lambda_max(H): closed form for d <= 2, cyclic Jacobi for d = 3
 //   L_k = min(M_k - 1, ceil(tau sqrt(lambda_max) / delta_k))  Eq. (15)
+//         (or tau sqrt(H_kk) with kde_params.extent = 1)
 //   P_k = smallest power of two >= max(16, M_k + L_k)          zero padding, Section 4.1
 //   k_0 = n^-1 (2 pi)^-d/2 |H|^-1/2                            Eq. (6) with Eq. (1)
 //
@@ -145,6 +146,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     double tau = kTauDefault;
     int prec = KDE_F32, Q = 32 / d;
     int Lovr[3] = {0, 0, 0}, tile[3] = {0, 0, 0};
+    int extent = 0;
     if (prm) {
         if (std::isnan(prm->tau) || std::isinf(prm->tau)) return KDE_ERR_ARG;
         if (prm->tau > 0.0) tau = prm->tau;
@@ -168,6 +170,8 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
             tcells *= T > 0 ? T : 1;
         }
         if (tcells > kde::kMaxTileCells) return KDE_ERR_ARG;
+        if (prm->extent != 0 && prm->extent != 1) return KDE_ERR_ARG;
+        extent = prm->extent;
         if (prm->trace_events && prm->trace_capacity < 0) return KDE_ERR_ARG;
     }
     p.prec = prec;
@@ -275,7 +279,9 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     for (int k = 0; k < d; ++k) {
         int L = Lovr[k];
         if (L == 0) {
-            const double x = std::ceil(tau * std::sqrt(std::fabs(lam)) / p.delta[k]);
+            // Eq. (15), or the axis-k half width of the ellipsoid u' H^-1 u <= tau^2
+            const double half = extent == 1 ? std::sqrt(Hs[k][k]) : std::sqrt(std::fabs(lam));
+            const double x = std::ceil(tau * half / p.delta[k]);
             const double cap = static_cast<double>(g->M[k] - 1);
             L = static_cast<int>(x < cap ? x : cap);
         }

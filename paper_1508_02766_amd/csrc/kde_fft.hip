@@ -68,20 +68,26 @@ __global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_
 // single-instance entry points of the passes
 // ---------------------------------------------------------------------------
 
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
-    rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(a, blockIdx.x);
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW>
+__global__ __launch_bounds__((RowShape<P, NARROW>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
+    rows_r2c_body<R, P, IN_KIND, OUT_REAL, D, NARROW>(a, blockIdx.x);
 }
 
-template <typename R, int P, bool MULT>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_kernel(C2RArgs<R> a) {
-    rows_c2r_body<R, P, MULT>(a, blockIdx.x);
+template <typename R, int P, bool MULT, bool NARROW>
+__global__ __launch_bounds__((RowShape<P, NARROW>::THREADS)) void rows_c2r_kernel(C2RArgs<R> a) {
+    rows_c2r_body<R, P, MULT, NARROW>(a, blockIdx.x);
 }
 
+// The (x, y) workgroup grid is walked in XCD-major order (xcd_major).
 template <typename R, int P, int MODE, bool NARROW>
 __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
-    cols_body<R, P, MODE, NARROW>(a, blockIdx.x, blockIdx.y);
+    const uint32_t G = gridDim.x * gridDim.y;
+    const uint32_t b = xcd_major(blockIdx.y * gridDim.x + blockIdx.x, G);
+    cols_body<R, P, MODE, NARROW>(a, b % gridDim.x, b / gridDim.x);
 }
+
+// Row launches with fewer than this many workgroups use the narrow shape.
+constexpr int64_t kRowNarrowBelow = 256;
 
 // ---------------------------------------------------------------------------
 // launch helpers
@@ -100,30 +106,45 @@ hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* la
     return hipGetLastError();
 }
 
+template <typename R, int P, bool NARROW>
+hipError_t rows_r2c_launch_b(int kind, int d, const RowArgs<R>& a, hipStream_t s) {
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
+    const dim3 blk(RowShape<P, NARROW>::THREADS);
+    if (kind == kRowCountsU64)
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false, 1, NARROW>), g, blk, 0, s, a);
+    else if (d == 1)
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1, NARROW>), g, blk, 0, s, a);
+    else if (d == 2)
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2, NARROW>), g, blk, 0, s, a);
+    else
+        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3, NARROW>), g, blk, 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename R, int P>
 hipError_t rows_r2c_launch(int kind, int d, const void* args, hipStream_t s) {
     const RowArgs<R>& a = *static_cast<const RowArgs<R>*>(args);
-    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B))), blk(RowShape<P>::THREADS);
-    if (kind == kRowCountsU64)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, a);
-    else if (d == 1)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, a);
-    else if (d == 2)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, a);
+    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B) < kRowNarrowBelow)
+        return rows_r2c_launch_b<R, P, true>(kind, d, a, s);
+    return rows_r2c_launch_b<R, P, false>(kind, d, a, s);
+}
+
+template <typename R, int P, bool NARROW>
+hipError_t rows_c2r_launch_b(const C2RArgs<R>& a, hipStream_t s) {
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
+    const dim3 blk(RowShape<P, NARROW>::THREADS);
+    if (a.mult)
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true, NARROW>), g, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, a);
+        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false, NARROW>), g, blk, 0, s, a);
     return hipGetLastError();
 }
 
 template <typename R, int P>
 hipError_t rows_c2r_launch(const void* args, hipStream_t s) {
     const C2RArgs<R>& a = *static_cast<const C2RArgs<R>*>(args);
-    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B))), blk(RowShape<P>::THREADS);
-    if (a.mult)
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true>), g, blk, 0, s, a);
-    else
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false>), g, blk, 0, s, a);
-    return hipGetLastError();
+    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B) < kRowNarrowBelow) return rows_c2r_launch_b<R, P, true>(a, s);
+    return rows_c2r_launch_b<R, P, false>(a, s);
 }
 
 template <typename R, int P, bool NARROW>

@@ -22,12 +22,14 @@ __global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_batch(BatchMa
     rows_c2r_body<R, P, MULT>(static_cast<const C2RArgs<R>*>(m.tab)[i], blockIdx.x - m.start[i]);
 }
 
-// An instance's workgroups cover its ceil(W / B) x outer tile grid, x fastest.
+// An instance's workgroups cover its ceil(W / B) x outer tile grid, x fastest;
+// the launch is walked in XCD-major order (xcd_major).
 template <typename R, int P, int MODE, bool NARROW>
 __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_batch(BatchMap m) {
-    const int i = static_cast<int>(m.owner[blockIdx.x]);
+    const uint32_t bid = xcd_major(blockIdx.x, gridDim.x);
+    const int i = static_cast<int>(m.owner[bid]);
     const ColArgs& a = static_cast<const ColArgs*>(m.tab)[i];
-    const uint32_t l = blockIdx.x - m.start[i];
+    const uint32_t l = bid - m.start[i];
     const uint32_t nbx = static_cast<uint32_t>(ceil_div(a.W, ColShape<R, P, NARROW>::B));
     cols_body<R, P, MODE, NARROW>(a, l % nbx, l / nbx);
 }

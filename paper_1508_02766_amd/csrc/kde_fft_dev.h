@@ -333,12 +333,24 @@ __device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
 // rows_r2c: real rows along the contiguous axis -> half spectra (P/2 + 1 bins)
 // ---------------------------------------------------------------------------
 
-template <int P>
+// B line pairs per workgroup: 128 threads, or half that (NARROW) for launches
+// that would otherwise leave CUs idle.
+template <int P, bool NARROW = false>
 struct RowShape {
     static constexpr int T = P / 16;
-    static constexpr int B = (128 / T) >= 1 ? 128 / T : 1;   // lines (row pairs) per workgroup
+    static constexpr int kWide = (128 / T) >= 1 ? 128 / T : 1;
+    static constexpr int B = NARROW ? (kWide >= 2 ? kWide / 2 : 1) : kWide;
     static constexpr int THREADS = T * B;
 };
+
+// Workgroup b of a launch of G workgroups, renumbered so that consecutive
+// numbers run on the same XCD: the hardware deals workgroups to the 8 XCDs
+// round robin, so neighbours that share 128-byte segments would otherwise
+// fetch them into eight different L2 caches.
+__device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t G) {
+    const uint32_t x = b & 7u, slot = b >> 3, q = G >> 3, r = G & 7u;
+    return x * q + (x < r ? x : r) + slot;
+}
 
 template <typename R, int D>
 __device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2) {
@@ -361,10 +373,10 @@ __device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, 
     }
 }
 
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW = false>
 __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
+    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
     __shared__ C lds[B * LINE];
     const void* __restrict__ in_ = gw.in;
     void* __restrict__ out_ = gw.out;
@@ -441,10 +453,10 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
 // rows_c2r: half spectra -> real rows, scaled, window [0, mout)
 // ---------------------------------------------------------------------------
 
-template <typename R, int P, bool MULT>
+template <typename R, int P, bool MULT, bool NARROW = false>
 __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P>::T, B = RowShape<P>::B, LINE = LineShape<P>::LDS;
+    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
     __shared__ C lds[B * LINE];
     const C* __restrict__ in = static_cast<const C*>(a.in);
     const R* __restrict__ mult = static_cast<const R*>(a.mult);

@@ -275,3 +275,16 @@ def test_search_helpers_on_host():
     except StopIteration as stop:
         xb, vb, evals = stop.value
     assert np.allclose(xb, a, atol=1e-5) and abs(vb - 2.0) < 1e-9 and evals > 10
+
+
+def test_plan_marginal_extent_matches_oracle():
+    rng = np.random.default_rng(78)
+    for d in (1, 2, 3):
+        H = W.random_spd(rng, d, ratio=(1.0, 20.0))
+        M = (70, 50, 40)[:d]
+        lo, hi = -np.ones(d) * 3, np.ones(d) * 3
+        p = K.kde_plan_query(H, 1000, (lo, hi, M), extent="marginal")
+        ref = O.truncation_L(H, O.bin_width(lo, hi, M), M, extent="marginal")
+        assert tuple(p["L"]) == ref
+    with pytest.raises(K.KdeError):
+        K.kde_plan_query(np.eye(2), 10, ((-1, -1), (1, 1), (8, 8)), extent=2)

@@ -205,6 +205,19 @@ def test_eval_small_diagonal_and_full_differ():
     assert _rel(full, diag) > 0.05
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("d,M", [(2, (80, 60)), (3, (20, 24, 18)), (1, (300,))])
+def test_eval_marginal_extent(prec, d, M):
+    """The tighter per-axis lag box (extent = marginal) against the oracle with the same box."""
+    w = W.small_mixture(200 + d, d, 20_000, M, ratio=(1.0, 20.0))
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, extent="marginal")
+    plan = K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M), extent="marginal")
+    assert tuple(plan["L"]) == tuple(info["L"])
+    got, _ = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec, extent="marginal")
+    torch.cuda.synchronize()
+    assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
 @pytest.fixture(scope="module")
 def ref2d512():
     w = W.mix2d_512()

@@ -431,3 +431,21 @@ def test_planted_mistakes_are_caught():
 
     for bad in (b_floor, b_round_half_up):
         assert not _binning_ok(bad), bad.__name__
+
+
+def test_marginal_extent_is_the_ellipsoid_bounding_box():
+    """tau sqrt(H_kk) is the largest |u_k| on the ellipsoid u' H^-1 u = tau^2 (found here by
+    dense sampling of its boundary), and it never exceeds the Eq. (15) half width."""
+    rng = np.random.default_rng(77)
+    for d in (2, 3):
+        H = W.random_spd(rng, d, ratio=(1.0, 20.0))
+        tau = 3.7
+        V = rng.normal(size=(200_000, d))
+        V /= np.linalg.norm(V, axis=1, keepdims=True)
+        U = tau * V @ np.linalg.cholesky(H).T          # u' H^-1 u = tau^2 for every row
+        box = np.max(np.abs(U), axis=0)
+        assert np.allclose(box, tau * np.sqrt(np.diag(H)), rtol=2e-3)
+        delta = np.full(d, 0.05)
+        Le = O.truncation_L(H, delta, (1000,) * d, tau)
+        Lm = O.truncation_L(H, delta, (1000,) * d, tau, extent="marginal")
+        assert all(m <= e for m, e in zip(Lm, Le)) and any(m < e for m, e in zip(Lm, Le))
