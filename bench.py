@@ -122,7 +122,6 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> int:
     common = {
         "zero_counts": cells * 8, "zero_dropped": 8, "bin": n * d * 8 + cells * 8, "kfill": lag * rs,
         "bin_hist": n * d * 8, "bin_scan": 0, "bin_scatter": n * d * 8 + n * 8, "bin_accum": n * 8 + cells * 8,
-        "bin_reduce": 0,
     }
     if name in common:
         return common[name]

@@ -47,7 +47,7 @@ struct Layout {
 
 struct BinLayout {
     // offsets into the binning workspace (tiled path)
-    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, records = 0, partial = 0, total = 0;
+    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, records = 0, total = 0;
 };
 
 struct Plan {
@@ -118,7 +118,6 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
     bl->drops = take(static_cast<size_t>(g.nchunk) * 4);
     bl->tile_start = take(static_cast<size_t>(g.ntiles) * 4);
     bl->records = take(static_cast<size_t>(g.max_records) * 8);
-    bl->partial = take(static_cast<size_t>(g.max_segments) * g.tile_cells * 8);
     bl->total = off;
     *tg = g;
     return true;
@@ -459,7 +458,6 @@ kde::BinArgs bin_args(const Plan& pl, const kde::BinConsts& c, const double* X, 
     a.w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
     a.w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
     a.w.records = reinterpret_cast<uint64_t*>(ws + b.records);
-    a.w.partial = reinterpret_cast<uint64_t*>(ws + b.partial);
     a.counts = counts;
     a.n_dropped = reinterpret_cast<unsigned long long*>(n_dropped);
     return a;
@@ -492,9 +490,9 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
     int64_t cells = 1;
     for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
     if (pl.tiled && n > 0) {
-        static const char* names[5] = {"bin_hist", "bin_scan", "bin_scatter", "bin_accum", "bin_reduce"};
+        static const char* names[4] = {"bin_hist", "bin_scan", "bin_scatter", "bin_accum"};
         const kde::BinArgs a = bin_args(pl, c, X, n, counts, n_dropped, ws);
-        for (int st = kde::kBinHist; st <= kde::kBinReduce; ++st) {
+        for (int st = kde::kBinHist; st <= kde::kBinAccum; ++st) {
             Pass p;
             p.kind = kPassBin;
             p.sub = st;

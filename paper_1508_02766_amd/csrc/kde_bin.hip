@@ -13,19 +13,19 @@
 //
 // * tiled (default): a counting sort of packed (sample, tile) records into
 //   per-tile buckets, then one workgroup per segment of a bucket sums its
-//   records in LDS and stores whole tiles with plain writes. Five launches:
+//   records in LDS. Four launches:
 //     hist     per-chunk histogram of records per tile (LDS atomics)
-//     scan     per-tile exclusive scan over chunks (one wavefront per tile)
+//     scan     per-tile exclusive scan over chunks (one wavefront per tile);
+//              zeroes the counts of tiles with more than one segment
 //     scatter  block scan of the tile totals, packed records into buckets
 //     accum    LDS sum of one segment (<= S records) of one tile; a tile with
-//              one segment is stored directly, others as partial sub-grids
-//     reduce   sum of the partial sub-grids of tiles with several segments
-//   The accumulate and reduce workgroups rebuild the segment -> tile map from
-//   the tile totals in LDS, so no pass ends waiting on one workgroup's
-//   bookkeeping.
+//              one segment is stored with plain writes, the segments of
+//              other tiles are added to the counts with 64-bit integer
+//              atomics (one per nonzero cell and segment; exact in any order)
+//   The accumulate workgroups rebuild the segment -> tile map from the tile
+//   totals in LDS, so no pass ends waiting on one workgroup's bookkeeping.
 //   A sample whose corners straddle a tile edge gets one record per tile it
-//   touches, so every cell is owned by exactly one tile and no global atomic
-//   is needed anywhere.
+//   touches, so every cell belongs to exactly one tile.
 // * atomic (fallback when a record does not fit in 64 bits or the grid needs
 //   more tiles than one workgroup can histogram): zero fill, then 2^d global
 //   64-bit atomic adds per sample.
@@ -189,9 +189,44 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
     if (tid == 0) drops[blk] = nd;
 }
 
+template <int D>
+__device__ __forceinline__ void tile_frame(const BinConsts& c, const TileGeom& g, uint32_t tile, int64_t (&org)[D],
+                                           int (&ext)[D]) {
+    uint32_t rem = tile;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+        const uint32_t ta = rem % static_cast<uint32_t>(g.nt[a]);
+        rem /= static_cast<uint32_t>(g.nt[a]);
+        org[a] = static_cast<int64_t>(ta) << g.logT[a];
+        const int64_t left = c.M[a] - org[a];
+        ext[a] = left < g.T[a] ? static_cast<int>(left) : g.T[a];
+    }
+}
+
+// Counts index of tile-local cell i (row-major over T), or -1 outside the grid.
+template <int D>
+__device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const TileGeom& g, const int64_t (&org)[D],
+                                                   const int (&ext)[D], int i) {
+    int64_t idx = 0;
+    bool inside = true;
+    int rem = i;
+#pragma unroll
+    for (int a = D - 1; a >= 0; --a) {
+        const int ca = rem & (g.T[a] - 1);
+        rem >>= g.logT[a];
+        inside = inside && ca < ext[a];
+        idx += (org[a] + ca) * c.stride[a];
+    }
+    return inside ? idx : -1;
+}
+
 // One wavefront per tile: exclusive scan of hist[., tile] over the chunks,
-// tot[tile] = the tile's record count. Block 0 also totals the dropped samples.
+// tot[tile] = the tile's record count; the counts of a tile with more than one
+// segment are zeroed for the accumulation. Block 0 also totals the dropped
+// samples.
+template <int D>
 __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
+    const BinConsts& c = a.c;
     const TileGeom& g = a.g;
     uint32_t* __restrict__ hist = a.w.hist;
     uint32_t* __restrict__ tot = a.w.tot;
@@ -219,6 +254,16 @@ __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
             run += v;
         }
         if (lane == 63) tot[tile] = x;
+        // a tile with several segments is summed into the counts with atomics: zero it here
+        if (__shfl(x, 63, 64) > static_cast<uint32_t>(g.S)) {
+            int64_t org[D];
+            int ext[D];
+            tile_frame<D>(c, g, static_cast<uint32_t>(tile), org, ext);
+            for (int i = lane; i < g.tile_cells; i += 64) {
+                const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
+                if (idx >= 0) a.counts[idx] = 0;
+            }
+        }
     }
     if (blk == 0 && n_dropped) {
         __shared__ unsigned long long acc;
@@ -266,39 +311,10 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
     }
 }
 
-template <int D>
-__device__ __forceinline__ void tile_frame(const BinConsts& c, const TileGeom& g, uint32_t tile, int64_t (&org)[D],
-                                           int (&ext)[D]) {
-    uint32_t rem = tile;
-#pragma unroll
-    for (int a = D - 1; a >= 0; --a) {
-        const uint32_t ta = rem % static_cast<uint32_t>(g.nt[a]);
-        rem /= static_cast<uint32_t>(g.nt[a]);
-        org[a] = static_cast<int64_t>(ta) << g.logT[a];
-        const int64_t left = c.M[a] - org[a];
-        ext[a] = left < g.T[a] ? static_cast<int>(left) : g.T[a];
-    }
-}
-
-// Counts index of tile-local cell i (row-major over T), or -1 outside the grid.
-template <int D>
-__device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const TileGeom& g, const int64_t (&org)[D],
-                                                   const int (&ext)[D], int i) {
-    int64_t idx = 0;
-    bool inside = true;
-    int rem = i;
-#pragma unroll
-    for (int a = D - 1; a >= 0; --a) {
-        const int ca = rem & (g.T[a] - 1);
-        rem >>= g.logT[a];
-        inside = inside && ca < ext[a];
-        idx += (org[a] + ca) * c.stride[a];
-    }
-    return inside ? idx : -1;
-}
-
 // One workgroup per segment (<= S records of one tile): sum the records'
-// corner weights in LDS, then store the tile (sole segment) or its partial.
+// corner weights in LDS, then store the tile (sole segment) or add the
+// segment's sums to the zeroed counts with 64-bit integer atomics (exact, in
+// any order).
 template <int D>
 __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const BinConsts& c = a.c;
@@ -383,76 +399,16 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
             if (idx >= 0) counts[idx] = grid[i];
         }
     } else {
-        uint64_t* part = w.partial + static_cast<int64_t>(s) * g.tile_cells;
-        for (int i = tid; i < g.tile_cells; i += kBinThreads) part[i] = grid[i];
-    }
-}
-
-// Tiles with several segments: sum their partial sub-grids into the counts
-// (the kernel boundary orders these reads after every partial store). Each
-// workgroup rebuilds the segment prefix and the list of shared tiles from the
-// tile totals, then takes work items (shared tile, block of 64 cells); its 4
-// wavefronts sum interleaved segments of the same 64 cells and combine
-// through LDS.
-template <int D>
-__device__ __forceinline__ void bin_reduce_body(const BinArgs& a, uint32_t blk, uint32_t nblk) {
-    const BinConsts& c = a.c;
-    const TileGeom& g = a.g;
-    const BinWork& w = a.w;
-    uint64_t* __restrict__ counts = a.counts;
-    extern __shared__ uint32_t reduce_lds[];
-    uint32_t* seg_base = reduce_lds;                     // [ntiles]
-    uint32_t* rank = reduce_lds + g.ntiles;              // [ntiles]
-    uint32_t* shared_list = reduce_lds + 2 * g.ntiles;   // [ntiles]
-    __shared__ uint32_t wave_sums[kBinThreads / 64];
-    __shared__ uint64_t part_sum[kBinThreads];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int t = tid; t < g.ntiles; t += kBinThreads) {
-        const uint32_t cnt = w.tot[t];
-        seg_base[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
-        rank[t] = cnt > static_cast<uint32_t>(g.S) ? 1u : 0u;
-    }
-    __syncthreads();
-    block_exclusive_scan(seg_base, g.ntiles, wave_sums);
-    const uint32_t nshared = block_exclusive_scan(rank, g.ntiles, wave_sums);
-    for (int t = tid; t < g.ntiles; t += kBinThreads)
-        if (w.tot[t] > static_cast<uint32_t>(g.S)) shared_list[rank[t]] = static_cast<uint32_t>(t);
-    __syncthreads();
-    const int blocks_per_tile = (g.tile_cells + 63) / 64;
-    const uint32_t items = nshared * static_cast<uint32_t>(blocks_per_tile);
-    for (uint32_t it = blk; it < items; it += nblk) {
-        const uint32_t tile = shared_list[it / blocks_per_tile];
-        const int i = static_cast<int>(it % blocks_per_tile) * 64 + lane;
-        const uint32_t cnt = w.tot[tile];
-        const uint32_t sb = seg_base[tile], nseg = (cnt + g.S - 1) / g.S;
-        const uint64_t* base = w.partial + static_cast<int64_t>(sb) * g.tile_cells;
-        uint64_t acc[4] = {0, 0, 0, 0};
-        if (i < g.tile_cells) {
-            uint32_t k = wave;
-            for (; k + 12 < nseg; k += 16) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] += base[static_cast<int64_t>(k + 4 * u) * g.tile_cells + i];
-            }
-            for (; k < nseg; k += 4) acc[0] += base[static_cast<int64_t>(k) * g.tile_cells + i];
-        }
-        part_sum[tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        __syncthreads();
-        if (wave == 0 && i < g.tile_cells) {
-            int64_t org[D];
-            int ext[D];
-            tile_frame<D>(c, g, tile, org, ext);
+        auto* cnt = reinterpret_cast<unsigned long long*>(counts);
+        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
-            if (idx >= 0)
-                counts[idx] = (part_sum[lane] + part_sum[64 + lane]) + (part_sum[128 + lane] + part_sum[192 + lane]);
+            if (idx >= 0 && grid[i]) atomicAdd(cnt + idx, grid[i]);
         }
-        __syncthreads();
     }
 }
 
-// Single-instance and batched entry points of the five stages (see BatchMap
+// Single-instance and batched entry points of the four stages (see BatchMap
 // for how a batched launch assigns workgroups to instances).
-constexpr uint32_t kReduceBlocks = 1024;        // persistent reduce grid (single instance)
-constexpr uint32_t kReduceBlocksBatch = 64;     // at most this many per instance of a batch
 
 #define KDE_BATCH_PROLOGUE                                              \
     const auto* tab = static_cast<const BinArgs*>(m.tab);               \
@@ -467,10 +423,12 @@ __global__ __launch_bounds__(kBinThreads) void bin_hist_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
     bin_hist_body<D>(a, blk);
 }
-__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(BinArgs a) { bin_scan_body(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(BinArgs a) { bin_scan_body<D>(a, blockIdx.x); }
+template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_scan_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
-    bin_scan_body(a, blk);
+    bin_scan_body<D>(a, blk);
 }
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
@@ -486,16 +444,6 @@ __global__ __launch_bounds__(kBinThreads) void bin_accum_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
     bin_accum_body<D>(a, blk);
 }
-template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_reduce_kernel(BinArgs a) {
-    bin_reduce_body<D>(a, blockIdx.x, gridDim.x);
-}
-template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_reduce_batch(BatchMap m) {
-    KDE_BATCH_PROLOGUE
-    bin_reduce_body<D>(a, blk, m.start[inst + 1] - m.start[inst]);
-}
-
 #undef KDE_BATCH_PROLOGUE
 
 // ---------------------------------------------------------------------------
@@ -571,8 +519,7 @@ int64_t bin_stage_extent(int stage, const TileGeom& g) {
         case kBinHist:
         case kBinScatter: return g.nchunk;
         case kBinScan: return (g.ntiles + kBinThreads / 64 - 1) / (kBinThreads / 64);
-        case kBinAccum: return g.max_segments;
-        default: return kReduceBlocks;
+        default: return g.max_segments;
     }
 }
 
@@ -582,10 +529,9 @@ hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
     const size_t lds = bin_stage_lds(stage, a.g);
     switch (stage) {
         case kBinHist: hipLaunchKernelGGL((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
-        case kBinScan: hipLaunchKernelGGL(bin_scan_kernel, grid, blk, 0, s, a); break;
+        case kBinScan: hipLaunchKernelGGL((bin_scan_kernel<D>), grid, blk, 0, s, a); break;
         case kBinScatter: hipLaunchKernelGGL((bin_scatter_kernel<D>), grid, blk, lds, s, a); break;
         case kBinAccum: hipLaunchKernelGGL((bin_accum_kernel<D>), grid, blk, lds, s, a); break;
-        case kBinReduce: hipLaunchKernelGGL((bin_reduce_kernel<D>), grid, blk, lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -596,10 +542,9 @@ hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream
     const dim3 blk(kBinThreads), grid(m.blocks);
     switch (stage) {
         case kBinHist: hipLaunchKernelGGL((bin_hist_batch<D>), grid, blk, lds, s, m); break;
-        case kBinScan: hipLaunchKernelGGL(bin_scan_batch, grid, blk, 0, s, m); break;
+        case kBinScan: hipLaunchKernelGGL((bin_scan_batch<D>), grid, blk, 0, s, m); break;
         case kBinScatter: hipLaunchKernelGGL((bin_scatter_batch<D>), grid, blk, lds, s, m); break;
         case kBinAccum: hipLaunchKernelGGL((bin_accum_batch<D>), grid, blk, lds, s, m); break;
-        case kBinReduce: hipLaunchKernelGGL((bin_reduce_batch<D>), grid, blk, lds, s, m); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -612,22 +557,12 @@ size_t bin_stage_lds(int stage, const TileGeom& g) {
         case kBinHist:
         case kBinScatter: return static_cast<size_t>(g.ntiles) * 4;
         case kBinAccum: return static_cast<size_t>(g.tile_cells) * 8 + static_cast<size_t>(g.ntiles) * 4;
-        case kBinReduce: return static_cast<size_t>(g.ntiles) * 12;
         default: return 0;
     }
 }
 
-// The reduce stage gets one workgroup per 8 possible shared segments of the
-// instance (at least 1, at most kReduceBlocksBatch); the other stages their
-// single-instance extent.
-int64_t bin_stage_batch_blocks(int stage, const TileGeom& g) {
-    if (stage != kBinReduce) return bin_stage_extent(stage, g);
-    const int64_t segs = g.max_records / g.S;
-    int64_t b = (segs + 7) / 8;
-    if (b < 1) b = 1;
-    if (b > kReduceBlocksBatch) b = kReduceBlocksBatch;
-    return b;
-}
+// A batched launch gives every instance its single-instance extent.
+int64_t bin_stage_batch_blocks(int stage, const TileGeom& g) { return bin_stage_extent(stage, g); }
 
 hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s) {
     if (a.c.d == 1) return bin_stage_d<1>(stage, a, s);

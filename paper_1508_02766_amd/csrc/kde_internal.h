@@ -24,8 +24,9 @@ struct BinConsts {
 // Tiled binning: the grid is cut into tiles of T_1 x ... x T_d cells; every
 // (sample, tile) pair the sample's 2^d corners touch becomes one packed 64-bit
 // record (tile-local lower corner + 1 and the d fixed-point fractions q), the
-// records are bucketed by tile with a counting sort, and each tile is summed
-// in LDS and stored with plain writes.
+// records are bucketed by tile with a counting sort, and each segment of a
+// tile is summed in LDS, then stored (a tile's only segment) or added to the
+// counts with integer atomics (tiles with several segments).
 constexpr int kBinThreads = 256;
 constexpr int kBinChunk = kBinThreads * 16;   // samples per histogram / scatter workgroup
 constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
@@ -43,7 +44,7 @@ struct TileGeom {
     int S;                  // records per accumulation segment
     int64_t nchunk;         // ceil(n / kBinChunk)
     int64_t max_records;    // n 2^d
-    int64_t max_segments;   // ntiles + ceil(max_records / S)
+    int64_t max_segments;   // ntiles + ceil(max_records / S): accumulation workgroups
 };
 
 struct BinWork {
@@ -52,7 +53,6 @@ struct BinWork {
     uint32_t* drops;        // [nchunk] dropped samples per chunk
     uint32_t* tile_start;   // [ntiles] first record of each tile
     uint64_t* records;      // [max_records]
-    uint64_t* partial;      // [max_segments][tile_cells] sums of segments of shared tiles
 };
 
 // Everything one instance of the tiled binning reads and writes.
@@ -66,7 +66,7 @@ struct BinArgs {
     unsigned long long* n_dropped;   // may be null
 };
 
-enum BinStage : int { kBinHist = 0, kBinScan = 1, kBinScatter = 2, kBinAccum = 3, kBinReduce = 4 };
+enum BinStage : int { kBinHist = 0, kBinScan = 1, kBinScatter = 2, kBinAccum = 3 };
 
 // One stage of the tiled binning for one instance; bin_stage_lds is the
 // dynamic LDS a stage needs for the geometry g.

@@ -47,9 +47,9 @@ def test_batch_matches_single_bit_identical(prec):
     _assert_matches_single(B, items, prec=prec)
     info = B.info()
     sides = {w.M[0] for w in wl}
-    # five binning stages, then one launch per padded length for each of the
+    # four binning stages, then one launch per padded length for each of the
     # four FFT passes
-    assert info["launches"] == 5 + 4 * len(sides)
+    assert info["launches"] == 4 + 4 * len(sides)
 
 
 def test_batch_matches_oracle():
@@ -158,7 +158,7 @@ def test_batch_trace_names_groups():
     B.eval()
     torch.cuda.synchronize()
     t = B.trace()
-    assert t["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "bin_reduce", "counts_r2c",
+    assert t["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "counts_r2c",
                           "kspec_r2c", "conv_col", "c2r"]
     _assert_matches_single(B, items, prec="f32")
     for e in evs:

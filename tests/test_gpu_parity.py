@@ -105,11 +105,14 @@ def test_bin_atomic_fallback_bit_exact(d, M, Q):
     assert np.array_equal(got, ref)
 
 
-def test_bin_heavy_tile_segments():
-    """All samples in one tile: thousands of records in one bucket, summed by many segments."""
+@pytest.mark.parametrize("d,M,center", [(2, (512, 512), 0.0), (2, (100, 70), 0.97), (3, (40, 50, 37), 0.95),
+                                         (1, (5000,), 0.99)])
+def test_bin_heavy_tile_segments(d, M, center):
+    """Most samples in one tile (also a ragged tile at the far edge of the grid): thousands of
+    records in one bucket, summed by many segments into the zeroed counts with atomics."""
     rng = np.random.default_rng(5)
-    X = rng.normal(0.0, 0.05, size=(300_000, 2))
-    lo, hi, M = np.array([-1.0, -1.0]), np.array([1.0, 1.0]), (512, 512)
+    X = rng.normal(center, 0.02, size=(300_000, d))
+    lo, hi = -np.ones(d), np.ones(d)
     ref, rnd = O.bin_fixed(X, lo, hi, M)
     got, gnd = _counts(X, lo, hi, M)
     assert gnd == rnd
@@ -321,7 +324,7 @@ def test_trace_events_record_every_kernel():
     K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), trace_events=evs, trace=tr)
     torch.cuda.synchronize()
     assert tr["count"] == len(tr["names"]) + 1
-    assert tr["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "bin_reduce", "counts_r2c",
+    assert tr["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "counts_r2c",
                            "kspec_r2c", "conv_col", "c2r"]
     for i in range(1, tr["count"]):
         ms = ctypes.c_float()
