@@ -184,8 +184,8 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
     }
     if (dropped) atomicAdd(&nd, dropped);
     __syncthreads();
-    uint32_t* row = hist + static_cast<int64_t>(blk) * g.ntiles;
-    for (int t = tid; t < g.ntiles; t += kBinThreads) row[t] = h[t];
+    // tile-major: the scan reads each tile's chunk counts contiguously
+    for (int t = tid; t < g.ntiles; t += kBinThreads) hist[static_cast<int64_t>(t) * g.nchunk + blk] = h[t];
     if (tid == 0) drops[blk] = nd;
 }
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const Til
     return inside ? idx : -1;
 }
 
-// One wavefront per tile: exclusive scan of hist[., tile] over the chunks,
+// One wavefront per tile: exclusive scan of hist[tile][.] over the chunks,
 // tot[tile] = the tile's record count; the counts of a tile with more than one
 // segment are zeroed for the accumulation. Block 0 also totals the dropped
 // samples.
@@ -240,7 +240,8 @@ __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
         const int64_t c0 = lane * per < nch ? lane * per : nch;
         const int64_t c1 = c0 + per < nch ? c0 + per : nch;
         uint32_t s = 0;
-        for (int64_t ch = c0; ch < c1; ++ch) s += hist[ch * g.ntiles + tile];
+        uint32_t* __restrict__ row = hist + static_cast<int64_t>(tile) * nch;
+        for (int64_t ch = c0; ch < c1; ++ch) s += row[ch];
         uint32_t x = s;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -249,8 +250,8 @@ __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
         }
         uint32_t run = x - s;
         for (int64_t ch = c0; ch < c1; ++ch) {
-            const uint32_t v = hist[ch * g.ntiles + tile];
-            hist[ch * g.ntiles + tile] = run;
+            const uint32_t v = row[ch];
+            row[ch] = run;
             run += v;
         }
         if (lane == 63) tot[tile] = x;
@@ -284,7 +285,7 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
-    extern __shared__ uint32_t cur[];   // [ntiles]
+    extern __shared__ uint32_t cur[];   // [ntiles], and [ntiles] more in workgroup 0
     __shared__ uint32_t wave_sums[kBinThreads / 64];
     const int tid = threadIdx.x;
     double x[kPer][D];
@@ -293,10 +294,25 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
     for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] = w.tot[t];
     __syncthreads();
     block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
-    if (blk == 0)
-        for (int t = tid; t < g.ntiles; t += kBinThreads) w.tile_start[t] = cur[t];
-    const uint32_t* off = w.hist + static_cast<int64_t>(blk) * g.ntiles;
-    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += off[t];
+    if (blk == 0) {
+        // the accumulation's work list: tile t owns segments [seg_first[t], seg_first[t] + max(1,
+        // ceil(tot / S))), and seg_tile maps each segment back to its tile (all ones past the end)
+        uint32_t* first = cur + g.ntiles;
+        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+            w.tile_start[t] = cur[t];
+            const uint32_t cnt = w.tot[t];
+            first[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+        }
+        __syncthreads();
+        const uint32_t nsegs = block_exclusive_scan(first, g.ntiles, wave_sums);
+        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+            w.seg_first[t] = first[t];
+            const uint32_t e = t + 1 < g.ntiles ? first[t + 1] : nsegs;
+            for (uint32_t q = first[t]; q < e; ++q) w.seg_tile[q] = static_cast<uint32_t>(t);
+        }
+        for (int64_t q = nsegs + tid; q < g.max_segments; q += kBinThreads) w.seg_tile[q] = 0xFFFFFFFFu;
+    }
+    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -321,28 +337,11 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
     uint64_t* __restrict__ counts = a.counts;
-    extern __shared__ unsigned long long accum_lds[];
-    unsigned long long* grid = accum_lds;                                            // [tile_cells]
-    uint32_t* seg_base = reinterpret_cast<uint32_t*>(accum_lds + g.tile_cells);      // [ntiles]
-    __shared__ uint32_t wave_sums[kBinThreads / 64];
-    __shared__ uint32_t found;
+    extern __shared__ unsigned long long grid[];   // [tile_cells]
     const int tid = threadIdx.x;
-    const uint32_t s = blk;
-    // segment -> tile: prefix of the per-tile segment counts max(1, ceil(tot / S))
-    for (int t = tid; t < g.ntiles; t += kBinThreads) {
-        const uint32_t cnt = w.tot[t];
-        seg_base[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
-    }
-    __syncthreads();
-    const uint32_t nsegs = block_exclusive_scan(seg_base, g.ntiles, wave_sums);
-    if (s >= nsegs) return;
-    for (int t = tid; t < g.ntiles; t += kBinThreads) {
-        const uint32_t e = t + 1 < g.ntiles ? seg_base[t + 1] : nsegs;
-        if (seg_base[t] <= s && s < e) found = static_cast<uint32_t>(t);
-    }
-    __syncthreads();
-    const uint32_t tile = found;
-    const uint32_t k = s - seg_base[tile];
+    const uint32_t tile = w.seg_tile[blk];          // work list written by the scatter pass
+    if (tile == 0xFFFFFFFFu) return;
+    const uint32_t k = blk - w.seg_first[tile];
     const uint32_t tcount = w.tot[tile];
     const uint32_t r0 = w.tile_start[tile] + k * static_cast<uint32_t>(g.S);
     const uint32_t tend = w.tile_start[tile] + tcount;
@@ -554,9 +553,9 @@ hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream
 
 size_t bin_stage_lds(int stage, const TileGeom& g) {
     switch (stage) {
-        case kBinHist:
-        case kBinScatter: return static_cast<size_t>(g.ntiles) * 4;
-        case kBinAccum: return static_cast<size_t>(g.tile_cells) * 8 + static_cast<size_t>(g.ntiles) * 4;
+        case kBinHist: return static_cast<size_t>(g.ntiles) * 4;
+        case kBinScatter: return static_cast<size_t>(g.ntiles) * 8;
+        case kBinAccum: return static_cast<size_t>(g.tile_cells) * 8;
         default: return 0;
     }
 }

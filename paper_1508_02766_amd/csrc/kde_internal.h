@@ -28,7 +28,7 @@ struct BinConsts {
 // tile is summed in LDS, then stored (a tile's only segment) or added to the
 // counts with integer atomics (tiles with several segments).
 constexpr int kBinThreads = 256;
-constexpr int kBinChunk = kBinThreads * 16;   // samples per histogram / scatter workgroup
+constexpr int kBinChunk = kBinThreads * 8;    // samples per histogram / scatter workgroup
 constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
 constexpr int kMaxTileCells = 4096;
 constexpr int kSegment = 4096;                // records per accumulation segment
@@ -48,11 +48,13 @@ struct TileGeom {
 };
 
 struct BinWork {
-    uint32_t* hist;         // [nchunk][ntiles] counts, then exclusive offsets over chunks
+    uint32_t* hist;         // [ntiles][nchunk] counts, then exclusive offsets over chunks
     uint32_t* tot;          // [ntiles] records per tile
     uint32_t* drops;        // [nchunk] dropped samples per chunk
     uint32_t* tile_start;   // [ntiles] first record of each tile
     uint64_t* records;      // [max_records]
+    uint32_t* seg_first;    // [ntiles] first accumulation segment of each tile
+    uint32_t* seg_tile;     // [max_segments] tile of each segment (all ones: none)
 };
 
 // Everything one instance of the tiled binning reads and writes.

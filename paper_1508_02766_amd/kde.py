@@ -27,7 +27,8 @@ import os
 import numpy as np
 import torch
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
+# KDE_LIBRARY may name another build of the same library (same ABI), e.g. for a tuning sweep.
+_LIB_PATH = os.environ.get("KDE_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
 
 KDE_F32, KDE_F64 = 1, 2
 _PREC = {"f32": KDE_F32, "f64": KDE_F64, KDE_F32: KDE_F32, KDE_F64: KDE_F64, None: KDE_F32}
