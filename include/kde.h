@@ -85,6 +85,11 @@ typedef struct kde_params {
                                  the ellipsoid u' H^-1 u <= tau^2 along that axis (a tighter
                                  box around the same ellipsoid; every lag left out lies outside
                                  it, as with Eq. (15)). Both capped at M_k - 1 */
+    int32_t reuse_spectrum;   /* kde_conv / kde_eval only. 1: the workspace already holds the
+                                 kernel spectrum written by an earlier call of the same entry
+                                 point with the same H, n, grid and options; it is not
+                                 recomputed. The caller guarantees the match; the result is
+                                 then identical to a full call */
     int32_t trace_capacity;   /* optional per-kernel timing, see below */
     hipEvent_t* trace_events; /* if non-NULL: events[0] is recorded before the first kernel
                                  and events[i] after the i-th kernel, on `stream`, up to

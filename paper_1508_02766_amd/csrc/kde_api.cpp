@@ -172,6 +172,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         }
         if (tcells > kde::kMaxTileCells) return KDE_ERR_ARG;
         if (prm->extent != 0 && prm->extent != 1) return KDE_ERR_ARG;
+        if (prm->reuse_spectrum != 0 && prm->reuse_spectrum != 1) return KDE_ERR_ARG;
         extent = prm->extent;
         if (prm->trace_events && prm->trace_capacity < 0) return KDE_ERR_ARG;
     }
@@ -1137,13 +1138,14 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
     if (ws_bytes < pl.pub.conv_ws_bytes) return KDE_ERR_WS;
     char* conv_ws = static_cast<char*>(ws);
+    const bool reuse = params && params->reuse_spectrum;
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
     const int r = run_phases(
         stream, tr,
         [&](hipStream_t s) {
             Direct e(s, tr);
-            return run_kspec(pl, conv_ws, -1, e);
+            return reuse ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
         },
         [&](hipStream_t s) {
             Direct e(s, tr);
@@ -1168,13 +1170,14 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     auto* counts = static_cast<uint64_t*>(ws);
     char* bin_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
     char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
+    const bool reuse = params && params->reuse_spectrum;
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
     const int r = run_phases(
         stream, tr,
         [&](hipStream_t s) {
             Direct e(s, tr);
-            return run_kspec(pl, conv_ws, -1, e);
+            return reuse ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
         },
         [&](hipStream_t s) {
             Direct e(s, tr);

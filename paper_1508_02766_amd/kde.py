@@ -16,7 +16,8 @@ The names and semantics follow include/kde.h:
 ``grid`` is ``(lo, hi, M)`` (per-axis sequences) or a ``KdeGrid``. Options:
 ``prec`` ("f32" default, or "f64"), ``tau``, ``L`` (per-axis override),
 ``Q`` (fixed-point bits), ``tile`` (binning tile per axis), ``extent`` ("eigen" = Eq. 15,
-"marginal" = tau sqrt(H_kk) per axis), ``trace_events`` (list of raw hipEvent_t handles
+"marginal" = tau sqrt(H_kk) per axis), ``reuse_spectrum`` (the workspace holds the kernel spectrum
+of an earlier call with the same H, n, grid and options), ``trace_events`` (list of raw hipEvent_t handles
 as ints) with ``trace`` (a dict that receives ``count`` and ``names``).
 """
 from __future__ import annotations
@@ -48,7 +49,7 @@ class KdeGrid(ctypes.Structure):
 
 class KdeParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * 3), ("Q", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("extent", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("extent", ctypes.c_int32), ("reuse_spectrum", ctypes.c_int32),
                 ("trace_capacity", ctypes.c_int32),
                 ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
                 ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
@@ -159,8 +160,11 @@ def _grid_shape(g: KdeGrid):
     return tuple(int(g.M[k]) for k in range(g.d))
 
 
-def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, trace_events=None, trace=None):
+def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, reuse_spectrum=None, trace_events=None,
+            trace=None):
     p = KdeParams()
+    if reuse_spectrum:
+        p.reuse_spectrum = 1
     if extent is not None:
         p.extent = {"eigen": 0, "marginal": 1}.get(extent, extent)
     if tile is not None:

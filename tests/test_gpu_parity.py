@@ -221,6 +221,28 @@ def test_eval_marginal_extent(prec, d, M):
     assert _rel(got.cpu().numpy(), f) <= TOL[prec]
 
 
+@pytest.mark.parametrize("name,M", [("2d", 256), ("3d", 48), ("1d", 1000)])
+def test_reused_spectrum_matches_full_call(name, M):
+    """A second estimate with the same H, n and grid reuses the spectrum left in the workspace:
+    bit-identical to a full call on the same samples."""
+    if name == "2d":
+        w1, w2 = W.mix2d_512(n=100_000, M=M), W.mix2d_512(n=100_000, M=M, seed_offset=3)
+    elif name == "3d":
+        w1, w2 = W.mix3d_128(n=100_000, M=M), W.mix3d_128(n=100_000, M=M, seed_offset=3)
+    else:
+        w1 = W.small_mixture(31, 1, 50_000, M)
+        w2 = W.small_mixture(32, 1, 50_000, M)
+    g = (w1.lo, w1.hi, w1.M)
+    plan = K.kde_plan_query(w1.H, w1.n, g)
+    ws = torch.empty(plan["eval_ws_bytes"], dtype=torch.uint8, device=DEV)
+    K.kde_eval(_dev(w1.X), w1.H, g, ws=ws)
+    X2 = _dev(w2.X)
+    reused = K.kde_eval(X2, w1.H, g, ws=ws, reuse_spectrum=True)[0]
+    full = K.kde_eval(X2, w1.H, g)[0]
+    torch.cuda.synchronize()
+    assert torch.equal(reused, full)
+
+
 @pytest.fixture(scope="module")
 def ref2d512():
     w = W.mix2d_512()
