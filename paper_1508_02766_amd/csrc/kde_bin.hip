@@ -15,7 +15,7 @@
 //   per-tile buckets, then one workgroup per segment of a bucket sums its
 //   records in LDS. Four launches:
 //     hist     per-chunk histogram of records per tile (LDS atomics)
-//     scan     per-tile exclusive scan over chunks (one wavefront per tile);
+//     scan     per-tile exclusive scan over chunks (one workgroup per tile);
 //              zeroes the counts of tiles with more than one segment
 //     scatter  block scan of the tile totals, packed records into buckets
 //     accum    LDS sum of one segment (<= S records) of one tile; a tile with
@@ -220,59 +220,65 @@ __device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const Til
     return inside ? idx : -1;
 }
 
-// One wavefront per tile: exclusive scan of hist[tile][.] over the chunks,
-// tot[tile] = the tile's record count; the counts of a tile with more than one
-// segment are zeroed for the accumulation. Block 0 also totals the dropped
-// samples.
+// One workgroup per tile: exclusive scan of hist[tile][.] over the chunks
+// (each thread a contiguous run of chunks, then a workgroup scan of the run
+// sums), tot[tile] = the tile's record count; the counts of a tile with more
+// than one segment are zeroed for the accumulation. Workgroup 0 also totals
+// the dropped samples.
 template <int D>
 __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
-    uint32_t* __restrict__ hist = a.w.hist;
-    uint32_t* __restrict__ tot = a.w.tot;
     const uint32_t* __restrict__ drops = a.w.drops;
     unsigned long long* __restrict__ n_dropped = a.n_dropped;
+    __shared__ uint32_t wave_sums[kBinThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile = static_cast<int>(blk) * (kBinThreads / 64) + wave;
+    const int tile = static_cast<int>(blk);
     const int64_t nch = g.nchunk;
-    if (tile < g.ntiles) {
-        const int64_t per = (nch + 63) / 64;
-        const int64_t c0 = lane * per < nch ? lane * per : nch;
-        const int64_t c1 = c0 + per < nch ? c0 + per : nch;
-        uint32_t s = 0;
-        uint32_t* __restrict__ row = hist + static_cast<int64_t>(tile) * nch;
-        for (int64_t ch = c0; ch < c1; ++ch) s += row[ch];
-        uint32_t x = s;
+    const int64_t per = (nch + kBinThreads - 1) / kBinThreads;
+    const int64_t c0 = tid * per < nch ? tid * per : nch;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    uint32_t* __restrict__ row = a.w.hist + static_cast<int64_t>(tile) * nch;
+    uint32_t s = 0;
+    for (int64_t ch = c0; ch < c1; ++ch) s += row[ch];
+    uint32_t x = s;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        uint32_t run = x - s;
-        for (int64_t ch = c0; ch < c1; ++ch) {
-            const uint32_t v = row[ch];
-            row[ch] = run;
-            run += v;
-        }
-        if (lane == 63) tot[tile] = x;
-        // a tile with several segments is summed into the counts with atomics: zero it here
-        if (__shfl(x, 63, 64) > static_cast<uint32_t>(g.S)) {
-            int64_t org[D];
-            int ext[D];
-            tile_frame<D>(c, g, static_cast<uint32_t>(tile), org, ext);
-            for (int i = lane; i < g.tile_cells; i += 64) {
-                const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
-                if (idx >= 0) a.counts[idx] = 0;
-            }
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sums[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBinThreads / 64; ++w) {
+        if (w < wave) before += wave_sums[w];
+        total += wave_sums[w];
+    }
+    uint32_t run = before + x - s;
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const uint32_t v = row[ch];
+        row[ch] = run;
+        run += v;
+    }
+    if (tid == 0) a.w.tot[tile] = total;
+    // a tile with several segments is summed into the counts with atomics: zero it here
+    if (total > static_cast<uint32_t>(g.S)) {
+        int64_t org[D];
+        int ext[D];
+        tile_frame<D>(c, g, static_cast<uint32_t>(tile), org, ext);
+        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
+            const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
+            if (idx >= 0) a.counts[idx] = 0;
         }
     }
     if (blk == 0 && n_dropped) {
         __shared__ unsigned long long acc;
         if (tid == 0) acc = 0;
         __syncthreads();
-        unsigned long long s = 0;
-        for (int64_t ch = tid; ch < nch; ch += kBinThreads) s += drops[ch];
-        if (s) atomicAdd(&acc, s);
+        unsigned long long d = 0;
+        for (int64_t ch = tid; ch < nch; ch += kBinThreads) d += drops[ch];
+        if (d) atomicAdd(&acc, d);
         __syncthreads();
         if (tid == 0) n_dropped[0] = acc;
     }
@@ -517,7 +523,7 @@ int64_t bin_stage_extent(int stage, const TileGeom& g) {
     switch (stage) {
         case kBinHist:
         case kBinScatter: return g.nchunk;
-        case kBinScan: return (g.ntiles + kBinThreads / 64 - 1) / (kBinThreads / 64);
+        case kBinScan: return g.ntiles;
         default: return g.max_segments;
     }
 }
