@@ -130,10 +130,10 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> int:
     if name in common:
         return common[name]
     if d == 1:
-        table = {"kspec_r2c": Hl * rs, "counts_r2c": cells * 8 + Hl * cs,
+        table = {"kspec_r2c": Hl * rs, "hist_kspec": n * d * 8 + Hl * rs, "counts_r2c": cells * 8 + Hl * cs,
                  "product_c2r": Hl * cs + Hl * rs + cells * rs}
     elif d == 2:
-        table = {"kspec_r2c": nb[0] * Hl * cs,
+        table = {"kspec_r2c": nb[0] * Hl * cs, "hist_kspec": n * d * 8 + nb[0] * Hl * cs,
                  "counts_r2c": cells * 8 + M[0] * Hl * cs,
                  "conv_col": 2 * M[0] * Hl * cs + nb[0] * Hl * cs,
                  "c2r": M[0] * Hl * cs + cells * rs}

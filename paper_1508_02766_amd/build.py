@@ -28,6 +28,7 @@ COMMON = [
 # per-source extra flags: binning must not fuse or approximate its FP64 arithmetic
 SOURCES = {
     "kde_bin.hip": ["-ffp-contract=off", "-fno-fast-math"],
+    "kde_fused.hip": ["-ffp-contract=off", "-fno-fast-math"],
     # FFT kernels: explicit fused multiply-adds only, so that every kernel built
     # from the same device code rounds identically
     "kde_fft.hip": ["-ffp-contract=off"],

@@ -370,7 +370,7 @@ struct Tracer {
 // produced; the batched path collects them and launches all passes with the
 // same kernel together.
 enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols, kPassDotPartial,
-                      kPassDotFinal };
+                      kPassDotFinal, kPassScanKspec };
 
 struct Pass {
     PassKind kind;
@@ -381,7 +381,7 @@ struct Pass {
     int64_t blocks = 0;                    // workgroups in a batched launch
     size_t lds = 0;                        // dynamic LDS (binning stages)
     size_t size = 0;                       // bytes of args
-    alignas(16) unsigned char args[384];
+    alignas(16) unsigned char args[512];
     // kPassZero / kPassBinAtomic
     uint64_t* zptr = nullptr;
     int64_t zcount = 0;
@@ -412,6 +412,7 @@ int exec_pass(const Pass& p, hipStream_t s) {
         case kPassCols:
             e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
             break;
+        case kPassScanKspec: e = kde::launch_scan_kspec(p.prec, p.P, p.d, p.args, s); break;
         case kPassDotPartial:
         case kPassDotFinal:
             // the single-problem path runs both stages through launch_dot
@@ -487,10 +488,12 @@ kde::BinConsts bin_consts(const Plan& pl, const kde_grid* g) {
     return c;
 }
 
-// Binning (Section 2, first step): the five tiled stages, or zero fill and
-// global atomics where the tiled path does not apply.
+// Binning (Section 2, first step): the four tiled stages, or zero fill and
+// global atomics where the tiled path does not apply. With `spec` (the
+// kernel-spectrum row pass of a 1-D or 2-D problem) the histogram stage and
+// that pass share one launch.
 int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
-            char* ws, Emit& emit) {
+            char* ws, Emit& emit, const Pass* spec = nullptr) {
     const kde::BinConsts c = bin_consts(pl, g);
     int64_t cells = 1;
     for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
@@ -498,6 +501,28 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
         static const char* names[4] = {"bin_hist", "bin_scan", "bin_scatter", "bin_accum"};
         const kde::BinArgs a = bin_args(pl, c, X, n, counts, n_dropped, ws);
         for (int st = kde::kBinHist; st <= kde::kBinAccum; ++st) {
+            if (st == kde::kBinHist && spec) {
+                Pass f;
+                f.kind = kPassScanKspec;
+                f.prec = spec->prec;
+                f.P = spec->P;
+                f.d = pl.pub.d;
+                f.order = st;
+                f.name = "hist_kspec";
+                if (spec->prec == KDE_F64) {
+                    kde::ScanSpecArgs<double> sa{};
+                    sa.bin = a;
+                    std::memcpy(&sa.row, spec->args, sizeof(sa.row));
+                    f.set_args(sa);
+                } else {
+                    kde::ScanSpecArgs<float> sa{};
+                    sa.bin = a;
+                    std::memcpy(&sa.row, spec->args, sizeof(sa.row));
+                    f.set_args(sa);
+                }
+                KDE_CHECK(emit(f));
+                continue;
+            }
             Pass p;
             p.kind = kPassBin;
             p.sub = st;
@@ -1175,17 +1200,24 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     char* bin_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
     char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
     const bool reuse = params && params->reuse_spectrum;
+    // 1-D / 2-D with tiled binning: the spectrum's row pass rides in the histogram launch
+    std::vector<Pass> spec;
+    if (pl.pub.d <= 2 && pl.tiled && !reuse) {
+        Collect c(spec);
+        KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
+        if (spec.size() != 1 || spec[0].kind != kPassRowR2C) spec.clear();
+    }
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
     const int r = run_phases(
         stream, tr, pl.pub.d == 3,
         [&](hipStream_t s) {
             Direct e(s, tr);
-            return reuse ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
+            return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
         },
         [&](hipStream_t s) {
             Direct e(s, tr);
-            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e));
+            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0]));
             return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
         },
         [&](hipStream_t s) {

@@ -373,10 +373,12 @@ __device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, 
     }
 }
 
-template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW = false>
+// BW > 0 overrides the number of line pairs per workgroup (the caller launches
+// P/16 * BW threads).
+template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW = false, int BW = 0>
 __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
+    constexpr int T = RowShape<P, NARROW>::T, B = BW > 0 ? BW : RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
     __shared__ C lds[B * LINE];
     const void* __restrict__ in_ = gw.in;
     void* __restrict__ out_ = gw.out;

@@ -1,0 +1,68 @@
+// The binning histogram and the kernel-spectrum row pass in one launch.
+//
+// For 1-D and 2-D problems the spectrum's row pass is independent of the
+// binning and too small to fill the GPU on its own, and a separate launch (or
+// a second stream) costs more than its work. Here it shares the launch of the
+// histogram pass: the first workgroups run the row transforms of the lag box
+// (Eq. 6 weights computed in place; first, so that they start at once and end
+// under the histogram's longer run), the others the per-chunk histograms of
+// the tiled binning, with the same device code as the separate passes. Built like the binning sources (no floating-point
+// contraction, no fast-math); the FFT code writes its fused multiply-adds
+// explicitly, so it rounds as in its own launch.
+
+#include "kde_bin_dev.h"
+#include "kde_fft_dev.h"
+
+namespace kde {
+namespace {
+
+template <int P>
+constexpr int scan_spec_pairs() { return kBinThreads / (P / 16); }   // line pairs per workgroup
+
+template <int D, typename R, int P>
+__global__ __launch_bounds__(kBinThreads) void scan_kspec_kernel(ScanSpecArgs<R> a) {
+    const uint32_t ns = static_cast<uint32_t>(ceil_div(ceil_div(a.row.nrows, 2), scan_spec_pairs<P>()));
+    if (blockIdx.x < ns) {
+        rows_r2c_body<R, P, kRowGaussCirc, D == 1, D, false, scan_spec_pairs<P>()>(a.row, blockIdx.x);
+        return;
+    }
+    bin_hist_body<D>(a.bin, blockIdx.x - ns);
+}
+
+template <typename R, int P>
+hipError_t scan_kspec_launch(int d, const void* args, hipStream_t s) {
+    const ScanSpecArgs<R>& a = *static_cast<const ScanSpecArgs<R>*>(args);
+    const dim3 g(static_cast<unsigned>(a.bin.g.nchunk + ceil_div(ceil_div(a.row.nrows, 2), scan_spec_pairs<P>())));
+    const dim3 blk(kBinThreads);
+    const size_t lds = bin_stage_lds(kBinHist, a.bin.g);   // the histogram's dynamic LDS
+    if (d == 1)
+        hipLaunchKernelGGL((scan_kspec_kernel<1, R, P>), g, blk, lds, s, a);
+    else
+        hipLaunchKernelGGL((scan_kspec_kernel<2, R, P>), g, blk, lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t scan_kspec_any(int P, int d, const void* args, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return scan_kspec_launch<R, PP>(d, args, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
+    return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / 16));
+}
+
+hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s) {
+    if (d != 1 && d != 2) return hipErrorInvalidValue;
+    if (prec == 2) return scan_kspec_any<double>(P, d, args, s);
+    return scan_kspec_any<float>(P, d, args, s);
+}
+
+}  // namespace kde

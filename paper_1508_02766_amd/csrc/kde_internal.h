@@ -179,6 +179,16 @@ C2RArgs<R> make_c2r_args(const void* in, int64_t nrows, int64_t in_ld, const voi
     return a;
 }
 
+// The binning histogram and the kernel-spectrum row pass in one launch
+// (d <= 2): the first workgroups transform lag-box rows, the rest histogram.
+template <typename R>
+struct ScanSpecArgs {
+    BinArgs bin;
+    RowArgs<R> row;
+};
+hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s);
+int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows);
+
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s);
 hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* counts,
