@@ -141,7 +141,9 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> int:
         M0, M1 = M[0], M[1]
         P1 = P[1]
         table = {"kspec_r2c": nb[0] * nb[1] * Hl * cs,
+                 "hist_kspec": n * d * 8 + nb[0] * nb[1] * Hl * cs,
                  "kspec_col2": nb[0] * nb[1] * Hl * cs + nb[0] * P1 * Hl * cs,
+                 "scan_kcol": nb[0] * nb[1] * Hl * cs + nb[0] * P1 * Hl * cs,
                  "counts_r2c": cells * 8 + M0 * M1 * Hl * cs,
                  "counts_col2": M0 * M1 * Hl * cs + M0 * P1 * Hl * cs,
                  "conv_col1": 2 * M0 * P1 * Hl * cs + nb[0] * P1 * Hl * cs,

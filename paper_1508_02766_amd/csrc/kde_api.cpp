@@ -370,7 +370,7 @@ struct Tracer {
 // produced; the batched path collects them and launches all passes with the
 // same kernel together.
 enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols, kPassDotPartial,
-                      kPassDotFinal, kPassScanKspec };
+                      kPassDotFinal, kPassScanKspec, kPassScanKcol };
 
 struct Pass {
     PassKind kind;
@@ -413,6 +413,9 @@ int exec_pass(const Pass& p, hipStream_t s) {
             e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
             break;
         case kPassScanKspec: e = kde::launch_scan_kspec(p.prec, p.P, p.d, p.args, s); break;
+        case kPassScanKcol:
+            e = kde::launch_scan_kcol(p.prec, p.P, *reinterpret_cast<const kde::ScanColArgs*>(p.args), s);
+            break;
         case kPassDotPartial:
         case kPassDotFinal:
             // the single-problem path runs both stages through launch_dot
@@ -490,10 +493,11 @@ kde::BinConsts bin_consts(const Plan& pl, const kde_grid* g) {
 
 // Binning (Section 2, first step): the four tiled stages, or zero fill and
 // global atomics where the tiled path does not apply. With `spec` (the
-// kernel-spectrum row pass of a 1-D or 2-D problem) the histogram stage and
-// that pass share one launch.
+// kernel-spectrum row pass) the histogram stage and that pass share one
+// launch; with `spec_col` (the 3-D spectrum's strided pass) the scan stage
+// and that pass do.
 int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
-            char* ws, Emit& emit, const Pass* spec = nullptr) {
+            char* ws, Emit& emit, const Pass* spec = nullptr, const Pass* spec_col = nullptr) {
     const kde::BinConsts c = bin_consts(pl, g);
     int64_t cells = 1;
     for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
@@ -520,6 +524,21 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
                     std::memcpy(&sa.row, spec->args, sizeof(sa.row));
                     f.set_args(sa);
                 }
+                KDE_CHECK(emit(f));
+                continue;
+            }
+            if (st == kde::kBinScan && spec_col) {
+                Pass f;
+                f.kind = kPassScanKcol;
+                f.prec = spec_col->prec;
+                f.P = spec_col->P;
+                f.d = pl.pub.d;
+                f.order = st;
+                f.name = "scan_kcol";
+                kde::ScanColArgs sa{};
+                sa.bin = a;
+                std::memcpy(&sa.col, spec_col->args, sizeof(sa.col));
+                f.set_args(sa);
                 KDE_CHECK(emit(f));
                 continue;
             }
@@ -1200,24 +1219,28 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     char* bin_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
     char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
     const bool reuse = params && params->reuse_spectrum;
-    // 1-D / 2-D with tiled binning: the spectrum's row pass rides in the histogram launch
+    // with tiled binning the spectrum rides in the binning launches: its row pass
+    // in the histogram's, its strided pass (3-D) in the scan's
     std::vector<Pass> spec;
-    if (pl.pub.d <= 2 && pl.tiled && !reuse) {
+    if (pl.tiled && !reuse) {
         Collect c(spec);
         KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
-        if (spec.size() != 1 || spec[0].kind != kPassRowR2C) spec.clear();
+        const size_t want = pl.pub.d == 3 ? 2 : 1;
+        if (spec.size() != want || spec[0].kind != kPassRowR2C || (want == 2 && spec[1].kind != kPassCols))
+            spec.clear();
     }
     Tracer tr(params, stream);
     KDE_TRY(tr.start());
     const int r = run_phases(
-        stream, tr, pl.pub.d == 3,
+        stream, tr, pl.pub.d == 3 && spec.empty(),
         [&](hipStream_t s) {
             Direct e(s, tr);
             return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
         },
         [&](hipStream_t s) {
             Direct e(s, tr);
-            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0]));
+            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0],
+                              spec.size() == 2 ? &spec[1] : nullptr));
             return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
         },
         [&](hipStream_t s) {

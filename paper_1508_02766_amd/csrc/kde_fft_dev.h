@@ -518,10 +518,12 @@ struct ColShape {
     static constexpr int THREADS = T * B;
 };
 
-template <typename R, int P, int MODE, bool NARROW>
+// BW > 0 overrides the number of lines per workgroup (a power of two; the
+// caller launches P/16 * BW threads).
+template <typename R, int P, int MODE, bool NARROW, int BW = 0>
 __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_t by) {
     using C = cpx<R>;
-    constexpr int T = ColShape<R, P, NARROW>::T, B = ColShape<R, P, NARROW>::B;
+    constexpr int T = ColShape<R, P, NARROW>::T, B = BW > 0 ? BW : ColShape<R, P, NARROW>::B;
     __shared__ C lds[B * LineShape<P>::LDS];
     const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
     const int64_t w = static_cast<int64_t>(bx) * B + b;

@@ -29,6 +29,39 @@ __global__ __launch_bounds__(kBinThreads) void scan_kspec_kernel(ScanSpecArgs<R>
     bin_hist_body<D>(a.bin, blockIdx.x - ns);
 }
 
+// Scan and the strided pass of the 3-D spectrum: BW = 256 / (P/16) lines per
+// workgroup, workgroups walk the (W / BW) x outer grid of the pass, x fastest.
+template <typename R, int P>
+__global__ __launch_bounds__(kBinThreads) void scan_kcol_kernel(ScanColArgs a) {
+    constexpr int BW = scan_spec_pairs<P>();
+    const uint32_t nbx = static_cast<uint32_t>(ceil_div(a.col.W, BW));
+    const uint32_t nc = nbx * static_cast<uint32_t>(a.col.outer);
+    if (blockIdx.x < nc) {
+        cols_body<R, P, kColFwdCirc, false, BW>(a.col, blockIdx.x % nbx, blockIdx.x / nbx);
+        return;
+    }
+    bin_scan_body<3>(a.bin, blockIdx.x - nc);
+}
+
+template <typename R, int P>
+hipError_t scan_kcol_launch(const ScanColArgs& a, hipStream_t s) {
+    constexpr int BW = scan_spec_pairs<P>();
+    const dim3 g(static_cast<unsigned>(ceil_div(a.col.W, BW) * a.col.outer + a.bin.g.ntiles)), blk(kBinThreads);
+    hipLaunchKernelGGL((scan_kcol_kernel<R, P>), g, blk, 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t scan_kcol_any(int P, const ScanColArgs& a, hipStream_t s) {
+    switch (P) {
+#define KDE_CASE(PP) \
+    case PP: return scan_kcol_launch<R, PP>(a, s);
+        KDE_FOR_EACH_P(KDE_CASE)
+#undef KDE_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R, int P>
 hipError_t scan_kspec_launch(int d, const void* args, hipStream_t s) {
     const ScanSpecArgs<R>& a = *static_cast<const ScanSpecArgs<R>*>(args);
@@ -37,8 +70,10 @@ hipError_t scan_kspec_launch(int d, const void* args, hipStream_t s) {
     const size_t lds = bin_stage_lds(kBinHist, a.bin.g);   // the histogram's dynamic LDS
     if (d == 1)
         hipLaunchKernelGGL((scan_kspec_kernel<1, R, P>), g, blk, lds, s, a);
-    else
+    else if (d == 2)
         hipLaunchKernelGGL((scan_kspec_kernel<2, R, P>), g, blk, lds, s, a);
+    else
+        hipLaunchKernelGGL((scan_kspec_kernel<3, R, P>), g, blk, lds, s, a);
     return hipGetLastError();
 }
 
@@ -59,8 +94,13 @@ int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
     return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / 16));
 }
 
+hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s) {
+    if (prec == 2) return scan_kcol_any<double>(P, a, s);
+    return scan_kcol_any<float>(P, a, s);
+}
+
 hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s) {
-    if (d != 1 && d != 2) return hipErrorInvalidValue;
+    if (d < 1 || d > 3) return hipErrorInvalidValue;
     if (prec == 2) return scan_kspec_any<double>(P, d, args, s);
     return scan_kspec_any<float>(P, d, args, s);
 }

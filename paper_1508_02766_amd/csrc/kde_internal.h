@@ -189,6 +189,14 @@ struct ScanSpecArgs {
 hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s);
 int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows);
 
+// The binning scan and the spectrum's strided pass (kColFwdCirc) in one launch
+// (d = 3): the first workgroups transform lag-box columns, the rest scan.
+struct ScanColArgs {
+    BinArgs bin;
+    ColArgs col;
+};
+hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s);
+
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s);
 hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* counts,
