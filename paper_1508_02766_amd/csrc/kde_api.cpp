@@ -370,7 +370,7 @@ struct Tracer {
 // produced; the batched path collects them and launches all passes with the
 // same kernel together.
 enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols, kPassDotPartial,
-                      kPassDotFinal, kPassScanKspec, kPassScanKcol };
+                      kPassDotFinal, kPassHistKspec, kPassScanKcol };
 
 struct Pass {
     PassKind kind;
@@ -412,7 +412,7 @@ int exec_pass(const Pass& p, hipStream_t s) {
         case kPassCols:
             e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
             break;
-        case kPassScanKspec: e = kde::launch_scan_kspec(p.prec, p.P, p.d, p.args, s); break;
+        case kPassHistKspec: e = kde::launch_hist_kspec(p.prec, p.P, p.d, p.args, s); break;
         case kPassScanKcol:
             e = kde::launch_scan_kcol(p.prec, p.P, *reinterpret_cast<const kde::ScanColArgs*>(p.args), s);
             break;
@@ -507,19 +507,19 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
         for (int st = kde::kBinHist; st <= kde::kBinAccum; ++st) {
             if (st == kde::kBinHist && spec) {
                 Pass f;
-                f.kind = kPassScanKspec;
+                f.kind = kPassHistKspec;
                 f.prec = spec->prec;
                 f.P = spec->P;
                 f.d = pl.pub.d;
                 f.order = st;
                 f.name = "hist_kspec";
                 if (spec->prec == KDE_F64) {
-                    kde::ScanSpecArgs<double> sa{};
+                    kde::HistSpecArgs<double> sa{};
                     sa.bin = a;
                     std::memcpy(&sa.row, spec->args, sizeof(sa.row));
                     f.set_args(sa);
                 } else {
-                    kde::ScanSpecArgs<float> sa{};
+                    kde::HistSpecArgs<float> sa{};
                     sa.bin = a;
                     std::memcpy(&sa.row, spec->args, sizeof(sa.row));
                     f.set_args(sa);

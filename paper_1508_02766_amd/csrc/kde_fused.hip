@@ -17,13 +17,13 @@ namespace kde {
 namespace {
 
 template <int P>
-constexpr int scan_spec_pairs() { return kBinThreads / (P / 16); }   // line pairs per workgroup
+constexpr int spec_pairs() { return kBinThreads / (P / 16); }   // line pairs per workgroup
 
 template <int D, typename R, int P>
-__global__ __launch_bounds__(kBinThreads) void scan_kspec_kernel(ScanSpecArgs<R> a) {
-    const uint32_t ns = static_cast<uint32_t>(ceil_div(ceil_div(a.row.nrows, 2), scan_spec_pairs<P>()));
+__global__ __launch_bounds__(kBinThreads) void hist_kspec_kernel(HistSpecArgs<R> a) {
+    const uint32_t ns = static_cast<uint32_t>(ceil_div(ceil_div(a.row.nrows, 2), spec_pairs<P>()));
     if (blockIdx.x < ns) {
-        rows_r2c_body<R, P, kRowGaussCirc, D == 1, D, false, scan_spec_pairs<P>()>(a.row, blockIdx.x);
+        rows_r2c_body<R, P, kRowGaussCirc, D == 1, D, false, spec_pairs<P>()>(a.row, blockIdx.x);
         return;
     }
     bin_hist_body<D>(a.bin, blockIdx.x - ns);
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kBinThreads) void scan_kspec_kernel(ScanSpecArgs<R>
 // workgroup, workgroups walk the (W / BW) x outer grid of the pass, x fastest.
 template <typename R, int P>
 __global__ __launch_bounds__(kBinThreads) void scan_kcol_kernel(ScanColArgs a) {
-    constexpr int BW = scan_spec_pairs<P>();
+    constexpr int BW = spec_pairs<P>();
     const uint32_t nbx = static_cast<uint32_t>(ceil_div(a.col.W, BW));
     const uint32_t nc = nbx * static_cast<uint32_t>(a.col.outer);
     if (blockIdx.x < nc) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kBinThreads) void scan_kcol_kernel(ScanColArgs a) {
 
 template <typename R, int P>
 hipError_t scan_kcol_launch(const ScanColArgs& a, hipStream_t s) {
-    constexpr int BW = scan_spec_pairs<P>();
+    constexpr int BW = spec_pairs<P>();
     const dim3 g(static_cast<unsigned>(ceil_div(a.col.W, BW) * a.col.outer + a.bin.g.ntiles)), blk(kBinThreads);
     hipLaunchKernelGGL((scan_kcol_kernel<R, P>), g, blk, 0, s, a);
     return hipGetLastError();
@@ -63,25 +63,25 @@ hipError_t scan_kcol_any(int P, const ScanColArgs& a, hipStream_t s) {
 }
 
 template <typename R, int P>
-hipError_t scan_kspec_launch(int d, const void* args, hipStream_t s) {
-    const ScanSpecArgs<R>& a = *static_cast<const ScanSpecArgs<R>*>(args);
-    const dim3 g(static_cast<unsigned>(a.bin.g.nchunk + ceil_div(ceil_div(a.row.nrows, 2), scan_spec_pairs<P>())));
+hipError_t hist_kspec_launch(int d, const void* args, hipStream_t s) {
+    const HistSpecArgs<R>& a = *static_cast<const HistSpecArgs<R>*>(args);
+    const dim3 g(static_cast<unsigned>(a.bin.g.nchunk + ceil_div(ceil_div(a.row.nrows, 2), spec_pairs<P>())));
     const dim3 blk(kBinThreads);
     const size_t lds = bin_stage_lds(kBinHist, a.bin.g);   // the histogram's dynamic LDS
     if (d == 1)
-        hipLaunchKernelGGL((scan_kspec_kernel<1, R, P>), g, blk, lds, s, a);
+        hipLaunchKernelGGL((hist_kspec_kernel<1, R, P>), g, blk, lds, s, a);
     else if (d == 2)
-        hipLaunchKernelGGL((scan_kspec_kernel<2, R, P>), g, blk, lds, s, a);
+        hipLaunchKernelGGL((hist_kspec_kernel<2, R, P>), g, blk, lds, s, a);
     else
-        hipLaunchKernelGGL((scan_kspec_kernel<3, R, P>), g, blk, lds, s, a);
+        hipLaunchKernelGGL((hist_kspec_kernel<3, R, P>), g, blk, lds, s, a);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t scan_kspec_any(int P, int d, const void* args, hipStream_t s) {
+hipError_t hist_kspec_any(int P, int d, const void* args, hipStream_t s) {
     switch (P) {
 #define KDE_CASE(PP) \
-    case PP: return scan_kspec_launch<R, PP>(d, args, s);
+    case PP: return hist_kspec_launch<R, PP>(d, args, s);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return hipErrorInvalidValue;
@@ -90,7 +90,7 @@ hipError_t scan_kspec_any(int P, int d, const void* args, hipStream_t s) {
 
 }  // namespace
 
-int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
+int64_t hist_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
     return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / 16));
 }
 
@@ -99,10 +99,10 @@ hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s
     return scan_kcol_any<float>(P, a, s);
 }
 
-hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s) {
+hipError_t launch_hist_kspec(int prec, int P, int d, const void* args, hipStream_t s) {
     if (d < 1 || d > 3) return hipErrorInvalidValue;
-    if (prec == 2) return scan_kspec_any<double>(P, d, args, s);
-    return scan_kspec_any<float>(P, d, args, s);
+    if (prec == 2) return hist_kspec_any<double>(P, d, args, s);
+    return hist_kspec_any<float>(P, d, args, s);
 }
 
 }  // namespace kde

@@ -182,12 +182,12 @@ C2RArgs<R> make_c2r_args(const void* in, int64_t nrows, int64_t in_ld, const voi
 // The binning histogram and the kernel-spectrum row pass in one launch
 // (d <= 2): the first workgroups transform lag-box rows, the rest histogram.
 template <typename R>
-struct ScanSpecArgs {
+struct HistSpecArgs {
     BinArgs bin;
     RowArgs<R> row;
 };
-hipError_t launch_scan_kspec(int prec, int P, int d, const void* args, hipStream_t s);
-int64_t scan_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows);
+hipError_t launch_hist_kspec(int prec, int P, int d, const void* args, hipStream_t s);
+int64_t hist_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows);
 
 // The binning scan and the spectrum's strided pass (kColFwdCirc) in one launch
 // (d = 3): the first workgroups transform lag-box columns, the rest scan.
