@@ -166,7 +166,7 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     ws = torch.empty(plan["eval_ws_bytes"], dtype=torch.uint8, device=dev)
     out = torch.empty(w.M, dtype=torch.float32 if prec == "f32" else torch.float64, device=dev)
     nd = torch.empty(1, dtype=torch.uint64, device=dev)
-    cap = 16
+    cap = 32   # event pairs for up to 16 kernels
     plain = K.prepare_eval(X, w.H, grid, out, ws, nd, prec=prec)
     for _ in range(warmup):
         plain()
@@ -219,8 +219,9 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         e1.synchronize()
         cold.append(e0.elapsed_time(e1))
     del flush
-    # traced region: the same K steps with an event after every kernel; tracing
-    # keeps all kernels on one stream so each interval times one kernel
+    # traced region: the same K steps, every kernel stamping an event pair with its
+    # own dispatch start and end (hipExtLaunchKernel); tracing keeps all kernels in
+    # order on one stream
     events = [[hip.event() for _ in range(cap)] for _ in range(steps)]
     calls = [K.prepare_eval(X, w.H, grid, out, ws, nd, prec=prec, trace_events=events[s]) for s in range(steps)]
     torch.cuda.synchronize()
@@ -235,8 +236,8 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         tr = calls[s].trace()
         names = tr["names"]
         for i, nm in enumerate(names):
-            per.setdefault(nm, []).append(hip.elapsed_ms(events[s][i], events[s][i + 1]))
-    gpu_step_ms = float(np.mean([hip.elapsed_ms(events[s][0], events[s][len(names)]) for s in range(steps)]))
+            per.setdefault(nm, []).append(hip.elapsed_ms(events[s][2 * i], events[s][2 * i + 1]))
+    gpu_step_ms = float(np.mean([hip.elapsed_ms(events[s][0], events[s][2 * len(names) - 1]) for s in range(steps)]))
     for row in events:
         for e in row:
             hip.destroy(e)
@@ -316,8 +317,9 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
     loop_ms = (time.perf_counter() - t0) * 1e3 / loop_steps
     same = all(torch.equal(outs[i], B.densities[i]) for i in range(len(wl)))
     del wss, outs, calls
-    # per-kernel times of the batched launches (traced: one stream, an event after each launch)
-    evs = [hip.event() for _ in range(64)]
+    # per-kernel times of the batched launches (traced: one stream, each launch stamping
+    # an event pair with its dispatch start and end)
+    evs = [hip.event() for _ in range(128)]
     T = K.KdeBatch(items, prec="f32", trace_events=evs, trace={}, tile=info["tile"] if any(info["tile"]) else None)
     T.eval()
     torch.cuda.synchronize()
@@ -328,7 +330,7 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
         torch.cuda.synchronize()
         names = T.trace()["names"]
         for i, nm in enumerate(names):
-            per.setdefault(nm, []).append(hip.elapsed_ms(evs[i], evs[i + 1]))
+            per.setdefault(nm, []).append(hip.elapsed_ms(evs[2 * i], evs[2 * i + 1]))
     for e in evs:
         hip.destroy(e)
     T.close()
@@ -369,7 +371,7 @@ def cpu_baseline(W, name: str, reps: int):
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
     return {"value": w.n / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full FP64 oracle passes over the {name} workload (n={w.n}, grid "
+            "sample": f"{reps} full FP64 oracle pass{'es' if reps != 1 else ''} over the {name} workload (n={w.n}, grid "
                       f"{'x'.join(map(str, w.M))}): fixed-point binning, lag weights, direct Eq. (7); "
                       f"median {t:.2f} s per pass, single thread"}
 

@@ -90,13 +90,19 @@ typedef struct kde_params {
                                  point with the same H, n, grid and options; it is not
                                  recomputed. The caller guarantees the match; the result is
                                  then identical to a full call */
-    int32_t trace_capacity;   /* optional per-kernel timing, see below */
-    hipEvent_t* trace_events; /* if non-NULL: events[0] is recorded before the first kernel
-                                 and events[i] after the i-th kernel, on `stream`, up to
-                                 trace_capacity events */
-    int32_t* trace_count;     /* if non-NULL: receives the number of events recorded */
-    const char** trace_names; /* if non-NULL: receives a static name for kernel i
-                                 (trace_capacity - 1 entries) */
+    int32_t trace_capacity;   /* optional per-kernel timing: number of events in
+                                 trace_events, used in pairs */
+    hipEvent_t* trace_events; /* if non-NULL: the i-th pass of the call (one kernel; the two
+                                 stages of a dot product count as one pass) stamps
+                                 events[2i] with its dispatch start and events[2i + 1] with
+                                 its end, through hipExtLaunchKernel, for the first
+                                 trace_capacity / 2 passes; hipEventElapsedTime of a pair is
+                                 the kernel's duration. All passes then run in order on
+                                 `stream`. Events are created by the caller with timing
+                                 enabled. A stream under graph capture: KDE_ERR_ARG */
+    int32_t* trace_count;     /* if non-NULL: receives the number of passes stamped */
+    const char** trace_names; /* if non-NULL: receives a static name for pass i
+                                 (trace_capacity / 2 entries) */
 } kde_params;
 
 /* Everything the host planner derives for one problem. */

@@ -27,6 +27,13 @@
 #include "../../include/kde.h"
 #include "kde_internal.h"
 
+namespace kde {
+KernelTiming& kernel_timing() {
+    thread_local KernelTiming t;
+    return t;
+}
+}  // namespace kde
+
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -329,24 +336,41 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     return KDE_OK;
 }
 
-// Optional per-kernel event trace (kde_params.trace_*).
+// Optional per-kernel timing (kde_params.trace_*): pass i of the call gets the
+// event pair (2i, 2i + 1), stamped by its kernels' own dispatches.
 struct Tracer {
     const kde_params* prm;
     hipStream_t s;
     int n = 0;
+    int pairs = 0;
     bool on = false;
     Tracer(const kde_params* p, hipStream_t st) : prm(p), s(st) {
-        on = prm && prm->trace_events && prm->trace_capacity > 0;
+        on = prm && prm->trace_events && prm->trace_capacity >= 2;
+        pairs = on ? prm->trace_capacity / 2 : 0;
     }
-    hipError_t start() {
-        if (!on) return hipSuccess;
-        n = 1;
-        return hipEventRecord(prm->trace_events[0], s);
+    // Stamped launches cannot be captured into a graph.
+    int start() {
+        if (!on) return KDE_OK;
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &st) != hipSuccess) return KDE_ERR_HIP;
+        return st == hipStreamCaptureStatusNone ? KDE_OK : KDE_ERR_ARG;
     }
-    hipError_t mark(const char* name) {
-        if (!on || n >= prm->trace_capacity) return hipSuccess;
-        if (prm->trace_names) prm->trace_names[n - 1] = name;
-        return hipEventRecord(prm->trace_events[n++], s);
+    // Runs f, which launches the kernels of one pass (returns a KDE_* code).
+    template <typename F>
+    int pass(const char* name, F&& f) {
+        if (!on || n >= pairs) return f();
+        kde::KernelTiming& t = kde::kernel_timing();
+        t.start = prm->trace_events[2 * n];
+        t.stop = prm->trace_events[2 * n + 1];
+        t.launched = 0;
+        const int r = f();
+        const int launched = t.launched;
+        t = kde::KernelTiming{};
+        if (launched > 0) {
+            if (prm->trace_names) prm->trace_names[n] = name;
+            ++n;
+        }
+        return r;
     }
     void finish() {
         if (prm && prm->trace_count) *prm->trace_count = on ? n : 0;
@@ -436,9 +460,7 @@ struct Direct : Emit {
     Tracer& tr;
     Direct(hipStream_t st, Tracer& t) : s(st), tr(t) {}
     int operator()(const Pass& p) override {
-        KDE_CHECK(exec_pass(p, s));
-        KDE_TRY(tr.mark(p.name));
-        return KDE_OK;
+        return tr.pass(p.name, [&] { return exec_pass(p, s); });
     }
 };
 
@@ -1098,8 +1120,7 @@ int launch_group(const kde_batch& b, const Group& g, hipStream_t s) {
 int run_batch_phase(const kde_batch& b, int phase, hipStream_t s, Tracer& tr) {
     for (const Group& g : b.groups) {
         if (g.phase != phase) continue;
-        KDE_CHECK(launch_group(b, g, s));
-        KDE_TRY(tr.mark(g.key.name));
+        KDE_CHECK(tr.pass(g.key.name, [&] { return launch_group(b, g, s); }));
     }
     return KDE_OK;
 }
@@ -1155,7 +1176,7 @@ int kde_bin(const double* X, int64_t n, const kde_grid* grid, const kde_params* 
         if (ws_bytes < pl.pub.bin_ws_bytes) return KDE_ERR_WS;
     }
     Tracer tr(params, stream);
-    KDE_TRY(tr.start());
+    KDE_CHECK(tr.start());
     Direct emit(stream, tr);
     const int r = run_bin(pl, X, n, grid, counts, n_dropped, static_cast<char*>(ws), emit);
     tr.finish();
@@ -1170,9 +1191,12 @@ int kde_kernel_grid(const double* H, int64_t n, const kde_grid* grid, const kde_
     if (!lags) return KDE_ERR_ARG;
     if (lags_bytes < pl.pub.lag_bytes) return KDE_ERR_WS;
     Tracer tr(params, stream);
-    KDE_TRY(tr.start());
-    KDE_TRY(kde::launch_kfill(pl.pub.prec, pl.pub.d, pl.pub.L, pl.A, pl.pub.norm, lags, stream));
-    KDE_TRY(tr.mark("kfill"));
+    KDE_CHECK(tr.start());
+    KDE_CHECK(tr.pass("kfill", [&] {
+        return kde::launch_kfill(pl.pub.prec, pl.pub.d, pl.pub.L, pl.A, pl.pub.norm, lags, stream) == hipSuccess
+                   ? KDE_OK
+                   : KDE_ERR_HIP;
+    }));
     tr.finish();
     return KDE_OK;
 }
@@ -1188,7 +1212,7 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     char* conv_ws = static_cast<char*>(ws);
     const bool reuse = params && params->reuse_spectrum;
     Tracer tr(params, stream);
-    KDE_TRY(tr.start());
+    KDE_CHECK(tr.start());
     const int r = run_phases(
         stream, tr, pl.pub.d == 3,
         [&](hipStream_t s) {
@@ -1230,7 +1254,7 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
             spec.clear();
     }
     Tracer tr(params, stream);
-    KDE_TRY(tr.start());
+    KDE_CHECK(tr.start());
     const int r = run_phases(
         stream, tr, pl.pub.d == 3 && spec.empty(),
         [&](hipStream_t s) {
@@ -1267,7 +1291,7 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     int64_t cells = 1;
     for (int k = 0; k < p1.pub.d; ++k) cells *= grid->M[k];
     Tracer tr(params, stream);
-    KDE_TRY(tr.start());
+    KDE_CHECK(tr.start());
     // first term with 2H, then the second with H; each convolution is followed
     // by its dot product on the caller's stream
     const Plan* plans[2] = {&p2, &p1};
@@ -1295,13 +1319,17 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
         a.partial = partial;
         a.nb = kde::dot_blocks(cells);
         a.out = dots + t;
-        KDE_TRY(kde::launch_dot(pl.pub.prec, a, stream));
-        KDE_TRY(tr.mark("dot"));
+        KDE_CHECK(tr.pass("dot", [&] {
+            return kde::launch_dot(pl.pub.prec, a, stream) == hipSuccess ? KDE_OK : KDE_ERR_HIP;
+        }));
     }
     // phi_H(0) = (2 pi)^-d/2 |H|^-1/2 = n k_0
     const double phi0 = p1.pub.norm * static_cast<double>(n);
-    KDE_TRY(kde::launch_lscv_combine(dots, static_cast<double>(n), phi0, out, stream));
-    KDE_TRY(tr.mark("lscv_combine"));
+    KDE_CHECK(tr.pass("lscv_combine", [&] {
+        return kde::launch_lscv_combine(dots, static_cast<double>(n), phi0, out, stream) == hipSuccess
+                   ? KDE_OK
+                   : KDE_ERR_HIP;
+    }));
     tr.finish();
     return KDE_OK;
 }
@@ -1549,7 +1577,7 @@ int kde_batch_eval(const kde_batch* b, hipStream_t stream) {
     if (!b || !b->bound) return KDE_ERR_ARG;
     const kde_params* prm = b->has_prm ? &b->prm : nullptr;
     Tracer tr(prm, stream);
-    KDE_TRY(tr.start());
+    KDE_CHECK(tr.start());
     const int r = run_phases(
         stream, tr, true, [&](hipStream_t s) { return run_batch_phase(*b, 0, s, tr); },
         [&](hipStream_t s) { return run_batch_phase(*b, 1, s, tr); },

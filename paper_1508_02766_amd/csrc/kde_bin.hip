@@ -119,7 +119,7 @@ hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, count);
+    KDE_LAUNCH(zero_u64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 
@@ -132,11 +132,11 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
     auto* nd = reinterpret_cast<unsigned long long*>(n_dropped);
     const dim3 g(static_cast<unsigned>(blocks)), blk(256);
     if (c.d == 1)
-        hipLaunchKernelGGL((bin_kernel<1>), g, blk, 0, s, X, n, c, cc, nd);
+        KDE_LAUNCH((bin_kernel<1>), g, blk, 0, s, X, n, c, cc, nd);
     else if (c.d == 2)
-        hipLaunchKernelGGL((bin_kernel<2>), g, blk, 0, s, X, n, c, cc, nd);
+        KDE_LAUNCH((bin_kernel<2>), g, blk, 0, s, X, n, c, cc, nd);
     else
-        hipLaunchKernelGGL((bin_kernel<3>), g, blk, 0, s, X, n, c, cc, nd);
+        KDE_LAUNCH((bin_kernel<3>), g, blk, 0, s, X, n, c, cc, nd);
     return hipGetLastError();
 }
 
@@ -156,10 +156,10 @@ hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
     const dim3 blk(kBinThreads), grid(static_cast<unsigned>(bin_stage_extent(stage, a.g)));
     const size_t lds = bin_stage_lds(stage, a.g);
     switch (stage) {
-        case kBinHist: hipLaunchKernelGGL((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
-        case kBinScan: hipLaunchKernelGGL((bin_scan_kernel<D>), grid, blk, 0, s, a); break;
-        case kBinScatter: hipLaunchKernelGGL((bin_scatter_kernel<D>), grid, blk, lds, s, a); break;
-        case kBinAccum: hipLaunchKernelGGL((bin_accum_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinHist: KDE_LAUNCH((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinScan: KDE_LAUNCH((bin_scan_kernel<D>), grid, blk, 0, s, a); break;
+        case kBinScatter: KDE_LAUNCH((bin_scatter_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinAccum: KDE_LAUNCH((bin_accum_kernel<D>), grid, blk, lds, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -169,10 +169,10 @@ template <int D>
 hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream_t s) {
     const dim3 blk(kBinThreads), grid(m.blocks);
     switch (stage) {
-        case kBinHist: hipLaunchKernelGGL((bin_hist_batch<D>), grid, blk, lds, s, m); break;
-        case kBinScan: hipLaunchKernelGGL((bin_scan_batch<D>), grid, blk, 0, s, m); break;
-        case kBinScatter: hipLaunchKernelGGL((bin_scatter_batch<D>), grid, blk, lds, s, m); break;
-        case kBinAccum: hipLaunchKernelGGL((bin_accum_batch<D>), grid, blk, lds, s, m); break;
+        case kBinHist: KDE_LAUNCH((bin_hist_batch<D>), grid, blk, lds, s, m); break;
+        case kBinScan: KDE_LAUNCH((bin_scan_batch<D>), grid, blk, 0, s, m); break;
+        case kBinScatter: KDE_LAUNCH((bin_scatter_batch<D>), grid, blk, lds, s, m); break;
+        case kBinAccum: KDE_LAUNCH((bin_accum_batch<D>), grid, blk, lds, s, m); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

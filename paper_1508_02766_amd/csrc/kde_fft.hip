@@ -98,7 +98,7 @@ hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* la
     int64_t count = 1;
     for (int k = 0; k < D; ++k) count *= 2 * L[k] + 1;
     const int64_t blocks = ceil_div(count, 256);
-    hipLaunchKernelGGL((kfill_kernel<R, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+    KDE_LAUNCH((kfill_kernel<R, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        static_cast<R*>(lags), count, L[0], D > 1 ? L[1] : 0, D > 2 ? L[2] : 0,
                        static_cast<R>(A[0]), static_cast<R>(A[1]), static_cast<R>(A[2]),
                        static_cast<R>(A[4]), static_cast<R>(A[5]), static_cast<R>(A[8]),
@@ -111,13 +111,13 @@ hipError_t rows_r2c_launch_b(int kind, int d, const RowArgs<R>& a, hipStream_t s
     const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
     const dim3 blk(RowShape<P, NARROW>::THREADS);
     if (kind == kRowCountsU64)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowCountsU64, false, 1, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowCountsU64, false, 1, NARROW>), g, blk, 0, s, a);
     else if (d == 1)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1, NARROW>), g, blk, 0, s, a);
     else if (d == 2)
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2, NARROW>), g, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3, NARROW>), g, blk, 0, s, a);
     return hipGetLastError();
 }
 
@@ -134,9 +134,9 @@ hipError_t rows_c2r_launch_b(const C2RArgs<R>& a, hipStream_t s) {
     const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
     const dim3 blk(RowShape<P, NARROW>::THREADS);
     if (a.mult)
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, true, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_c2r_kernel<R, P, true, NARROW>), g, blk, 0, s, a);
     else
-        hipLaunchKernelGGL((rows_c2r_kernel<R, P, false, NARROW>), g, blk, 0, s, a);
+        KDE_LAUNCH((rows_c2r_kernel<R, P, false, NARROW>), g, blk, 0, s, a);
     return hipGetLastError();
 }
 
@@ -153,10 +153,10 @@ hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
     const dim3 g(static_cast<unsigned>(ceil_div(a.W, B)), static_cast<unsigned>(a.outer));
     const dim3 blk(ColShape<R, P, NARROW>::THREADS);
     switch (mode) {
-        case kColFwdPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, a); break;
-        case kColFwdCirc: hipLaunchKernelGGL((cols_kernel<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, a); break;
-        case kColInvPrefix: hipLaunchKernelGGL((cols_kernel<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, a); break;
-        case kColConvLag: hipLaunchKernelGGL((cols_kernel<R, P, kColConvLag, NARROW>), g, blk, 0, s, a); break;
+        case kColFwdPrefix: KDE_LAUNCH((cols_kernel<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, a); break;
+        case kColFwdCirc: KDE_LAUNCH((cols_kernel<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, a); break;
+        case kColInvPrefix: KDE_LAUNCH((cols_kernel<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, a); break;
+        case kColConvLag: KDE_LAUNCH((cols_kernel<R, P, kColConvLag, NARROW>), g, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

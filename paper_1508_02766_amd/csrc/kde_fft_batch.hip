@@ -38,13 +38,13 @@ template <typename R, int P>
 hipError_t rows_r2c_batch_launch(int kind, int d, const BatchMap& m, hipStream_t s) {
     const dim3 g(m.blocks), blk(RowShape<P>::THREADS);
     if (kind == kRowCountsU64)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_r2c_batch<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, m);
     else if (d == 1)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, m);
     else if (d == 2)
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, m);
     else
-        hipLaunchKernelGGL((rows_r2c_batch<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, m);
     return hipGetLastError();
 }
 
@@ -52,9 +52,9 @@ template <typename R, int P>
 hipError_t rows_c2r_batch_launch(bool mult, const BatchMap& m, hipStream_t s) {
     const dim3 g(m.blocks), blk(RowShape<P>::THREADS);
     if (mult)
-        hipLaunchKernelGGL((rows_c2r_batch<R, P, true>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_c2r_batch<R, P, true>), g, blk, 0, s, m);
     else
-        hipLaunchKernelGGL((rows_c2r_batch<R, P, false>), g, blk, 0, s, m);
+        KDE_LAUNCH((rows_c2r_batch<R, P, false>), g, blk, 0, s, m);
     return hipGetLastError();
 }
 
@@ -62,10 +62,10 @@ template <typename R, int P, bool NARROW>
 hipError_t cols_batch_launch_b(int mode, const BatchMap& m, hipStream_t s) {
     const dim3 g(m.blocks), blk(ColShape<R, P, NARROW>::THREADS);
     switch (mode) {
-        case kColFwdPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, m); break;
-        case kColFwdCirc: hipLaunchKernelGGL((cols_batch<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, m); break;
-        case kColInvPrefix: hipLaunchKernelGGL((cols_batch<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, m); break;
-        case kColConvLag: hipLaunchKernelGGL((cols_batch<R, P, kColConvLag, NARROW>), g, blk, 0, s, m); break;
+        case kColFwdPrefix: KDE_LAUNCH((cols_batch<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, m); break;
+        case kColFwdCirc: KDE_LAUNCH((cols_batch<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, m); break;
+        case kColInvPrefix: KDE_LAUNCH((cols_batch<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, m); break;
+        case kColConvLag: KDE_LAUNCH((cols_batch<R, P, kColConvLag, NARROW>), g, blk, 0, s, m); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

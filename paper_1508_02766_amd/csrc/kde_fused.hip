@@ -47,7 +47,7 @@ template <typename R, int P>
 hipError_t scan_kcol_launch(const ScanColArgs& a, hipStream_t s) {
     constexpr int BW = spec_pairs<P>();
     const dim3 g(static_cast<unsigned>(ceil_div(a.col.W, BW) * a.col.outer + a.bin.g.ntiles)), blk(kBinThreads);
-    hipLaunchKernelGGL((scan_kcol_kernel<R, P>), g, blk, 0, s, a);
+    KDE_LAUNCH((scan_kcol_kernel<R, P>), g, blk, 0, s, a);
     return hipGetLastError();
 }
 
@@ -69,11 +69,11 @@ hipError_t hist_kspec_launch(int d, const void* args, hipStream_t s) {
     const dim3 blk(kBinThreads);
     const size_t lds = bin_stage_lds(kBinHist, a.bin.g);   // the histogram's dynamic LDS
     if (d == 1)
-        hipLaunchKernelGGL((hist_kspec_kernel<1, R, P>), g, blk, lds, s, a);
+        KDE_LAUNCH((hist_kspec_kernel<1, R, P>), g, blk, lds, s, a);
     else if (d == 2)
-        hipLaunchKernelGGL((hist_kspec_kernel<2, R, P>), g, blk, lds, s, a);
+        KDE_LAUNCH((hist_kspec_kernel<2, R, P>), g, blk, lds, s, a);
     else
-        hipLaunchKernelGGL((hist_kspec_kernel<3, R, P>), g, blk, lds, s, a);
+        KDE_LAUNCH((hist_kspec_kernel<3, R, P>), g, blk, lds, s, a);
     return hipGetLastError();
 }
 

@@ -2,10 +2,35 @@
 // gfx950 kernels (kde_bin.hip, kde_fft.hip). Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace kde {
+
+// Per-kernel timing. While `stop` is set on the calling thread, every launch
+// hands the events to hipExtLaunchKernel, which stamps them with the kernel's
+// own dispatch start (first launch only) and end: one pair times the kernels
+// of one pass, without the gaps between packets that events recorded around
+// the launches would add.
+struct KernelTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    int launched = 0;
+};
+KernelTiming& kernel_timing();   // thread-local; defined with the C ABI
+
+#define KDE_LAUNCH(kernel, grid, block, lds, stream, ...)                                          \
+    do {                                                                                           \
+        ::kde::KernelTiming& kt_ = ::kde::kernel_timing();                                         \
+        if (kt_.stop) {                                                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, static_cast<uint32_t>(lds), stream,         \
+                                  kt_.launched ? nullptr : kt_.start, kt_.stop, 0, __VA_ARGS__);   \
+            ++kt_.launched;                                                                        \
+        } else {                                                                                   \
+            hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                     \
+        }                                                                                          \
+    } while (0)
 
 constexpr int kMaxP = 4096;   // largest padded FFT length per axis
 constexpr int kMinP = 16;     // smallest (one radix-16 stage)

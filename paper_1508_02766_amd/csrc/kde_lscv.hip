@@ -89,12 +89,12 @@ int64_t dot_blocks(int64_t cells) { return (cells + kDotChunk - 1) / kDotChunk; 
 hipError_t launch_dot(int prec, const DotArgs& a, hipStream_t s) {
     const dim3 blk(kDotThreads), g(static_cast<unsigned>(dot_blocks(a.cells)));
     if (prec == 2)
-        hipLaunchKernelGGL(dot_partial_kernel<double>, g, blk, 0, s, a);
+        KDE_LAUNCH(dot_partial_kernel<double>, g, blk, 0, s, a);
     else
-        hipLaunchKernelGGL(dot_partial_kernel<float>, g, blk, 0, s, a);
+        KDE_LAUNCH(dot_partial_kernel<float>, g, blk, 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), blk, 0, s, a);
+    KDE_LAUNCH(dot_final_kernel, dim3(1), blk, 0, s, a);
     return hipGetLastError();
 }
 
@@ -102,16 +102,16 @@ hipError_t launch_dot_batch(int prec, bool final_stage, const BatchMap& m, hipSt
     if (m.count <= 0 || m.blocks == 0) return hipSuccess;
     const dim3 blk(kDotThreads), g(m.blocks);
     if (final_stage)
-        hipLaunchKernelGGL(dot_final_batch, g, blk, 0, s, m);
+        KDE_LAUNCH(dot_final_batch, g, blk, 0, s, m);
     else if (prec == 2)
-        hipLaunchKernelGGL(dot_partial_batch<double>, g, blk, 0, s, m);
+        KDE_LAUNCH(dot_partial_batch<double>, g, blk, 0, s, m);
     else
-        hipLaunchKernelGGL(dot_partial_batch<float>, g, blk, 0, s, m);
+        KDE_LAUNCH(dot_partial_batch<float>, g, blk, 0, s, m);
     return hipGetLastError();
 }
 
 hipError_t launch_lscv_combine(const double* dots, double n, double phi0, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(lscv_combine_kernel, dim3(1), dim3(64), 0, s, dots, n, phi0, out);
+    KDE_LAUNCH(lscv_combine_kernel, dim3(1), dim3(64), 0, s, dots, n, phi0, out);
     return hipGetLastError();
 }
 

@@ -297,15 +297,15 @@ hipError_t launch_mlp(int op, const MlpArgs& a, const float* params, hipStream_t
     const dim3 blk(kThreads);
     const unsigned pblocks = static_cast<unsigned>((kMlpParams + kThreads - 1) / kThreads);
     switch (op) {
-        case kMlpOpLoad: hipLaunchKernelGGL(mlp_load_kernel, dim3(pblocks), blk, 0, s, a, params); break;
+        case kMlpOpLoad: KDE_LAUNCH(mlp_load_kernel, dim3(pblocks), blk, 0, s, a, params); break;
         case kMlpOpForward:
-            hipLaunchKernelGGL(mlp_fwd_kernel, dim3(static_cast<unsigned>(a.groups)), blk, 0, s, a);
+            KDE_LAUNCH(mlp_fwd_kernel, dim3(static_cast<unsigned>(a.groups)), blk, 0, s, a);
             break;
         case kMlpOpBackward:
-            hipLaunchKernelGGL(mlp_bwd_kernel, dim3(static_cast<unsigned>(a.groups)), blk, 0, s, a);
+            KDE_LAUNCH(mlp_bwd_kernel, dim3(static_cast<unsigned>(a.groups)), blk, 0, s, a);
             break;
-        case kMlpOpReduce: hipLaunchKernelGGL(mlp_reduce_kernel, dim3(pblocks), blk, 0, s, a); break;
-        case kMlpOpAdam: hipLaunchKernelGGL(mlp_adam_kernel, dim3(pblocks), blk, 0, s, a); break;
+        case kMlpOpReduce: KDE_LAUNCH(mlp_reduce_kernel, dim3(pblocks), blk, 0, s, a); break;
+        case kMlpOpAdam: KDE_LAUNCH(mlp_adam_kernel, dim3(pblocks), blk, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -18,7 +18,8 @@ The names and semantics follow include/kde.h:
 ``Q`` (fixed-point bits), ``tile`` (binning tile per axis), ``extent`` ("eigen" = Eq. 15,
 "marginal" = tau sqrt(H_kk) per axis), ``reuse_spectrum`` (the workspace holds the kernel spectrum
 of an earlier call with the same H, n, grid and options), ``trace_events`` (list of raw hipEvent_t handles
-as ints) with ``trace`` (a dict that receives ``count`` and ``names``).
+as ints, used in pairs: pass i stamps events 2i and 2i + 1 with its kernel's start and end) with
+``trace`` (a dict that receives ``count``, the number of passes stamped, and their ``names``).
 """
 from __future__ import annotations
 
@@ -182,7 +183,7 @@ def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, reuse_s
     if trace_events:
         arr = (ctypes.c_void_p * len(trace_events))(*[int(e) for e in trace_events])
         cnt = ctypes.c_int32(0)
-        names = (ctypes.c_char_p * len(trace_events))()
+        names = (ctypes.c_char_p * max(len(trace_events) // 2, 1))()
         p.trace_capacity = len(trace_events)
         p.trace_events = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
         p.trace_count = ctypes.pointer(cnt)
@@ -196,7 +197,7 @@ def _finish_trace(keep):
         arr, cnt, names, trace = keep
         n = cnt.value
         trace["count"] = n
-        trace["names"] = [names[i].decode() for i in range(max(n - 1, 0))]
+        trace["names"] = [names[i].decode() for i in range(n)]
 
 
 def _H(H, d: int):

@@ -160,6 +160,11 @@ def test_batch_trace_names_groups():
     t = B.trace()
     assert t["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "counts_r2c",
                           "kspec_r2c", "conv_col", "c2r"]
+    for i in range(t["count"]):
+        ms = ctypes.c_float()
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(evs[2 * i]),
+                                       ctypes.c_void_p(evs[2 * i + 1])) == 0
+        assert ms.value > 0.0
     _assert_matches_single(B, items, prec="f32")
     for e in evs:
         hip.hipEventDestroy(ctypes.c_void_p(e))
