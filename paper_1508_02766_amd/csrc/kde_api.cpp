@@ -54,7 +54,7 @@ struct Layout {
 
 struct BinLayout {
     // offsets into the binning workspace (tiled path)
-    size_t hist = 0, tot = 0, drops = 0, tile_start = 0, records = 0, seg_first = 0, seg_tile = 0, total = 0;
+    size_t hist = 0, tot = 0, drops = 0, records = 0, seg = 0, total = 0;
 };
 
 struct Plan {
@@ -123,10 +123,8 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
     bl->hist = take(static_cast<size_t>(g.nchunk) * g.ntiles * 4);
     bl->tot = take(static_cast<size_t>(g.ntiles) * 4);
     bl->drops = take(static_cast<size_t>(g.nchunk) * 4);
-    bl->tile_start = take(static_cast<size_t>(g.ntiles) * 4);
     bl->records = take(static_cast<size_t>(g.max_records) * 8);
-    bl->seg_first = take(static_cast<size_t>(g.ntiles) * 4);
-    bl->seg_tile = take(static_cast<size_t>(g.max_segments) * 4);
+    bl->seg = take(static_cast<size_t>(g.max_segments) * 16);
     bl->total = off;
     *tg = g;
     return true;
@@ -485,10 +483,8 @@ kde::BinArgs bin_args(const Plan& pl, const kde::BinConsts& c, const double* X, 
     a.w.hist = reinterpret_cast<uint32_t*>(ws + b.hist);
     a.w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
     a.w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
-    a.w.tile_start = reinterpret_cast<uint32_t*>(ws + b.tile_start);
     a.w.records = reinterpret_cast<uint64_t*>(ws + b.records);
-    a.w.seg_first = reinterpret_cast<uint32_t*>(ws + b.seg_first);
-    a.w.seg_tile = reinterpret_cast<uint32_t*>(ws + b.seg_tile);
+    a.w.seg = reinterpret_cast<uint4*>(ws + b.seg);
     a.counts = counts;
     a.n_dropped = reinterpret_cast<unsigned long long*>(n_dropped);
     return a;

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const double* __restrict__ X, 
     unsigned long long dropped = 0;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-        int64_t j[D];
+        int j[D];
         uint64_t q[D];
         if (!classify<D>(X, i, c, j, q)) {
             ++dropped;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void bin_kernel(const double* __restrict__ X, 
             for (int k = 0; k < D; ++k) {
                 const int bit = (corner >> (D - 1 - k)) & 1;
                 w *= bit ? q[k] : one - q[k];
-                idx += (j[k] + bit) * c.stride[k];
+                idx += static_cast<int64_t>(j[k] + bit) * c.stride[k];
             }
             if (w) atomicAdd(counts + idx, static_cast<unsigned long long>(w));
         }

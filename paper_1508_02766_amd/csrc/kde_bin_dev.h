@@ -13,12 +13,13 @@ namespace {
 
 // Classification of a sample with coordinates x: false when it lies outside
 // the closed grid box (or is NaN) on some axis; otherwise the lower-corner
-// node j and the fractions q.
+// node j and the fractions q. Nodes fit 32 bits (M_k <= 2^24); so does q
+// when Q < 32, and then one 32-bit conversion replaces the 64-bit one.
 template <int D>
-__device__ __forceinline__ bool classify_x(const double (&x)[D], const BinConsts& c, int64_t (&j)[D],
-                                           uint64_t (&q)[D]) {
+__device__ __forceinline__ bool classify_x(const double (&x)[D], const BinConsts& c, int (&j)[D], uint64_t (&q)[D]) {
     const double scale = static_cast<double>(1ull << c.Q);   // exact power of two
     bool ok = true;
+    double r[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const double u = (x[k] - c.lo[k]) / c.delta[k];
@@ -27,15 +28,22 @@ __device__ __forceinline__ bool classify_x(const double (&x)[D], const BinConsts
         double jf = floor(u);
         jf = jf < c.top[k] - 1.0 ? jf : c.top[k] - 1.0;  // a sample on the last node
         const double t = u - jf;                           // exact
-        q[k] = in ? static_cast<uint64_t>(rint(t * scale)) : 0;
-        j[k] = in ? static_cast<int64_t>(jf) : 0;
+        r[k] = in ? rint(t * scale) : 0.0;                 // in [0, 2^Q]
+        j[k] = in ? static_cast<int>(jf) : 0;
+    }
+    if (c.Q < 32) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) q[k] = static_cast<uint32_t>(r[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) q[k] = static_cast<uint64_t>(r[k]);
     }
     return ok;
 }
 
 template <int D>
-__device__ __forceinline__ bool classify(const double* __restrict__ X, int64_t i, const BinConsts& c,
-                                         int64_t (&j)[D], uint64_t (&q)[D]) {
+__device__ __forceinline__ bool classify(const double* __restrict__ X, int64_t i, const BinConsts& c, int (&j)[D],
+                                         uint64_t (&q)[D]) {
     double x[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = X[i * D + k];
@@ -62,8 +70,8 @@ __device__ __forceinline__ void load_chunk(const double* __restrict__ X, int64_t
 
 // Calls f(tile, record) for every tile the corners j..j+1 touch.
 template <int D, typename F>
-__device__ __forceinline__ void for_each_tile(const TileGeom& g, const int64_t (&j)[D], const uint64_t (&q)[D], F&& f) {
-    int64_t tlo[D];
+__device__ __forceinline__ void for_each_tile(const TileGeom& g, const int (&j)[D], const uint64_t (&q)[D], F&& f) {
+    int tlo[D];
     int span[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -76,20 +84,20 @@ __device__ __forceinline__ void for_each_tile(const TileGeom& g, const int64_t (
 #pragma unroll
     for (int b = 0; b < (1 << D); ++b) {
         bool use = true;
-        int64_t tile = 0;
+        uint32_t tile = 0;
         uint64_t rec = qpart;
         int shift = D * g.qbits;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             const int bk = (b >> k) & 1;
             use = use && (bk <= span[k]);
-            const int64_t tk = tlo[k] + bk;
-            tile = tile * g.nt[k] + tk;
-            const uint64_t jl = static_cast<uint64_t>(j[k] - (tk << g.logT[k]) + 1);   // in [0, T_k]
-            rec |= jl << shift;
+            const int tk = tlo[k] + bk;
+            tile = tile * static_cast<uint32_t>(g.nt[k]) + static_cast<uint32_t>(tk);
+            const uint32_t jl = static_cast<uint32_t>(j[k] - (tk << g.logT[k]) + 1);   // in [0, T_k]
+            rec |= static_cast<uint64_t>(jl) << shift;
             shift += g.jbits[k];
         }
-        if (use) f(static_cast<uint32_t>(tile), rec);
+        if (use) f(tile, rec);
     }
 }
 
@@ -150,7 +158,7 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (!valid[k]) continue;
-        int64_t j[D];
+        int j[D];
         uint64_t q[D];
         if (!classify_x<D>(x[k], c, j, q)) {
             ++dropped;
@@ -267,39 +275,68 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
-    extern __shared__ uint32_t cur[];   // [ntiles], and [ntiles] more in workgroup 0
+    extern __shared__ uint32_t cur[];   // [ntiles] cursors, [ntiles] this chunk's offsets
     __shared__ uint32_t wave_sums[kBinThreads / 64];
+    uint32_t* aux = cur + g.ntiles;
     const int tid = threadIdx.x;
+    const bool lead = blk == 0;
+    // The tile totals and this chunk's offsets are loaded before the samples: vector
+    // memory loads return in order, so the prologue below waits for them alone while
+    // the samples are still in flight (up to kPre * kBinThreads tiles in registers).
+    constexpr int kPre = 4;
+    uint32_t pt[kPre], ph[kPre];
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+        const int t = tid + m * kBinThreads;
+        pt[m] = t < g.ntiles ? w.tot[t] : 0u;
+        ph[m] = t < g.ntiles && !lead ? w.hist[static_cast<int64_t>(t) * g.nchunk + blk] : 0u;
+    }
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D>(X, n, blk, x, valid);   // in flight during the prologue
-    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] = w.tot[t];
+    load_chunk<D>(X, n, blk, x, valid);
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+        const int t = tid + m * kBinThreads;
+        if (t < g.ntiles) {
+            cur[t] = pt[m];
+            aux[t] = ph[m];
+        }
+    }
+    for (int t = tid + kPre * kBinThreads; t < g.ntiles; t += kBinThreads) {
+        cur[t] = w.tot[t];
+        if (!lead) aux[t] = w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
+    }
     __syncthreads();
     block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
-    if (blk == 0) {
-        // the accumulation's work list: tile t owns segments [seg_first[t], seg_first[t] + max(1,
-        // ceil(tot / S))), and seg_tile maps each segment back to its tile (all ones past the end)
-        uint32_t* first = cur + g.ntiles;
+    if (lead) {
+        // the accumulation's work list: tile t owns max(1, ceil(tot / S)) consecutive segments
+        // of at most S records; aux first holds the segment counts, then their offsets
         for (int t = tid; t < g.ntiles; t += kBinThreads) {
-            w.tile_start[t] = cur[t];
             const uint32_t cnt = w.tot[t];
-            first[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+            aux[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
         }
         __syncthreads();
-        const uint32_t nsegs = block_exclusive_scan(first, g.ntiles, wave_sums);
+        const uint32_t nsegs = block_exclusive_scan(aux, g.ntiles, wave_sums);
+        const uint32_t S = static_cast<uint32_t>(g.S);
         for (int t = tid; t < g.ntiles; t += kBinThreads) {
-            w.seg_first[t] = first[t];
-            const uint32_t e = t + 1 < g.ntiles ? first[t + 1] : nsegs;
-            for (uint32_t q = first[t]; q < e; ++q) w.seg_tile[q] = static_cast<uint32_t>(t);
+            const uint32_t cnt = w.tot[t];
+            const uint32_t end = cur[t] + cnt;
+            const uint32_t e = t + 1 < g.ntiles ? aux[t + 1] : nsegs;
+            uint32_t r = cur[t];
+            for (uint32_t q = aux[t]; q < e; ++q, r += S)
+                w.seg[q] = make_uint4(static_cast<uint32_t>(t), r, end - r > S ? r + S : end, cnt > S ? 1u : 0u);
+            cur[t] += w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
         }
-        for (int64_t q = nsegs + tid; q < g.max_segments; q += kBinThreads) w.seg_tile[q] = 0xFFFFFFFFu;
+        for (int64_t q = nsegs + tid; q < g.max_segments; q += kBinThreads)
+            w.seg[q] = make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
+    } else {
+        for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += aux[t];
     }
-    for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         if (!valid[k]) continue;
-        int64_t j[D];
+        int j[D];
         uint64_t q[D];
         if (!classify_x<D>(x[k], c, j, q)) continue;
         for_each_tile<D>(g, j, q, [&](uint32_t tile, uint64_t rec) {
@@ -321,14 +358,10 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     uint64_t* __restrict__ counts = a.counts;
     extern __shared__ unsigned long long grid[];   // [tile_cells]
     const int tid = threadIdx.x;
-    const uint32_t tile = w.seg_tile[blk];          // work list written by the scatter pass
-    if (tile == 0xFFFFFFFFu) return;
-    const uint32_t k = blk - w.seg_first[tile];
-    const uint32_t tcount = w.tot[tile];
-    const uint32_t r0 = w.tile_start[tile] + k * static_cast<uint32_t>(g.S);
-    const uint32_t tend = w.tile_start[tile] + tcount;
-    const uint32_t r1 = r0 + static_cast<uint32_t>(g.S) < tend ? r0 + static_cast<uint32_t>(g.S) : tend;
-    const bool shared_tile = tcount > static_cast<uint32_t>(g.S);
+    const uint4 sd = w.seg[blk];                    // work list written by the scatter pass
+    if (sd.x == 0xFFFFFFFFu) return;
+    const uint32_t tile = sd.x, r0 = sd.y, r1 = sd.z;
+    const bool shared_tile = sd.w != 0;
     // this thread's records, loaded together
     constexpr int kRec = kSegment / kBinThreads;
     uint64_t recs[kRec];

@@ -76,10 +76,9 @@ struct BinWork {
     uint32_t* hist;         // [ntiles][nchunk] counts, then exclusive offsets over chunks
     uint32_t* tot;          // [ntiles] records per tile
     uint32_t* drops;        // [nchunk] dropped samples per chunk
-    uint32_t* tile_start;   // [ntiles] first record of each tile
     uint64_t* records;      // [max_records]
-    uint32_t* seg_first;    // [ntiles] first accumulation segment of each tile
-    uint32_t* seg_tile;     // [max_segments] tile of each segment (all ones: none)
+    uint4* seg;             // [max_segments] accumulation work list: {tile, first record, end
+                            // record, tile has several segments}; tile all ones: no work
 };
 
 // Everything one instance of the tiled binning reads and writes.
