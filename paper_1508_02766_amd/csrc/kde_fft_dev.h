@@ -211,63 +211,63 @@ __device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
 // the stride-16 stores of the first stage off a single bank.
 __device__ __forceinline__ int padi(int p) { return p + (p >> 4); }
 
-template <int P>
-struct LineShape {
-    static constexpr int T = P / 16;          // threads per line
-    static constexpr int LDS = P + P / 16;    // padded LDS elements per line
-};
+// Points per thread E of a line transform of length P: the line's T = P / E
+// threads hold element t + T m in register slot m. E = 16 up to P = 256, where
+// the transform takes at most three stages. Longer lines are few (at most P/2
+// per axis of a grid), so they spread over more threads: the row passes use 4
+// points per thread at P = 512 and 1024, the column passes (three transforms
+// per line in the product pass) 8; beyond, the fewest that keep a line within
+// 256 threads. A function of P and the pass alone: every launch shape of a
+// pass rounds identically.
+__host__ __device__ constexpr int row_points(int P) { return P <= 256 ? 16 : (P <= 1024 ? 4 : P / 256); }
+__host__ __device__ constexpr int col_points(int P) { return P <= 256 ? 16 : (P <= 1024 ? 8 : P / 256); }
 
-// Radices of the stages after the first radix-16 one.
-template <int P>
-struct Stages {
-    static constexpr int R1 = P > 16 ? ((P / 16 >= 16) ? 16 : P / 16) : 1;   // second stage (NS = 16)
-    static constexpr int R2 = P > 256 ? P / 256 : 1;                         // third stage (NS = 256)
-    static constexpr int N1 = P > 16 ? (16 / R1) * (R1 - 1) : 0;            // twiddles per thread
-    static constexpr int N2 = P > 256 ? (16 / R2) * (R2 - 1) : 0;
-};
+// Radix of the stage that follows the stages with product NS.
+template <int P, int E, int NS>
+constexpr int stage_radix() { return (P / NS) < E ? P / NS : E; }
 
-// The twiddles one thread uses in the second and third stages, loaded
-// together at the start of the transform so their latency overlaps the first
-// stage instead of stalling each later one.
-template <typename R, int P>
-struct LineTwiddles {
-    cpx<R> w1[Stages<P>::N1 > 0 ? Stages<P>::N1 : 1];
-    cpx<R> w2[Stages<P>::N2 > 0 ? Stages<P>::N2 : 1];
+// The twiddles one thread uses in the stages with product NS and after,
+// loaded together at the start of the transform so their latency overlaps the
+// first stage instead of stalling each later one.
+template <typename R, int P, int E, int NS>
+struct StageTwiddles {
+    static constexpr int RAD = stage_radix<P, E, NS>();
+    static constexpr int N = (E / RAD) * (RAD - 1);
+    cpx<R> w[N];
+    StageTwiddles<R, P, E, NS * RAD> next;
 };
+template <typename R, int P, int E>
+struct StageTwiddles<R, P, E, P> {};
 
-template <typename R, int P, int RAD, int NS, int N>
-__device__ __forceinline__ void load_stage_twiddles(cpx<R> (&w)[N], int t) {
-    constexpr int T = LineShape<P>::T;
-    constexpr int NB = 16 / RAD;
+template <typename R, int P, int E, int NS>
+__device__ __forceinline__ void load_twiddles(StageTwiddles<R, P, E, NS>& tw, int t) {
+    if constexpr (NS < P) {
+        constexpr int T = P / E, RAD = stage_radix<P, E, NS>(), NB = E / RAD;
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int jm = (t + T * u) & (NS - 1);
+        for (int u = 0; u < NB; ++u) {
+            const int jm = (t + T * u) & (NS - 1);
 #pragma unroll
-        for (int r = 1; r < RAD; ++r) w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+            for (int r = 1; r < RAD; ++r) tw.w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+        }
+        load_twiddles<R, P, E, NS * RAD>(tw.next, t);
     }
 }
 
-template <typename R, int P>
-__device__ __forceinline__ void load_twiddles(LineTwiddles<R, P>& tw, int t) {
-    if constexpr (Stages<P>::N1 > 0) load_stage_twiddles<R, P, Stages<P>::R1, 16>(tw.w1, t);
-    if constexpr (Stages<P>::N2 > 0) load_stage_twiddles<R, P, Stages<P>::R2, 256>(tw.w2, t);
-}
-
 // One radix-RAD pass with NS = product of the earlier radices. Thread t owns
-// the butterflies j = t + T u, u < 16/RAD; butterfly j reads elements
+// the butterflies j = t + T u, u < E/RAD; butterfly j reads elements
 // j + r P/RAD and writes (j / NS) NS RAD + j % NS + r NS. Element
 // t + T m always lives in register slot m. `w` holds this thread's twiddles
 // exp(-2 pi i r (j mod NS) / (NS RAD)) for u, r >= 1.
-template <typename R, int P, int LS, int RAD, int NS, int NW>
-__device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t, const cpx<R> (&w)[NW]) {
-    constexpr int T = LineShape<P>::T;
-    constexpr int NB = 16 / RAD;
+template <typename R, int P, int E, int LS, int RAD, int NS, int NW>
+__device__ __forceinline__ void fft_stage(cpx<R> (&v)[E], cpx<R>* lds, int t, const cpx<R> (&w)[NW]) {
+    constexpr int T = P / E;
+    constexpr int NB = E / RAD;
     constexpr bool kFirst = (NS == 1);
     constexpr bool kLast = (NS * RAD == P);
     if constexpr (!kFirst) {
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = lds[padi(t + T * m) * LS];
+        for (int m = 0; m < E; ++m) v[m] = lds[padi(t + T * m) * LS];
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -294,29 +294,37 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[16], cpx<R>* lds, int t, c
     }
 }
 
-// Forward DFT (sign -1) of the line whose element t + T m is in v[m]; on
-// return v[m] holds output t + T m. Every thread of the workgroup must call
-// it (it contains barriers). LS is the LDS distance between padded elements.
-template <typename R, int P, int LS>
-__device__ __forceinline__ void fft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
-    static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
-    LineTwiddles<R, P> tw;
-    load_twiddles<R, P>(tw, t);
-    fft_stage<R, P, LS, 16, 1>(v, lds, t, tw.w1);
-    if constexpr (P > 16) {
-        fft_stage<R, P, LS, Stages<P>::R1, 16>(v, lds, t, tw.w1);
-        if constexpr (P > 256) fft_stage<R, P, LS, Stages<P>::R2, 256>(v, lds, t, tw.w2);
+template <typename R, int P, int E, int LS, int NS>
+__device__ __forceinline__ void fft_stages(cpx<R> (&v)[E], cpx<R>* lds, int t, const StageTwiddles<R, P, E, NS>& tw) {
+    if constexpr (NS < P) {
+        constexpr int RAD = stage_radix<P, E, NS>();
+        fft_stage<R, P, E, LS, RAD, NS>(v, lds, t, tw.w);
+        fft_stages<R, P, E, LS, NS * RAD>(v, lds, t, tw.next);
     }
 }
 
+// Forward DFT (sign -1) of the line whose element t + T m is in v[m]; on
+// return v[m] holds output t + T m. Every thread of the workgroup must call
+// it (it contains barriers). LS is the LDS distance between padded elements.
+template <typename R, int P, int E, int LS>
+__device__ __forceinline__ void fft_line(cpx<R> (&v)[E], cpx<R>* lds, int t) {
+    static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
+    static_assert((E == 4 || E == 8 || E == 16) && E <= P, "4, 8 or 16 points per thread");
+    StageTwiddles<R, P, E, E> tw;
+    load_twiddles<R, P, E, E>(tw, t);
+    constexpr cpx<R> none[1] = {};
+    fft_stage<R, P, E, LS, E, 1>(v, lds, t, none);
+    fft_stages<R, P, E, LS, E>(v, lds, t, tw);
+}
+
 // Unnormalised inverse DFT (sign +1) through conj(F(conj(x))).
-template <typename R, int P, int LS>
-__device__ __forceinline__ void ifft_line(cpx<R> (&v)[16], cpx<R>* lds, int t) {
+template <typename R, int P, int E, int LS>
+__device__ __forceinline__ void ifft_line(cpx<R> (&v)[E], cpx<R>* lds, int t) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
-    fft_line<R, P, LS>(v, lds, t);
+    for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
+    fft_line<R, P, E, LS>(v, lds, t);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m].im = -v[m].im;
+    for (int m = 0; m < E; ++m) v[m].im = -v[m].im;
 }
 
 template <typename R>
@@ -337,7 +345,8 @@ __device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
 // that would otherwise leave CUs idle.
 template <int P, bool NARROW = false>
 struct RowShape {
-    static constexpr int T = P / 16;
+    static constexpr int E = row_points(P);
+    static constexpr int T = P / E;
     static constexpr int kWide = (128 / T) >= 1 ? 128 / T : 1;
     static constexpr int B = NARROW ? (kWide >= 2 ? kWide / 2 : 1) : kWide;
     static constexpr int THREADS = T * B;
@@ -374,11 +383,11 @@ __device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, 
 }
 
 // BW > 0 overrides the number of line pairs per workgroup (the caller launches
-// P/16 * BW threads).
+// P/E * BW threads).
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW = false, int BW = 0>
 __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P, NARROW>::T, B = BW > 0 ? BW : RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
+    constexpr int T = RowShape<P, NARROW>::T, B = BW > 0 ? BW : RowShape<P, NARROW>::B, LINE = P + P / 16, E = RowShape<P, NARROW>::E;
     __shared__ C lds[B * LINE];
     const void* __restrict__ in_ = gw.in;
     void* __restrict__ out_ = gw.out;
@@ -387,11 +396,11 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
     const int b = threadIdx.x / T, t = threadIdx.x - b * T;
     const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
     const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
-    C v[16];
+    C v[E];
     if constexpr (IN_KIND == kRowCountsU64) {
         const uint64_t* in = static_cast<const uint64_t*>(in_);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < E; ++m) {
             const int p = t + T * m;
             R x = 0, y = 0;
             if (p < len) {
@@ -408,7 +417,7 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
             row_lags<R, D>(gw, r1, a1, b1);
         }
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < E; ++m) {
             const int p = t + T * m;
             R x = 0, y = 0;
             const bool on = p <= len || p >= P - len;
@@ -428,11 +437,11 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
         }
     }
     C* line = lds + b * LINE;
-    fft_line<R, P, 1>(v, line, t);
+    fft_line<R, P, E, 1>(v, line, t);
     // split Z = X + iY of two real rows: X_k = (Z_k + conj Z_-k)/2, Y_k = (Z_k - conj Z_-k)/(2i)
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < 16; ++m) line[padi(t + T * m)] = v[m];
+    for (int m = 0; m < E; ++m) line[padi(t + T * m)] = v[m];
     __syncthreads();
     const R h = R(0.5);
     for (int k = t; k <= P / 2; k += T) {
@@ -458,7 +467,7 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
 template <typename R, int P, bool MULT, bool NARROW = false>
 __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = LineShape<P>::LDS;
+    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = P + P / 16, E = RowShape<P, NARROW>::E;
     __shared__ C lds[B * LINE];
     const C* __restrict__ in = static_cast<const C*>(a.in);
     const R* __restrict__ mult = static_cast<const R*>(a.mult);
@@ -469,9 +478,9 @@ __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk)
     const int b = threadIdx.x / T, t = threadIdx.x - b * T;
     const int64_t r0 = 2 * (static_cast<int64_t>(blk) * B + b), r1 = r0 + 1;
     const bool ok0 = r0 < nrows, ok1 = r1 < nrows;
-    C v[16];
+    C v[E];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int p = t + T * m;
         const bool upper = p > P / 2;
         const int src = upper ? P - p : p;
@@ -489,9 +498,9 @@ __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk)
         }
         v[m] = C{X.re - Y.im, X.im + Y.re};   // Z = X + iY
     }
-    ifft_line<R, P, 1>(v, lds + b * LINE, t);
+    ifft_line<R, P, E, 1>(v, lds + b * LINE, t);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int p = t + T * m;
         if (p < mout) {
             if (ok0) out[r0 * out_ld + p] = v[m].re * scale;
@@ -508,8 +517,9 @@ __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk)
 // threads (up to 16), or 4 for launches that would otherwise leave CUs idle.
 template <typename R, int P, bool NARROW>
 struct ColShape {
-    static constexpr int T = P / 16;
-    static constexpr int kLineBytes = LineShape<P>::LDS * static_cast<int>(sizeof(cpx<R>));
+    static constexpr int E = col_points(P);
+    static constexpr int T = P / E;
+    static constexpr int kLineBytes = (P + P / 16) * static_cast<int>(sizeof(cpx<R>));
     static constexpr int kCap = 73728 / kLineBytes;                 // at most 72 KiB of LDS
     static constexpr int kThr = 1024 / T;
     static constexpr int kRaw = kCap < kThr ? (kCap < 16 ? kCap : 16) : (kThr < 16 ? kThr : 16);
@@ -519,20 +529,21 @@ struct ColShape {
 };
 
 // BW > 0 overrides the number of lines per workgroup (a power of two; the
-// caller launches P/16 * BW threads).
+// caller launches P/E * BW threads).
 template <typename R, int P, int MODE, bool NARROW, int BW = 0>
 __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_t by) {
     using C = cpx<R>;
-    constexpr int T = ColShape<R, P, NARROW>::T, B = BW > 0 ? BW : ColShape<R, P, NARROW>::B;
-    __shared__ C lds[B * LineShape<P>::LDS];
+    constexpr int T = ColShape<R, P, NARROW>::T, E = ColShape<R, P, NARROW>::E;
+    constexpr int B = BW > 0 ? BW : ColShape<R, P, NARROW>::B;
+    __shared__ C lds[B * (P + P / 16)];
     const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
     const int64_t w = static_cast<int64_t>(bx) * B + b;
     const int64_t o = by;
     const bool act = w < a.W;
     const C* in = static_cast<const C*>(a.in) + o * a.in_os + w;
-    C v[16];
+    C v[E];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
+    for (int m = 0; m < E; ++m) {
         const int p = t + T * m;
         C x{0, 0};
         if constexpr (MODE == kColFwdPrefix || MODE == kColConvLag) {
@@ -549,32 +560,32 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
         // the spectrum of this line: transform of the lag column, placed circularly
         // (it is real because the lag box is centrally symmetric)
         const C* kin = static_cast<const C*>(a.kt) + o * a.kt_os + w;
-        C kv[16];
+        C kv[E];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < E; ++m) {
             const int p = t + T * m;
             const int idx = p <= a.kt_len ? p + a.kt_len : (p >= P - a.kt_len ? p - P + a.kt_len : -1);
             kv[m] = (act && idx >= 0) ? kin[idx * a.kt_ps] : C{0, 0};
         }
-        fft_line<R, P, B>(kv, lds + b, t);
-        fft_line<R, P, B>(v, lds + b, t);
+        fft_line<R, P, E, B>(kv, lds + b, t);
+        fft_line<R, P, E, B>(v, lds + b, t);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = scal(v[m], kv[m].re);
-        ifft_line<R, P, B>(v, lds + b, t);
+        for (int m = 0; m < E; ++m) v[m] = scal(v[m], kv[m].re);
+        ifft_line<R, P, E, B>(v, lds + b, t);
     } else if constexpr (MODE == kColInvPrefix) {
-        ifft_line<R, P, B>(v, lds + b, t);
+        ifft_line<R, P, E, B>(v, lds + b, t);
     } else {
-        fft_line<R, P, B>(v, lds + b, t);
+        fft_line<R, P, E, B>(v, lds + b, t);
     }
     if (!act) return;
     if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
         C* out = static_cast<C*>(a.out) + o * a.out_os + w;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) out[(t + T * m) * a.out_ps] = v[m];
+        for (int m = 0; m < E; ++m) out[(t + T * m) * a.out_ps] = v[m];
     } else {   // kColConvLag (in place) and kColInvPrefix: keep [0, mout)
         C* out = static_cast<C*>(a.out) + o * a.out_os + w;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) {
+        for (int m = 0; m < E; ++m) {
             const int p = t + T * m;
             if (p < a.mout) out[p * a.out_ps] = v[m];
         }

@@ -17,7 +17,15 @@ namespace kde {
 namespace {
 
 template <int P>
-constexpr int spec_pairs() { return kBinThreads / (P / 16); }   // line pairs per workgroup
+constexpr int spec_pairs() {   // row pairs per workgroup
+    static_assert(RowShape<P>::T <= kBinThreads, "a line must fit one binning workgroup");
+    return kBinThreads / RowShape<P>::T;
+}
+template <typename R, int P>
+constexpr int spec_cols() {    // column lines per workgroup
+    static_assert(ColShape<R, P, false>::T <= kBinThreads, "a line must fit one binning workgroup");
+    return kBinThreads / ColShape<R, P, false>::T;
+}
 
 template <int D, typename R, int P>
 __global__ __launch_bounds__(kBinThreads) void hist_kspec_kernel(HistSpecArgs<R> a) {
@@ -29,11 +37,11 @@ __global__ __launch_bounds__(kBinThreads) void hist_kspec_kernel(HistSpecArgs<R>
     bin_hist_body<D>(a.bin, blockIdx.x - ns);
 }
 
-// Scan and the strided pass of the 3-D spectrum: BW = 256 / (P/16) lines per
+// Scan and the strided pass of the 3-D spectrum: BW = 256 / (P/E) lines per
 // workgroup, workgroups walk the (W / BW) x outer grid of the pass, x fastest.
 template <typename R, int P>
 __global__ __launch_bounds__(kBinThreads) void scan_kcol_kernel(ScanColArgs a) {
-    constexpr int BW = spec_pairs<P>();
+    constexpr int BW = spec_cols<R, P>();
     const uint32_t nbx = static_cast<uint32_t>(ceil_div(a.col.W, BW));
     const uint32_t nc = nbx * static_cast<uint32_t>(a.col.outer);
     if (blockIdx.x < nc) {
@@ -45,7 +53,7 @@ __global__ __launch_bounds__(kBinThreads) void scan_kcol_kernel(ScanColArgs a) {
 
 template <typename R, int P>
 hipError_t scan_kcol_launch(const ScanColArgs& a, hipStream_t s) {
-    constexpr int BW = spec_pairs<P>();
+    constexpr int BW = spec_cols<R, P>();
     const dim3 g(static_cast<unsigned>(ceil_div(a.col.W, BW) * a.col.outer + a.bin.g.ntiles)), blk(kBinThreads);
     KDE_LAUNCH((scan_kcol_kernel<R, P>), g, blk, 0, s, a);
     return hipGetLastError();
@@ -91,7 +99,7 @@ hipError_t hist_kspec_any(int P, int d, const void* args, hipStream_t s) {
 }  // namespace
 
 int64_t hist_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
-    return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / 16));
+    return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / row_points(P)));
 }
 
 hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s) {
