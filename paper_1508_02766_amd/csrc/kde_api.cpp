@@ -621,7 +621,7 @@ Pass row_r2c_pass(const Plan& pl, int P, int kind, const void* in, const kde::Ga
     p.d = kind == kde::kRowGaussCirc ? pl.pub.d : 1;
     p.order = order;
     p.name = name;
-    p.blocks = kde::rows_pass_blocks(P, nrows);
+    p.blocks = kde::rows_pass_blocks(P, kind == kde::kRowCountsU64 ? 0 : 1, nrows);
     if (p.prec == KDE_F64)
         p.set_args(kde::make_row_args<double>(in, gl, nrows, in_ld, len, out, out_ld));
     else
@@ -638,7 +638,7 @@ Pass row_c2r_pass(const Plan& pl, int P, const void* in, int64_t nrows, int64_t 
     p.sub = mult ? 1 : 0;
     p.order = order;
     p.name = name;
-    p.blocks = kde::rows_pass_blocks(P, nrows);
+    p.blocks = kde::rows_pass_blocks(P, 2, nrows);
     if (p.prec == KDE_F64)
         p.set_args(kde::make_c2r_args<double>(in, nrows, in_ld, mult, out, out_ld, mout, scale));
     else

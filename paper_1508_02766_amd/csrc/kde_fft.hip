@@ -69,12 +69,12 @@ __global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_
 // ---------------------------------------------------------------------------
 
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW>
-__global__ __launch_bounds__((RowShape<P, NARROW>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
+__global__ __launch_bounds__((RowShape<P, NARROW, row_pass_of(IN_KIND)>::THREADS)) void rows_r2c_kernel(RowArgs<R> a) {
     rows_r2c_body<R, P, IN_KIND, OUT_REAL, D, NARROW>(a, blockIdx.x);
 }
 
 template <typename R, int P, bool MULT, bool NARROW>
-__global__ __launch_bounds__((RowShape<P, NARROW>::THREADS)) void rows_c2r_kernel(C2RArgs<R> a) {
+__global__ __launch_bounds__((RowShape<P, NARROW, kRowPassInv>::THREADS)) void rows_c2r_kernel(C2RArgs<R> a) {
     rows_c2r_body<R, P, MULT, NARROW>(a, blockIdx.x);
 }
 
@@ -106,33 +106,34 @@ hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* la
     return hipGetLastError();
 }
 
-template <typename R, int P, bool NARROW>
-hipError_t rows_r2c_launch_b(int kind, int d, const RowArgs<R>& a, hipStream_t s) {
-    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
-    const dim3 blk(RowShape<P, NARROW>::THREADS);
-    if (kind == kRowCountsU64)
-        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowCountsU64, false, 1, NARROW>), g, blk, 0, s, a);
-    else if (d == 1)
-        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, true, 1, NARROW>), g, blk, 0, s, a);
-    else if (d == 2)
-        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, false, 2, NARROW>), g, blk, 0, s, a);
-    else
-        KDE_LAUNCH((rows_r2c_kernel<R, P, kRowGaussCirc, false, 3, NARROW>), g, blk, 0, s, a);
+template <typename R, int P, int KIND, bool OUT_REAL, int D, bool NARROW>
+hipError_t rows_r2c_go(const RowArgs<R>& a, hipStream_t s) {
+    using S = RowShape<P, NARROW, row_pass_of(KIND)>;
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), S::B))), blk(S::THREADS);
+    KDE_LAUNCH((rows_r2c_kernel<R, P, KIND, OUT_REAL, D, NARROW>), g, blk, 0, s, a);
     return hipGetLastError();
+}
+
+template <typename R, int P, int KIND, bool OUT_REAL, int D>
+hipError_t rows_r2c_pick(const RowArgs<R>& a, hipStream_t s) {
+    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P, false, row_pass_of(KIND)>::B) < kRowNarrowBelow)
+        return rows_r2c_go<R, P, KIND, OUT_REAL, D, true>(a, s);
+    return rows_r2c_go<R, P, KIND, OUT_REAL, D, false>(a, s);
 }
 
 template <typename R, int P>
 hipError_t rows_r2c_launch(int kind, int d, const void* args, hipStream_t s) {
     const RowArgs<R>& a = *static_cast<const RowArgs<R>*>(args);
-    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B) < kRowNarrowBelow)
-        return rows_r2c_launch_b<R, P, true>(kind, d, a, s);
-    return rows_r2c_launch_b<R, P, false>(kind, d, a, s);
+    if (kind == kRowCountsU64) return rows_r2c_pick<R, P, kRowCountsU64, false, 1>(a, s);
+    if (d == 1) return rows_r2c_pick<R, P, kRowGaussCirc, true, 1>(a, s);
+    if (d == 2) return rows_r2c_pick<R, P, kRowGaussCirc, false, 2>(a, s);
+    return rows_r2c_pick<R, P, kRowGaussCirc, false, 3>(a, s);
 }
 
 template <typename R, int P, bool NARROW>
 hipError_t rows_c2r_launch_b(const C2RArgs<R>& a, hipStream_t s) {
-    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), RowShape<P, NARROW>::B)));
-    const dim3 blk(RowShape<P, NARROW>::THREADS);
+    using S = RowShape<P, NARROW, kRowPassInv>;
+    const dim3 g(static_cast<unsigned>(ceil_div(ceil_div(a.nrows, 2), S::B))), blk(S::THREADS);
     if (a.mult)
         KDE_LAUNCH((rows_c2r_kernel<R, P, true, NARROW>), g, blk, 0, s, a);
     else
@@ -143,7 +144,8 @@ hipError_t rows_c2r_launch_b(const C2RArgs<R>& a, hipStream_t s) {
 template <typename R, int P>
 hipError_t rows_c2r_launch(const void* args, hipStream_t s) {
     const C2RArgs<R>& a = *static_cast<const C2RArgs<R>*>(args);
-    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P>::B) < kRowNarrowBelow) return rows_c2r_launch_b<R, P, true>(a, s);
+    if (ceil_div(ceil_div(a.nrows, 2), RowShape<P, false, kRowPassInv>::B) < kRowNarrowBelow)
+        return rows_c2r_launch_b<R, P, true>(a, s);
     return rows_c2r_launch_b<R, P, false>(a, s);
 }
 

@@ -11,13 +11,13 @@ namespace kde {
 namespace {
 
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_r2c_batch(BatchMap m) {
+__global__ __launch_bounds__((RowShape<P, false, row_pass_of(IN_KIND)>::THREADS)) void rows_r2c_batch(BatchMap m) {
     const int i = static_cast<int>(m.owner[blockIdx.x]);
     rows_r2c_body<R, P, IN_KIND, OUT_REAL, D>(static_cast<const RowArgs<R>*>(m.tab)[i], blockIdx.x - m.start[i]);
 }
 
 template <typename R, int P, bool MULT>
-__global__ __launch_bounds__((RowShape<P>::THREADS)) void rows_c2r_batch(BatchMap m) {
+__global__ __launch_bounds__((RowShape<P, false, kRowPassInv>::THREADS)) void rows_c2r_batch(BatchMap m) {
     const int i = static_cast<int>(m.owner[blockIdx.x]);
     rows_c2r_body<R, P, MULT>(static_cast<const C2RArgs<R>*>(m.tab)[i], blockIdx.x - m.start[i]);
 }
@@ -36,7 +36,9 @@ __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_batch(
 
 template <typename R, int P>
 hipError_t rows_r2c_batch_launch(int kind, int d, const BatchMap& m, hipStream_t s) {
-    const dim3 g(m.blocks), blk(RowShape<P>::THREADS);
+    const dim3 g(m.blocks);
+    const dim3 blk(kind == kRowCountsU64 ? RowShape<P, false, kRowPassCounts>::THREADS
+                                         : RowShape<P, false, kRowPassSpec>::THREADS);
     if (kind == kRowCountsU64)
         KDE_LAUNCH((rows_r2c_batch<R, P, kRowCountsU64, false, 1>), g, blk, 0, s, m);
     else if (d == 1)
@@ -50,7 +52,7 @@ hipError_t rows_r2c_batch_launch(int kind, int d, const BatchMap& m, hipStream_t
 
 template <typename R, int P>
 hipError_t rows_c2r_batch_launch(bool mult, const BatchMap& m, hipStream_t s) {
-    const dim3 g(m.blocks), blk(RowShape<P>::THREADS);
+    const dim3 g(m.blocks), blk(RowShape<P, false, kRowPassInv>::THREADS);
     if (mult)
         KDE_LAUNCH((rows_c2r_batch<R, P, true>), g, blk, 0, s, m);
     else
@@ -116,10 +118,13 @@ int cols_lines_per_group(int P, bool narrow) {
     }
 }
 
-int rows_lines_per_group(int P) {
+int rows_lines_per_group(int P, int pass) {
     switch (P) {
-#define KDE_CASE(PP) \
-    case PP: return RowShape<PP>::B;
+#define KDE_CASE(PP)                                                                         \
+    case PP:                                                                                 \
+        return pass == kRowPassCounts ? RowShape<PP, false, kRowPassCounts>::B                \
+                                      : (pass == kRowPassSpec ? RowShape<PP, false, kRowPassSpec>::B \
+                                                              : RowShape<PP, false, kRowPassInv>::B);
         KDE_FOR_EACH_P(KDE_CASE)
 #undef KDE_CASE
         default: return 1;
@@ -128,7 +133,9 @@ int rows_lines_per_group(int P) {
 
 }  // namespace
 
-int64_t rows_pass_blocks(int P, int64_t nrows) { return ceil_div(ceil_div(nrows, 2), rows_lines_per_group(P)); }
+int64_t rows_pass_blocks(int P, int pass, int64_t nrows) {
+    return ceil_div(ceil_div(nrows, 2), rows_lines_per_group(P, pass));
+}
 
 int64_t cols_pass_blocks(int prec, int P, bool narrow, int64_t W, int64_t outer) {
     const int B = prec == 2 ? cols_lines_per_group<double>(P, narrow) : cols_lines_per_group<float>(P, narrow);

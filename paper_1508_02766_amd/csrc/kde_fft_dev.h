@@ -214,12 +214,18 @@ __device__ __forceinline__ int padi(int p) { return p + (p >> 4); }
 // Points per thread E of a line transform of length P: the line's T = P / E
 // threads hold element t + T m in register slot m. E = 16 up to P = 256, where
 // the transform takes at most three stages. Longer lines are few (at most P/2
-// per axis of a grid), so they spread over more threads: the row passes use 4
-// points per thread at P = 512 and 1024, the column passes (three transforms
-// per line in the product pass) 8; beyond, the fewest that keep a line within
-// 256 threads. A function of P and the pass alone: every launch shape of a
-// pass rounds identically.
-__host__ __device__ constexpr int row_points(int P) { return P <= 256 ? 16 : (P <= 1024 ? 4 : P / 256); }
+// per axis of a grid), so they spread over more threads: at P = 512 and 1024
+// the forward row pass of the counts (the first pass after binning, alone on
+// the GPU) uses 4 points per thread, the other row passes and the column
+// passes 8; beyond, the fewest that keep a line within 256 threads. A function
+// of P and the pass alone: every launch shape of a pass rounds identically.
+enum RowPass : int { kRowPassCounts = 0, kRowPassSpec = 1, kRowPassInv = 2 };
+__host__ __device__ constexpr int row_points(int P, int pass) {
+    return P <= 256 ? 16 : (P <= 1024 ? (pass == kRowPassCounts ? 4 : 8) : P / 256);
+}
+__host__ __device__ constexpr int row_pass_of(int in_kind) {
+    return in_kind == kRowCountsU64 ? kRowPassCounts : kRowPassSpec;
+}
 __host__ __device__ constexpr int col_points(int P) { return P <= 256 ? 16 : (P <= 1024 ? 8 : P / 256); }
 
 // Radix of the stage that follows the stages with product NS.
@@ -343,9 +349,9 @@ __device__ __forceinline__ double fexp<double>(double x) { return exp(x); }
 
 // B line pairs per workgroup: 128 threads, or half that (NARROW) for launches
 // that would otherwise leave CUs idle.
-template <int P, bool NARROW = false>
+template <int P, bool NARROW = false, int PASS = kRowPassCounts>
 struct RowShape {
-    static constexpr int E = row_points(P);
+    static constexpr int E = row_points(P, PASS);
     static constexpr int T = P / E;
     static constexpr int kWide = (128 / T) >= 1 ? 128 / T : 1;
     static constexpr int B = NARROW ? (kWide >= 2 ? kWide / 2 : 1) : kWide;
@@ -387,7 +393,8 @@ __device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, 
 template <typename R, int P, int IN_KIND, bool OUT_REAL, int D, bool NARROW = false, int BW = 0>
 __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P, NARROW>::T, B = BW > 0 ? BW : RowShape<P, NARROW>::B, LINE = P + P / 16, E = RowShape<P, NARROW>::E;
+    using S = RowShape<P, NARROW, row_pass_of(IN_KIND)>;
+    constexpr int T = S::T, B = BW > 0 ? BW : S::B, LINE = P + P / 16, E = S::E;
     __shared__ C lds[B * LINE];
     const void* __restrict__ in_ = gw.in;
     void* __restrict__ out_ = gw.out;
@@ -467,7 +474,8 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
 template <typename R, int P, bool MULT, bool NARROW = false>
 __device__ __forceinline__ void rows_c2r_body(const C2RArgs<R>& a, uint32_t blk) {
     using C = cpx<R>;
-    constexpr int T = RowShape<P, NARROW>::T, B = RowShape<P, NARROW>::B, LINE = P + P / 16, E = RowShape<P, NARROW>::E;
+    using S = RowShape<P, NARROW, kRowPassInv>;
+    constexpr int T = S::T, B = S::B, LINE = P + P / 16, E = S::E;
     __shared__ C lds[B * LINE];
     const C* __restrict__ in = static_cast<const C*>(a.in);
     const R* __restrict__ mult = static_cast<const R*>(a.mult);

@@ -18,8 +18,8 @@ namespace {
 
 template <int P>
 constexpr int spec_pairs() {   // row pairs per workgroup
-    static_assert(RowShape<P>::T <= kBinThreads, "a line must fit one binning workgroup");
-    return kBinThreads / RowShape<P>::T;
+    static_assert(RowShape<P, false, kRowPassSpec>::T <= kBinThreads, "a line must fit one binning workgroup");
+    return kBinThreads / RowShape<P, false, kRowPassSpec>::T;
 }
 template <typename R, int P>
 constexpr int spec_cols() {    // column lines per workgroup
@@ -99,7 +99,7 @@ hipError_t hist_kspec_any(int P, int d, const void* args, hipStream_t s) {
 }  // namespace
 
 int64_t hist_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows) {
-    return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / row_points(P)));
+    return nchunk + ceil_div(ceil_div(spec_rows, 2), kBinThreads / (P / row_points(P, kRowPassSpec)));
 }
 
 hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s) {

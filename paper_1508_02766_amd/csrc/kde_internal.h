@@ -253,7 +253,7 @@ struct BatchMap {
 
 // Workgroups one instance needs in a batched launch of each pass.
 int64_t bin_stage_batch_blocks(int stage, const TileGeom& g);
-int64_t rows_pass_blocks(int P, int64_t nrows);
+int64_t rows_pass_blocks(int P, int pass, int64_t nrows);   // pass: 0 counts r2c, 1 spectrum r2c, 2 c2r
 int64_t cols_pass_blocks(int prec, int P, bool narrow, int64_t W, int64_t outer);
 
 hipError_t launch_bin_stage_batch(int stage, int d, const BatchMap& m, size_t lds, hipStream_t s);
