@@ -77,7 +77,7 @@ typedef struct kde_params {
                                  else 1 <= Q and d Q <= 62 */
     int32_t prec;             /* KDE_F32 (also when 0) or KDE_F64 */
     int32_t tile[3];          /* > 0: binning tile extent (cells, a power of two <= 4096) on
-                                 axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 16;
+                                 axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 32;
                                  the product must stay <= 4096. Changes speed and workspace
                                  size, never the counts */
     int32_t extent;           /* lag-box half widths: 0 (default) Eq. (15), tau sqrt(lambda_max)

@@ -69,14 +69,14 @@ struct Plan {
     BinLayout blay;
 };
 
-// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 16 x 16 in
+// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 16 x 32 in
 // 3-D, 1024 in 1-D, or the caller's tile (clamped to the grid), widened until
 // the tile count fits the per-workgroup histogram. Returns false when the
 // tiled path cannot be used: too many cells per tile, records wider than 64
 // bits, or n 2^d >= 2^32.
 bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde::TileGeom* tg, BinLayout* bl) {
     kde::TileGeom g{};
-    static const int base[3][3] = {{1024, 0, 0}, {32, 32, 0}, {8, 16, 16}};
+    static const int base[3][3] = {{1024, 0, 0}, {32, 32, 0}, {8, 16, 32}};
     for (int k = 0; k < d; ++k) {
         int T = tile[k] > 0 ? tile[k] : base[d - 1][k];
         while (T > 1 && T / 2 >= M[k]) T /= 2;
@@ -961,7 +961,7 @@ struct kde_batch {
 namespace {
 
 constexpr int kTuneTiles2[][3] = {{0, 0, 0}, {16, 64, 0}, {64, 16, 0}, {64, 64, 0}, {16, 16, 0}};
-constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 8, 8}, {4, 16, 16}, {16, 16, 16}, {8, 8, 32}};
+constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 16, 16}, {4, 16, 16}, {16, 16, 16}, {4, 32, 32}};
 constexpr int kTuneTiles1[][3] = {{0, 0, 0}, {512, 0, 0}, {2048, 0, 0}, {4096, 0, 0}};
 
 kde_params batch_params(const kde_batch& b, const int tile[3]) {
