@@ -59,16 +59,16 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_batch(BatchMap m) {
     bin_scan_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_scatter_batch(BatchMap m) {
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
     bin_scatter_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
+__global__ __launch_bounds__(kAccumThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_accum_batch(BatchMap m) {
+__global__ __launch_bounds__(kAccumThreads) void bin_accum_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
     bin_accum_body<D>(a, blk);
 }
@@ -153,7 +153,8 @@ int64_t bin_stage_extent(int stage, const TileGeom& g) {
 
 template <int D>
 hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
-    const dim3 blk(kBinThreads), grid(static_cast<unsigned>(bin_stage_extent(stage, a.g)));
+    const dim3 blk(stage == kBinAccum ? kAccumThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
+    const dim3 grid(static_cast<unsigned>(bin_stage_extent(stage, a.g)));
     const size_t lds = bin_stage_lds(stage, a.g);
     switch (stage) {
         case kBinHist: KDE_LAUNCH((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
@@ -167,7 +168,8 @@ hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
 
 template <int D>
 hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream_t s) {
-    const dim3 blk(kBinThreads), grid(m.blocks);
+    const dim3 blk(stage == kBinAccum ? kAccumThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
+    const dim3 grid(m.blocks);
     switch (stage) {
         case kBinHist: KDE_LAUNCH((bin_hist_batch<D>), grid, blk, lds, s, m); break;
         case kBinScan: KDE_LAUNCH((bin_scan_batch<D>), grid, blk, 0, s, m); break;

@@ -50,17 +50,19 @@ __device__ __forceinline__ bool classify(const double* __restrict__ X, int64_t i
     return classify_x<D>(x, c, j, q);
 }
 
-constexpr int kPer = kBinChunk / kBinThreads;   // samples per thread in hist / scatter
+// Samples per thread of a histogram / scatter workgroup of NT threads.
+template <int NT>
+constexpr int per_thread() { return kBinChunk / NT; }
 
-// Loads this thread's kPer samples of chunk `blk` up front so that all their
-// loads are in flight together; rows past n are marked invalid.
-template <int D>
-__device__ __forceinline__ void load_chunk(const double* __restrict__ X, int64_t n, int64_t blk, double (&x)[kPer][D],
-                                           bool (&valid)[kPer]) {
+// Loads this thread's samples of chunk `blk` up front so that all their loads
+// are in flight together; rows past n are marked invalid.
+template <int D, int NT>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ X, int64_t n, int64_t blk,
+                                           double (&x)[per_thread<NT>()][D], bool (&valid)[per_thread<NT>()]) {
     const int64_t base = blk * kBinChunk + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int64_t i = base + static_cast<int64_t>(k) * kBinThreads;
+    for (int k = 0; k < per_thread<NT>(); ++k) {
+        const int64_t i = base + static_cast<int64_t>(k) * NT;
         valid[k] = i < n;
         const int64_t ii = valid[k] ? i : 0;
 #pragma unroll
@@ -101,10 +103,11 @@ __device__ __forceinline__ void for_each_tile(const TileGeom& g, const int (&j)[
     }
 }
 
-// Exclusive scan of a[0..n) in LDS by a 256-thread block; returns the total.
+// Exclusive scan of a[0..n) in LDS by a block of NT threads; returns the total.
+template <int NT>
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, int n, uint32_t* wave_sums) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per = (n + kBinThreads - 1) / kBinThreads;
+    const int per = (n + NT - 1) / NT;
     const int b0 = tid * per < n ? tid * per : n;
     const int b1 = b0 + per < n ? b0 + per : n;
     uint32_t s = 0;
@@ -119,7 +122,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, int n, uin
     __syncthreads();
     uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int w = 0; w < kBinThreads / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
         if (w < wave) before += wave_sums[w];
         total += wave_sums[w];
     }
@@ -148,9 +151,10 @@ __device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
     extern __shared__ uint32_t h[];     // [ntiles]
     __shared__ uint32_t nd;
     const int tid = threadIdx.x;
+    constexpr int kPer = per_thread<kBinThreads>();
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D>(X, n, blk, x, valid);   // in flight while the histogram is cleared
+    load_chunk<D, kBinThreads>(X, n, blk, x, valid);   // in flight while the histogram is cleared
     for (int t = tid; t < g.ntiles; t += kBinThreads) h[t] = 0;
     if (tid == 0) nd = 0;
     __syncthreads();
@@ -268,7 +272,7 @@ __device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
     }
 }
 
-template <int D>
+template <int D, int NT = kScatterThreads>
 __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk) {
     const double* __restrict__ X = a.X;
     const int64_t n = a.n;
@@ -276,49 +280,50 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
     extern __shared__ uint32_t cur[];   // [ntiles] cursors, [ntiles] this chunk's offsets
-    __shared__ uint32_t wave_sums[kBinThreads / 64];
+    __shared__ uint32_t wave_sums[NT / 64];
     uint32_t* aux = cur + g.ntiles;
     const int tid = threadIdx.x;
     const bool lead = blk == 0;
     // The tile totals and this chunk's offsets are loaded before the samples: vector
     // memory loads return in order, so the prologue below waits for them alone while
-    // the samples are still in flight (up to kPre * kBinThreads tiles in registers).
+    // the samples are still in flight (up to kPre * NT tiles in registers).
     constexpr int kPre = 4;
     uint32_t pt[kPre], ph[kPre];
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
-        const int t = tid + m * kBinThreads;
+        const int t = tid + m * NT;
         pt[m] = t < g.ntiles ? w.tot[t] : 0u;
         ph[m] = t < g.ntiles && !lead ? w.hist[static_cast<int64_t>(t) * g.nchunk + blk] : 0u;
     }
+    constexpr int kPer = per_thread<NT>();
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D>(X, n, blk, x, valid);
+    load_chunk<D, NT>(X, n, blk, x, valid);
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
-        const int t = tid + m * kBinThreads;
+        const int t = tid + m * NT;
         if (t < g.ntiles) {
             cur[t] = pt[m];
             aux[t] = ph[m];
         }
     }
-    for (int t = tid + kPre * kBinThreads; t < g.ntiles; t += kBinThreads) {
+    for (int t = tid + kPre * NT; t < g.ntiles; t += NT) {
         cur[t] = w.tot[t];
         if (!lead) aux[t] = w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
     }
     __syncthreads();
-    block_exclusive_scan(cur, g.ntiles, wave_sums);   // cur = tile starts
+    block_exclusive_scan<NT>(cur, g.ntiles, wave_sums);   // cur = tile starts
     if (lead) {
         // the accumulation's work list: tile t owns max(1, ceil(tot / S)) consecutive segments
         // of at most S records; aux first holds the segment counts, then their offsets
-        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+        for (int t = tid; t < g.ntiles; t += NT) {
             const uint32_t cnt = w.tot[t];
             aux[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
         }
         __syncthreads();
-        const uint32_t nsegs = block_exclusive_scan(aux, g.ntiles, wave_sums);
+        const uint32_t nsegs = block_exclusive_scan<NT>(aux, g.ntiles, wave_sums);
         const uint32_t S = static_cast<uint32_t>(g.S);
-        for (int t = tid; t < g.ntiles; t += kBinThreads) {
+        for (int t = tid; t < g.ntiles; t += NT) {
             const uint32_t cnt = w.tot[t];
             const uint32_t end = cur[t] + cnt;
             const uint32_t e = t + 1 < g.ntiles ? aux[t + 1] : nsegs;
@@ -327,10 +332,10 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
                 w.seg[q] = make_uint4(static_cast<uint32_t>(t), r, end - r > S ? r + S : end, cnt > S ? 1u : 0u);
             cur[t] += w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
         }
-        for (int64_t q = nsegs + tid; q < g.max_segments; q += kBinThreads)
+        for (int64_t q = nsegs + tid; q < g.max_segments; q += NT)
             w.seg[q] = make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
     } else {
-        for (int t = tid; t < g.ntiles; t += kBinThreads) cur[t] += aux[t];
+        for (int t = tid; t < g.ntiles; t += NT) cur[t] += aux[t];
     }
     __syncthreads();
 #pragma unroll
@@ -363,23 +368,23 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const uint32_t tile = sd.x, r0 = sd.y, r1 = sd.z;
     const bool shared_tile = sd.w != 0;
     // this thread's records, loaded together
-    constexpr int kRec = kSegment / kBinThreads;
+    constexpr int kRec = kSegment / kAccumThreads;
     uint64_t recs[kRec];
 #pragma unroll
     for (int m = 0; m < kRec; ++m) {
-        const uint32_t r = r0 + tid + m * kBinThreads;
+        const uint32_t r = r0 + tid + m * kAccumThreads;
         recs[m] = r < r1 ? w.records[r] : 0;
     }
     int64_t org[D];
     int ext[D];
     tile_frame<D>(c, g, tile, org, ext);
-    for (int i = tid; i < g.tile_cells; i += kBinThreads) grid[i] = 0;
+    for (int i = tid; i < g.tile_cells; i += kAccumThreads) grid[i] = 0;
     __syncthreads();
     const uint64_t one = 1ull << c.Q;
     const uint64_t qmask = (1ull << g.qbits) - 1;
 #pragma unroll
     for (int m = 0; m < kRec; ++m) {
-        if (r0 + tid + m * kBinThreads >= r1) break;
+        if (r0 + tid + m * kAccumThreads >= r1) break;
         const uint64_t rec = recs[m];
         uint64_t q[D];
         int jl[D];
@@ -408,13 +413,13 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     }
     __syncthreads();
     if (!shared_tile) {
-        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
+        for (int i = tid; i < g.tile_cells; i += kAccumThreads) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
             if (idx >= 0) counts[idx] = grid[i];
         }
     } else {
         auto* cnt = reinterpret_cast<unsigned long long*>(counts);
-        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
+        for (int i = tid; i < g.tile_cells; i += kAccumThreads) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
             if (idx >= 0 && grid[i]) atomicAdd(cnt + idx, grid[i]);
         }

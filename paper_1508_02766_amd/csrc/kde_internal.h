@@ -57,6 +57,8 @@ constexpr int kBinChunk = kBinThreads * 8;    // samples per histogram / scatter
 constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
 constexpr int kMaxTileCells = 4096;
 constexpr int kSegment = 4096;                // records per accumulation segment
+constexpr int kAccumThreads = 1024;           // threads of an accumulation workgroup
+constexpr int kScatterThreads = 512;          // threads of a scatter workgroup (divides kBinChunk)
 
 struct TileGeom {
     int T[3];               // tile extent (cells, power of two) per axis
