@@ -53,7 +53,7 @@ struct BinConsts {
 // tile is summed in LDS, then stored (a tile's only segment) or added to the
 // counts with integer atomics (tiles with several segments).
 constexpr int kBinThreads = 256;
-constexpr int kBinChunk = kBinThreads * 8;    // samples per histogram / scatter workgroup
+constexpr int kBinChunk = 2048;              // samples per histogram / scatter workgroup
 constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
 constexpr int kMaxTileCells = 4096;
 constexpr int kSegment = 4096;                // records per accumulation segment
