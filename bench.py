@@ -171,8 +171,7 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     for _ in range(warmup):
         plain()
     torch.cuda.synchronize()
-    # timed region: K whole steps as a caller runs them (the kernel spectrum on
-    # the library's second stream, overlapping the binning)
+    # timed region: K whole steps as a caller runs them
     t0 = time.perf_counter()
     for _ in range(steps):
         plain()

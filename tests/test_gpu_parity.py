@@ -166,6 +166,10 @@ CONV_CASES = [
     (3, (33, 40, 31), 10, None, 2.0),
     (3, (6, 5, 4), 11, (5, 4, 3), 1.0),    # P = 16: separate row / column passes
     (3, (24, 40, 10), 13, None, 1.0),      # P = (32, 64, 16): P_2 != P_3, separate passes
+    (2, (300, 257), 14, None, 1.0),        # P = 512 on both axes (4 / 8 points per thread)
+    (2, (520, 700), 15, None, 1.0),        # P = 1024 on both axes
+    (3, (7, 9, 300), 16, None, 1.0),       # P_3 = 512: row passes at 4 / 8 points per thread
+    (3, (300, 7, 9), 17, None, 1.0),       # P_1 = 512: product pass at 8 points per thread
 ]
 
 
@@ -174,7 +178,9 @@ CONV_CASES = [
 def test_conv_from_counts(prec, case):
     d, M, seed, Lovr, hs = case
     w = W.small_mixture(seed=seed, d=d, n=4000, M=M, H_scale=hs)
-    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, L=Lovr)
+    # large grids: the oracle's FFT form of Eq. (7) (pinned to the direct sum on the CPU)
+    method = "fft" if np.prod(M) > 200_000 else "direct"
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, L=Lovr, method=method)
     counts = _dev(info["counts"])
     got = K.kde_conv(counts, w.n, w.H, (w.lo, w.hi, w.M), prec=prec, L=Lovr)
     torch.cuda.synchronize()
