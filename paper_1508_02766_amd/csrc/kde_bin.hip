@@ -68,9 +68,9 @@ __global__ __launch_bounds__(kScatterThreads) void bin_scatter_batch(BatchMap m)
 template <int D>
 __global__ __launch_bounds__(kAccumThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
 template <int D>
-__global__ __launch_bounds__(kAccumThreads) void bin_accum_batch(BatchMap m) {
+__global__ __launch_bounds__(kAccumBatchThreads) void bin_accum_batch(BatchMap m) {
     KDE_BATCH_PROLOGUE
-    bin_accum_body<D>(a, blk);
+    bin_accum_body<D, kAccumBatchThreads>(a, blk);
 }
 #undef KDE_BATCH_PROLOGUE
 
@@ -168,7 +168,7 @@ hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
 
 template <int D>
 hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream_t s) {
-    const dim3 blk(stage == kBinAccum ? kAccumThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
+    const dim3 blk(stage == kBinAccum ? kAccumBatchThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
     const dim3 grid(m.blocks);
     switch (stage) {
         case kBinHist: KDE_LAUNCH((bin_hist_batch<D>), grid, blk, lds, s, m); break;

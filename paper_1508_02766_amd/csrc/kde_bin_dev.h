@@ -355,7 +355,7 @@ __device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk)
 // corner weights in LDS, then store the tile (sole segment) or add the
 // segment's sums to the zeroed counts with 64-bit integer atomics (exact, in
 // any order).
-template <int D>
+template <int D, int NT = kAccumThreads>
 __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
@@ -368,23 +368,23 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const uint32_t tile = sd.x, r0 = sd.y, r1 = sd.z;
     const bool shared_tile = sd.w != 0;
     // this thread's records, loaded together
-    constexpr int kRec = kSegment / kAccumThreads;
+    constexpr int kRec = kSegment / NT;
     uint64_t recs[kRec];
 #pragma unroll
     for (int m = 0; m < kRec; ++m) {
-        const uint32_t r = r0 + tid + m * kAccumThreads;
+        const uint32_t r = r0 + tid + m * NT;
         recs[m] = r < r1 ? w.records[r] : 0;
     }
     int64_t org[D];
     int ext[D];
     tile_frame<D>(c, g, tile, org, ext);
-    for (int i = tid; i < g.tile_cells; i += kAccumThreads) grid[i] = 0;
+    for (int i = tid; i < g.tile_cells; i += NT) grid[i] = 0;
     __syncthreads();
     const uint64_t one = 1ull << c.Q;
     const uint64_t qmask = (1ull << g.qbits) - 1;
 #pragma unroll
     for (int m = 0; m < kRec; ++m) {
-        if (r0 + tid + m * kAccumThreads >= r1) break;
+        if (r0 + tid + m * NT >= r1) break;
         const uint64_t rec = recs[m];
         uint64_t q[D];
         int jl[D];
@@ -413,13 +413,13 @@ __device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     }
     __syncthreads();
     if (!shared_tile) {
-        for (int i = tid; i < g.tile_cells; i += kAccumThreads) {
+        for (int i = tid; i < g.tile_cells; i += NT) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
             if (idx >= 0) counts[idx] = grid[i];
         }
     } else {
         auto* cnt = reinterpret_cast<unsigned long long*>(counts);
-        for (int i = tid; i < g.tile_cells; i += kAccumThreads) {
+        for (int i = tid; i < g.tile_cells; i += NT) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
             if (idx >= 0 && grid[i]) atomicAdd(cnt + idx, grid[i]);
         }

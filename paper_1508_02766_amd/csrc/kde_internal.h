@@ -58,6 +58,7 @@ constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most
 constexpr int kMaxTileCells = 4096;
 constexpr int kSegment = 4096;                // records per accumulation segment
 constexpr int kAccumThreads = 1024;           // threads of an accumulation workgroup
+constexpr int kAccumBatchThreads = 256;       // the same in batched launches (many small tiles)
 constexpr int kScatterThreads = 512;          // threads of a scatter workgroup (divides kBinChunk)
 
 struct TileGeom {
