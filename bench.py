@@ -75,7 +75,7 @@ def parse():
                     help="comma-separated side measurements to run")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched measurement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--cpu-reps", type=int, default=11)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
