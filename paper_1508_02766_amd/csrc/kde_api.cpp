@@ -866,9 +866,10 @@ Aux* aux_for(hipStream_t s) {
 // caller's stream after both. With tracing on or overlap off, everything runs
 // in order on the caller's stream. The fork and join cost the host about as
 // much as several kernel launches, so the overlap pays only where the GPU work
-// is large: 3-D problems and batches (measured: 2-D 512^2 60 us serial vs
-// 64 us overlapped; 3-D 128^3 145 vs 147 us; a 256-problem batch 1.10 vs
-// 1.12 ms).
+// is large and the spectrum does not already share the binning's launches:
+// 3-D convolutions from counts and batches (measured with separate spectrum
+// launches: 2-D 512^2 60 us serial vs 64 us overlapped; 3-D 128^3 145 vs
+// 147 us; a 256-problem batch 1.10 vs 1.12 ms).
 template <typename Spec, typename Fwd, typename Inv>
 int run_phases(hipStream_t s, Tracer& tr, bool overlap, Spec&& spec, Fwd&& fwd, Inv&& inv) {
     if (overlap && !tr.on) {
