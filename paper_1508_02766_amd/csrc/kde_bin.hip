@@ -40,15 +40,25 @@ namespace {
 
 #define KDE_BATCH_PROLOGUE                                              \
     const auto* tab = static_cast<const BinArgs*>(m.tab);               \
-    const int inst = static_cast<int>(m.owner[blockIdx.x]);      \
+    const int inst = static_cast<int>(m.owner[blockIdx.x]);             \
     const BinArgs& a = tab[inst];                                       \
     const uint32_t blk = blockIdx.x - m.start[inst];
 
+// The histogram and scatter stages take the chunks in XCD-major order:
+// consecutive chunks write (histogram) and read (scatter) neighbouring words
+// of the tile-major histogram, so they share one L2.
+#define KDE_BATCH_PROLOGUE_XCD                                          \
+    const auto* tab = static_cast<const BinArgs*>(m.tab);               \
+    const uint32_t bid = xcd_major(blockIdx.x, gridDim.x);              \
+    const int inst = static_cast<int>(m.owner[bid]);                    \
+    const BinArgs& a = tab[inst];                                       \
+    const uint32_t blk = bid - m.start[inst];
+
 template <int D>
-__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(BinArgs a) { bin_hist_body<D>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(BinArgs a) { bin_hist_body<D>(a, xcd_major(blockIdx.x, gridDim.x)); }
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void bin_hist_batch(BatchMap m) {
-    KDE_BATCH_PROLOGUE
+    KDE_BATCH_PROLOGUE_XCD
     bin_hist_body<D>(a, blk);
 }
 template <int D>
@@ -59,10 +69,10 @@ __global__ __launch_bounds__(kBinThreads) void bin_scan_batch(BatchMap m) {
     bin_scan_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kScatterThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, blockIdx.x); }
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, xcd_major(blockIdx.x, gridDim.x)); }
 template <int D>
 __global__ __launch_bounds__(kScatterThreads) void bin_scatter_batch(BatchMap m) {
-    KDE_BATCH_PROLOGUE
+    KDE_BATCH_PROLOGUE_XCD
     bin_scatter_body<D>(a, blk);
 }
 template <int D>
@@ -73,6 +83,7 @@ __global__ __launch_bounds__(kAccumBatchThreads) void bin_accum_batch(BatchMap m
     bin_accum_body<D, kAccumBatchThreads>(a, blk);
 }
 #undef KDE_BATCH_PROLOGUE
+#undef KDE_BATCH_PROLOGUE_XCD
 
 // ---------------------------------------------------------------------------
 // atomic path

@@ -358,15 +358,6 @@ struct RowShape {
     static constexpr int THREADS = T * B;
 };
 
-// Workgroup b of a launch of G workgroups, renumbered so that consecutive
-// numbers run on the same XCD: the hardware deals workgroups to the 8 XCDs
-// round robin, so neighbours that share 128-byte segments would otherwise
-// fetch them into eight different L2 caches.
-__device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t G) {
-    const uint32_t x = b & 7u, slot = b >> 3, q = G >> 3, r = G & 7u;
-    return x * q + (x < r ? x : r) + slot;
-}
-
 template <typename R, int D>
 __device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2) {
     R q = g.a00 * l0 * l0;

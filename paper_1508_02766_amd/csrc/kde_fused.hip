@@ -3,10 +3,12 @@
 // For 1-D and 2-D problems the spectrum's row pass is independent of the
 // binning and too small to fill the GPU on its own, and a separate launch (or
 // a second stream) costs more than its work. Here it shares the launch of the
-// histogram pass: the first workgroups run the row transforms of the lag box
-// (Eq. 6 weights computed in place; first, so that they start at once and end
-// under the histogram's longer run), the others the per-chunk histograms of
-// the tiled binning, with the same device code as the separate passes. Built like the binning sources (no floating-point
+// histogram pass: the first workgroups in XCD-major order run the row
+// transforms of the lag box (Eq. 6 weights computed in place; first, so that
+// they start at once and end under the histogram's longer run), the others the
+// per-chunk histograms of the tiled binning, consecutive chunks on one XCD (the
+// chunks' histogram columns share cache lines), with the same device code as
+// the separate passes. Built like the binning sources (no floating-point
 // contraction, no fast-math); the FFT code writes its fused multiply-adds
 // explicitly, so it rounds as in its own launch.
 
@@ -30,11 +32,12 @@ constexpr int spec_cols() {    // column lines per workgroup
 template <int D, typename R, int P>
 __global__ __launch_bounds__(kBinThreads) void hist_kspec_kernel(HistSpecArgs<R> a) {
     const uint32_t ns = static_cast<uint32_t>(ceil_div(ceil_div(a.row.nrows, 2), spec_pairs<P>()));
-    if (blockIdx.x < ns) {
-        rows_r2c_body<R, P, kRowGaussCirc, D == 1, D, false, spec_pairs<P>()>(a.row, blockIdx.x);
+    const uint32_t bx = xcd_major(blockIdx.x, gridDim.x);
+    if (bx < ns) {
+        rows_r2c_body<R, P, kRowGaussCirc, D == 1, D, false, spec_pairs<P>()>(a.row, bx);
         return;
     }
-    bin_hist_body<D>(a.bin, blockIdx.x - ns);
+    bin_hist_body<D>(a.bin, bx - ns);
 }
 
 // Scan and the strided pass of the 3-D spectrum: BW = 256 / (P/E) lines per

@@ -20,6 +20,15 @@ struct KernelTiming {
 };
 KernelTiming& kernel_timing();   // thread-local; defined with the C ABI
 
+// Workgroup b of a launch of G workgroups, renumbered so that consecutive
+// numbers run on the same XCD: the hardware deals workgroups to the 8 XCDs
+// round robin, so neighbours that share 128-byte segments would otherwise
+// fetch them into eight different L2 caches.
+__device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t G) {
+    const uint32_t x = b & 7u, slot = b >> 3, q = G >> 3, r = G & 7u;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 #define KDE_LAUNCH(kernel, grid, block, lds, stream, ...)                                          \
     do {                                                                                           \
         ::kde::KernelTiming& kt_ = ::kde::kernel_timing();                                         \
