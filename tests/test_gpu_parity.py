@@ -119,6 +119,21 @@ def test_bin_heavy_tile_segments(d, M, center):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("n", [1, 2, 511, 2047, 2048, 2049, 16_385])
+def test_bin_chunk_boundaries(d, n):
+    """Sample counts around the 2048-sample chunk of the histogram and scatter passes (a
+    last chunk of one sample, exact multiples, one chunk short of a group of eight)."""
+    rng = np.random.default_rng(700 + 10 * d)
+    X = rng.normal(size=(n, d))
+    lo, hi = np.full(d, -3.0), np.full(d, 3.0)
+    M = {1: (300,), 2: (61, 70), 3: (20, 17, 33)}[d]
+    ref, rnd = O.bin_fixed(X, lo, hi, M)
+    got, gnd = _counts(X, lo, hi, M)
+    assert gnd == rnd
+    assert np.array_equal(got, ref)
+
+
 def test_bin_empty_and_order_independent():
     got, gnd = _counts(np.zeros((0, 2)), [0.0, 0.0], [1.0, 1.0], (8, 8))
     assert gnd == 0 and not got.any()
