@@ -427,49 +427,61 @@ class KdeBatch:
 
     def __init__(self, items, n_dropped: bool = False, dots: bool = False, **opts):
         self._X = []
-        self._H = []
         arr = (KdeBatchItem * len(items))()
-        dev = None
         p, keep = _params(**opts)
         prec = _PREC.get(opts.get("prec"), opts.get("prec"))
         dt = _TDTYPE[prec]
-        self.densities = []
-        self.n_dropped = []
         first = items[0][0]
-        self.dots = torch.zeros(len(items), dtype=torch.float64, device=first.device) if dots else None
+        dev = first.device
+        self.dots = torch.zeros(len(items), dtype=torch.float64, device=dev) if dots else None
+        # one allocation for all densities (and dropped-sample counters): item i's density
+        # starts on a 256-byte boundary at element self._offs[i]; `densities` are views
+        grids = [_grid(item[-1]) for item in items]
+        self._shapes = [_grid_shape(g) for g in grids]
+        esize = torch.empty(0, dtype=dt).element_size()
+        align = 256 // esize
+        offs, total = [], 0
+        for shp in self._shapes:
+            offs.append(total)
+            cells = 1
+            for m in shp:
+                cells *= m
+            total += -(-cells // align) * align
+        self._offs = offs
+        self._dens_buf = torch.empty(max(total, 1), dtype=dt, device=dev)
+        self._nd_buf = torch.empty(len(items), dtype=torch.uint64, device=dev) if n_dropped else None
+        dbase = self._dens_buf.data_ptr()
+        ndbase = self._nd_buf.data_ptr() if n_dropped else 0
+        dotbase = self.dots.data_ptr() if dots else 0
         for i, item in enumerate(items):
             it = arr[i]
+            g = grids[i]
             if len(item) == 4:
-                C, n, H, grid = item
-                g = _grid(grid)
+                C, n, H, _ = item
                 if not (C.is_cuda and C.dtype in (torch.uint64, torch.int64) and C.is_contiguous()):
                     raise TypeError("counts must be a contiguous uint64 CUDA tensor")
                 it.counts = C.data_ptr()
                 it.n = int(n)
                 X = C
             else:
-                X, H, grid = item
-                g = _grid(grid)
+                X, H, _ = item
                 _need_cuda(X, torch.float64, "X")
                 if X.dim() != 2 or X.shape[1] != g.d:
                     raise ValueError("X must be (n, d)")
                 it.X = X.data_ptr()
                 it.n = X.shape[0]
-            dev = X.device if dev is None else dev
-            Hn = np.asarray(H, dtype=np.float64).reshape(g.d, g.d)
-            if dots:
-                it.dot = self.dots.data_ptr() + 8 * i
-            for a in range(g.d):
-                for b in range(g.d):
-                    it.H[a * g.d + b] = float(Hn[a, b])
+            if X.device != dev:
+                raise ValueError("all items of a batch must be on one device")
+            Hn = np.asarray(H, dtype=np.float64)
+            if Hn.size != g.d * g.d:
+                raise ValueError("H must be d x d")
+            it.H[:g.d * g.d] = Hn.ravel().tolist()
             it.grid = g
-            out = torch.empty(_grid_shape(g), dtype=dt, device=dev)
-            it.density = out.data_ptr()
-            self.densities.append(out)
+            it.density = dbase + esize * offs[i]
+            if dots:
+                it.dot = dotbase + 8 * i
             if n_dropped:
-                nd = torch.empty(1, dtype=torch.uint64, device=dev)
-                it.n_dropped = nd.data_ptr()
-                self.n_dropped.append(nd)
+                it.n_dropped = ndbase + 8 * i
             self._X.append(X)
         self.device = dev
         self._params, self._keep = p, keep
@@ -482,6 +494,21 @@ class KdeBatch:
             raise RuntimeError("workspace not 256-byte aligned")
         _check(lib().kde_batch_bind(self._h, _ptr(self.ws), self.ws.numel(), _stream(dev)), "kde_batch_bind")
         self._stream = _stream(dev)
+
+    @property
+    def densities(self) -> list:
+        """One tensor per item (views of the batch's density buffer)."""
+        if getattr(self, "_dens_views", None) is None:
+            self._dens_views = [self._dens_buf[o:o + int(np.prod(shp))].view(shp)
+                                for o, shp in zip(self._offs, self._shapes)]
+        return self._dens_views
+
+    @property
+    def n_dropped(self) -> list:
+        """One single-element uint64 tensor per item (with ``n_dropped=True``)."""
+        if self._nd_buf is None:
+            return []
+        return [self._nd_buf[i:i + 1] for i in range(self._nd_buf.numel())]
 
     def info(self) -> dict:
         inf = KdeBatchInfo()

@@ -91,11 +91,6 @@ def nelder_mead(x0, step: float = 0.25, iters: int = 100, tol: float = 1e-7):
     return pts[i], vals[i], evals
 
 
-def _phi0(H, n, grid, opts) -> float:
-    """phi_H(0) as the library forms it (n k_0), so host and device combine identically."""
-    return K.kde_plan_query(H, n, grid, **{k: v for k, v in opts.items() if k in K._PLAN_OPTS})["norm"] * n
-
-
 def project(H, grid, min_bins: float = 1.0, margin: float = 1.01) -> np.ndarray:
     """The nearest H (same eigenvectors) whose eigenvalues respect the search domain's floor."""
     g = K._grid(grid)
@@ -106,15 +101,32 @@ def project(H, grid, min_bins: float = 1.0, margin: float = 1.01) -> np.ndarray:
     return 0.5 * (Hp + Hp.T)
 
 
-def _admissible(H, n, grid, opts, min_bins: float = 1.0) -> bool:
+def _min_eig(H: np.ndarray) -> float:
+    if H.shape == (1, 1):
+        return float(H[0, 0])
+    if H.shape == (2, 2):   # closed form; LAPACK's call overhead dominates at this size
+        a, b, c = float(H[0, 0]), 0.5 * (float(H[0, 1]) + float(H[1, 0])), float(H[1, 1])
+        return 0.5 * (a + c) - math.hypot(0.5 * (a - c), b)
+    return float(np.linalg.eigvalsh(H)[0])
+
+
+def _admissible_phi0(H, n, grid, opts, min_bins: float = 1.0):
+    """(admissible, phi_H(0)) from one plan query: admissible H have smallest eigenvalue
+    >= (min_bins max delta)^2 and plan (with 2H) within the transform limits; phi_H(0) is
+    formed as the library forms it (n k_0), so host and device combine identically."""
     g = K._grid(grid)
     dmax = max((g.hi[k] - g.lo[k]) / (g.M[k] - 1) for k in range(g.d))
-    if np.linalg.eigvalsh(np.asarray(H, dtype=np.float64))[0] < (min_bins * dmax) ** 2:
-        return False
+    if _min_eig(np.asarray(H, dtype=np.float64)) < (min_bins * dmax) ** 2:
+        return False, math.nan
     try:
-        return K.kde_plan_query(H, n, grid, **{k: v for k, v in opts.items() if k in K._PLAN_OPTS})["lscv_ws_bytes"] > 0
+        p = K.kde_plan_query(H, n, grid, **{k: v for k, v in opts.items() if k in K._PLAN_OPTS})
     except K.KdeError:
-        return False
+        return False, math.nan
+    return p["lscv_ws_bytes"] > 0, p["norm"] * n
+
+
+def _admissible(H, n, grid, opts, min_bins: float = 1.0) -> bool:
+    return _admissible_phi0(H, n, grid, opts, min_bins)[0]
 
 
 def lscv_search(X: torch.Tensor, grid, H0=None, iters: int = 100, step: float = 0.25, min_bins: float = 1.0,
@@ -152,15 +164,17 @@ def lscv_search(X: torch.Tensor, grid, H0=None, iters: int = 100, step: float = 
 def lscv_values_batch(problems, min_bins: float = 1.0, **opts) -> np.ndarray:
     """LSCV(H) of many (counts, n, H, grid) problems through one batched pipeline:
     two items per problem (2H and H) with dot products; inadmissible H give +inf."""
-    items, idx = [], []
+    items, idx, phi0 = [], [], []
     out = np.full(len(problems), math.inf)
     for p, (C, n, H, grid) in enumerate(problems):
         H = np.asarray(H, dtype=np.float64)
-        if not _admissible(H, n, grid, opts, min_bins):
+        ok, f0 = _admissible_phi0(H, n, grid, opts, min_bins)
+        if not ok:
             continue
         items.append((C, n, 2.0 * H, grid))
         items.append((C, n, H, grid))
         idx.append(p)
+        phi0.append(f0)
     if not items:
         return out
     B = K.KdeBatch(items, dots=True, **opts)
@@ -168,11 +182,10 @@ def lscv_values_batch(problems, min_bins: float = 1.0, **opts) -> np.ndarray:
     dots = B.dots.cpu().numpy()
     B.close()
     for k, p in enumerate(idx):
-        C, n, H, grid = problems[p]
-        H = np.asarray(H, dtype=np.float64)
+        n = problems[p][1]
         # the same operations, in the same order, as the device combine of kde_lscv
         t1 = dots[2 * k] / float(n)
-        t2 = 2.0 * (dots[2 * k + 1] - _phi0(H, n, grid, opts)) / (float(n) - 1.0)
+        t2 = 2.0 * (dots[2 * k + 1] - phi0[k]) / (float(n) - 1.0)
         out[p] = t1 - t2
     return out
 

@@ -275,6 +275,17 @@ def test_search_helpers_on_host():
     except StopIteration as stop:
         xb, vb, evals = stop.value
     assert np.allclose(xb, a, atol=1e-5) and abs(vb - 2.0) < 1e-9 and evals > 10
+    # smallest eigenvalue of the admissibility test (closed form for 2 x 2) against LAPACK
+    for d in (1, 2, 3):
+        for _ in range(200):
+            H = W.random_spd(rng, d, ratio=(1.0, 50.0))
+            assert abs(S._min_eig(H) - np.linalg.eigvalsh(H)[0]) <= 1e-12 * np.abs(H).max()
+    # one plan query gives both the admissibility and phi_H(0) = n k_0 of the library
+    g = ((-3.0, -3.0), (3.0, 3.0), (256, 256))
+    H = np.array([[0.05, 0.01], [0.01, 0.04]])
+    ok, f0 = S._admissible_phi0(H, 5000, g, {})
+    assert ok and f0 == K.kde_plan_query(H, 5000, g)["norm"] * 5000
+    assert not S._admissible_phi0(H * 1e-6, 5000, g, {})[0]
 
 
 def test_plan_marginal_extent_matches_oracle():
