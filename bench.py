@@ -378,8 +378,8 @@ def cpu_baseline(W, name: str, reps: int):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {a.gpus}); the design shards independent KDEs "
-              "or haloed slabs across GPUs but this build runs on a single MI355X", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {a.gpus}): independent KDEs or haloed slabs of one "
+              "KDE would shard across GPUs, but this benchmark runs the single-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1508_02766_amd as K

@@ -198,7 +198,7 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
  * Learned bandwidth proposal: a perceptron 24 -> 128 -> 128 -> 128 -> 3 (ReLU)
  * mapping summary features of a sample to Cholesky coordinates of H, trained
  * by mean squared error against LSCV-optimal bandwidths (kde_lscv), with the
- * plain LSCV search kept as fallback and judge. Products on the matrix cores
+ * plain LSCV search kept as fallback and reference. Products on the matrix cores
  * in BF16 with FP32 accumulation; FP32 master parameters and Adam state.
  * State (device, state_bytes, 256-byte aligned, caller-owned) holds the FP32
  * parameters, the Adam moments and the BF16 weight copies. Parameter vector

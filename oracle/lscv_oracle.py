@@ -15,7 +15,7 @@ phi_A the N(0, A) density (K_A of Eq. 1), f the estimate of Eq. (1) and
 f_{-i} the estimate without sample i. The first line is the definition; the
 second uses that the convolution of two N(0, H) densities is N(0, 2H).
 
-Binned form (the reading this build adopts; the paper gives no formula):
+Binned form (the reading adopted here; the paper gives no formula):
 each double sum over sample pairs becomes a double sum over grid counts,
 
     S(A) = sum_j c_j sum_{|l_k| <= L_k(A)} c_{j-l} phi_A(delta l),

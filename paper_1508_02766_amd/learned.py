@@ -4,7 +4,7 @@ A small network maps 24 summary features of a sample to the Cholesky
 coordinates of a bandwidth matrix; it is trained on the GPU (kde_mlp_*
 kernels) against LSCV-optimal bandwidths found by the plain search of
 ``lscv`` on the binned objective, and the plain search stays available as
-fallback and as judge (``evaluate``).
+fallback and as reference (``evaluate``).
 
 Frame: with sample mean m, covariance S = L L' and the normal-scale factor
 c_n = n^(-1/3) (d = 2), a bandwidth is written H = c_n L A L' and the network

@@ -6,7 +6,7 @@ Training mixtures (2-5 components, n log-uniform in [1e3, 1e5]) are drawn,
 featurised and labelled with the LSCV-optimal H of the plain batched search
 chunk by chunk (samples are not kept). The network trains on the features and
 labels; on held-out mixtures at the same grid size the plain search from the
-normal-scale start is the judge: the report gives the mean relative LSCV gap
+normal-scale start is the reference: the report gives the mean relative LSCV gap
 of the normal-scale rule, of the proposal alone and of the plain search
 warm-started at the proposal, with the search evaluations and times.
 """

@@ -1,6 +1,6 @@
 """The learned bandwidth proposal end to end on the GPU: LSCV labels from the
-batched search, training with the network kernels, and the comparison the
-plain search judges. Reduced sizes (hundreds of mixtures, 128^2 grids) so the
+batched search, training with the network kernels, and the comparison with
+the plain search as reference. Reduced sizes (hundreds of mixtures, 128^2 grids) so the
 test runs in seconds; the full-size run is ``python -m
 paper_1508_02766_amd.learned_report``. Reports the LSCV gap and the search
 time saved."""
