@@ -53,6 +53,34 @@ def test_lscv_batch_terms_bit_identical_to_single():
         assert v == s[0]
 
 
+def test_lscv_trace_pairs_time_each_pass():
+    """Traced kde_lscv: one kernel-stamped event pair per pass, the two dot-product stages
+    counted as one pass; the traced call gives the untraced call's bits."""
+    import ctypes
+    hip = K.lib()
+    evs = []
+    for _ in range(64):
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        evs.append(e.value)
+    w = W.small_mixture(130, 2, 3000, 64)
+    g = (w.lo, w.hi, w.M)
+    counts, _ = K.kde_bin(_dev(w.X), g)
+    plain = K.kde_lscv(counts, w.n, w.H, g).cpu().numpy()
+    tr = {}
+    got = K.kde_lscv(counts, w.n, w.H, g, trace_events=evs, trace=tr).cpu().numpy()
+    assert np.array_equal(got, plain)
+    names = tr["names"]
+    assert names.count("dot") == 2 and names[-1] == "lscv_combine" and tr["count"] == len(names)
+    for i in range(tr["count"]):
+        ms = ctypes.c_float()
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(evs[2 * i]),
+                                       ctypes.c_void_p(evs[2 * i + 1])) == 0
+        assert ms.value > 0.0
+    for e in evs:
+        hip.hipEventDestroy(ctypes.c_void_p(e))
+
+
 def test_lscv_rejects_bad_input():
     w = W.small_mixture(130, 2, 100, 32)
     g = (w.lo, w.hi, w.M)
