@@ -32,14 +32,23 @@ def to_theta(H) -> np.ndarray:
 
 
 def from_theta(theta, d: int) -> np.ndarray:
-    R = np.zeros((d, d))
+    """H = R R' from the Cholesky coordinates, summed in plain double arithmetic
+    (exactly symmetric; a search evaluates this once per point, so no array
+    machinery)."""
+    R = [[0.0] * d for _ in range(d)]
     k = 0
     for i in range(d):
         for j in range(i + 1):
-            R[i, j] = math.exp(theta[k]) if i == j else theta[k]
+            R[i][j] = math.exp(theta[k]) if i == j else float(theta[k])
             k += 1
-    H = R @ R.T
-    return 0.5 * (H + H.T)
+    H = np.empty((d, d))
+    for i in range(d):
+        for j in range(i + 1):
+            s = 0.0
+            for m in range(j + 1):
+                s += R[i][m] * R[j][m]
+            H[i, j] = H[j, i] = s
+    return H
 
 
 def normal_scale(X: np.ndarray) -> np.ndarray:
@@ -64,7 +73,10 @@ def nelder_mead(x0, step: float = 0.25, iters: int = 100, tol: float = 1e-7):
         vals = [vals[i] for i in idx]
         if abs(vals[-1] - vals[0]) <= tol * abs(vals[0]):
             break
-        c = np.mean(pts[:-1], axis=0)
+        c = pts[0]                      # centroid of all but the worst, summed in order
+        for q in pts[1:-1]:
+            c = c + q
+        c = c / m
         worst = pts[-1]
         xr = 2.0 * c - worst
         fr = yield xr
