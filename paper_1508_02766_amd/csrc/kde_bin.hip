@@ -44,9 +44,9 @@ namespace {
     const BinArgs& a = tab[inst];                                       \
     const uint32_t blk = blockIdx.x - m.start[inst];
 
-// The histogram and scatter stages take the chunks in XCD-major order:
-// consecutive chunks write (histogram) and read (scatter) neighbouring words
-// of the tile-major histogram, so they share one L2.
+// The batched histogram takes the chunks in XCD-major order: consecutive
+// chunks write neighbouring words of the tile-major histogram, so they share
+// one L2 (the batched scatter measured faster in launch order).
 #define KDE_BATCH_PROLOGUE_XCD                                          \
     const auto* tab = static_cast<const BinArgs*>(m.tab);               \
     const uint32_t bid = xcd_major(blockIdx.x, gridDim.x);              \
@@ -72,7 +72,7 @@ template <int D>
 __global__ __launch_bounds__(kScatterThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, xcd_major(blockIdx.x, gridDim.x)); }
 template <int D>
 __global__ __launch_bounds__(kScatterThreads) void bin_scatter_batch(BatchMap m) {
-    KDE_BATCH_PROLOGUE_XCD
+    KDE_BATCH_PROLOGUE
     bin_scatter_body<D>(a, blk);
 }
 template <int D>
