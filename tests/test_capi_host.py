@@ -299,3 +299,34 @@ def test_plan_marginal_extent_matches_oracle():
         assert tuple(p["L"]) == ref
     with pytest.raises(K.KdeError):
         K.kde_plan_query(np.eye(2), 10, ((-1, -1), (1, 1), (8, 8)), extent=2)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it says so and exits with status 2
+    before touching a device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_counter_record_names_the_sources():
+    """The committed HBM byte counters carry the hash of the device sources they were taken
+    with; bench.py reports them only while that hash matches (else traffic is null)."""
+    import bench
+    import json
+    with open(bench.COUNTERS) as fh:
+        c = json.load(fh)
+    assert len(c["source_sha256"]) == 64
+    for wl in ("mix2d_512", "mix3d_128"):
+        cal = c["copy_calibration"][wl]
+        assert 1.5 < cal["fetch_factor"] < 2.5 and 0.5 < cal["write_factor"] < 1.5
+        assert all(k["FETCH_SIZE"] > 0 for k in c["workloads"][wl].values())
+    if c["source_sha256"] == bench.kernel_source_hash():
+        assert bench.measured_traffic("mix2d_512", "bin_scatter") > 0
+    else:
+        assert bench.measured_traffic("mix2d_512", "bin_scatter") is None
