@@ -75,7 +75,7 @@ def parse():
                     help="comma-separated side measurements to run")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched measurement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-reps", type=int, default=11)
+    ap.add_argument("--cpu-reps", type=int, default=9)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run 5 plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -108,52 +108,94 @@ class Hip:
 
 
 # --------------------------------------------------------------------------
-# algorithmic HBM bytes per launch of each kernel (each input read once, each
-# output written once)
+# HBM bytes per launch. `alg` counts the method's bytes only (the measurement
+# contract of the path): binning reads X once and writes the counts once; the
+# FFT convolution reads the u64 counts, moves the half-spectrum intermediates
+# once per pass (r2c on the contiguous axis), reads a half-space real kernel
+# spectrum once and writes the density. `design` adds what this design moves
+# on top (binning records, histograms, the lag columns the product pass
+# transforms in place).
 # --------------------------------------------------------------------------
 
-def kernel_bytes(name: str, w, plan: dict, prec: str) -> int:
+def conv_method_bytes(d, M, P, prec):
+    """Method bytes of the FFT convolution (counts -> density), per pass, r2c form:
+    2-D: 8 M^2 + 4 M H w_c + P H w_r + M^2 w_r; 3-D: 8 M^3 + 4 M^2 H w_c + 4 M P H w_c
+    + P^2 H w_r + M^3 w_r, with H = P_d / 2 + 1 (1-D: 8 M + 2 H w_c + H w_r + M w_r)."""
+    rs = 4 if prec == "f32" else 8
+    cs = 2 * rs
+    H = P[-1] // 2 + 1
+    cells = int(np.prod(M))
+    if d == 1:
+        return {"counts_r2c": cells * 8 + H * cs, "product_c2r": H * cs + H * rs + cells * rs}
+    if d == 2:
+        rows = M[0] * H * cs
+        return {"counts_r2c": cells * 8 + rows, "conv_col": 2 * rows + P[0] * H * rs, "c2r": rows + cells * rs}
+    plane = M[0] * M[1] * H * cs
+    mid = M[0] * P[1] * H * cs
+    return {"counts_r2c": cells * 8 + plane, "counts_col2": plane + mid, "conv_col1": 2 * mid + P[0] * P[1] * H * rs,
+            "inv_col2": mid + plane, "c2r": plane + cells * rs}
+
+
+def spectrum_bytes(d, L, P, prec):
+    """The kernel spectrum (computed once per H, n and grid): the strided passes of the
+    lag box's transform, in + out (the row pass computes its weights in place)."""
+    cs = 8 if prec == "f32" else 16
+    H = P[-1] // 2 + 1
+    nb = [2 * l + 1 for l in L]
+    if d == 1:
+        return {"kspec_r2c": H * cs // 2}
+    if d == 2:
+        return {"kspec_r2c": nb[0] * H * cs}
+    return {"kspec_r2c": nb[0] * nb[1] * H * cs, "kspec_col2": nb[0] * nb[1] * H * cs + nb[0] * P[1] * H * cs}
+
+
+def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
+    """{"alg": method bytes, "design": bytes this design moves} of one launch."""
     rs = 4 if prec == "f32" else 8
     cs = 2 * rs
     d, M, L, P, n = w.d, w.M, plan["L"], plan["P"], w.n
-    Hl = P[-1] // 2 + 1
+    H = P[-1] // 2 + 1
     cells = int(np.prod(M))
+    x_read, counts_write = n * d * 8, cells * 8
+    records = n * 8            # about one packed 8-byte record per sample (more where cells straddle tiles)
+    conv = conv_method_bytes(d, M, P, prec)
+    spec = spectrum_bytes(d, L, P, prec)
     nb = [2 * l + 1 for l in L]
-    lag = int(np.prod(nb))
-    # binning: the minimum each pass must move (samples read, one 8-byte record per
-    # sample written / read, counts written); the histogram scan and the partial
-    # reduction only touch workspace and count 0
-    common = {
-        "zero_counts": cells * 8, "zero_dropped": 8, "bin": n * d * 8 + cells * 8, "kfill": lag * rs,
-        "bin_hist": n * d * 8, "bin_scan": 0, "bin_scatter": n * d * 8 + n * 8, "bin_accum": n * 8 + cells * 8,
+    # the product pass also reads its lag columns and transforms them in place
+    lagcols = {2: {"conv_col": nb[0] * H * cs - P[0] * H * rs},
+               3: {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs}}.get(d, {})
+    binning = {
+        "zero_counts": (0, cells * 8), "zero_dropped": (0, 8), "bin": (x_read + counts_write, 0),
+        "bin_hist": (x_read, 0), "bin_scan": (0, 0), "bin_scatter": (0, x_read + records),
+        "bin_accum": (counts_write, records),
     }
-    if name in common:
-        return common[name]
-    if d == 1:
-        table = {"kspec_r2c": Hl * rs, "hist_kspec": n * d * 8 + Hl * rs, "counts_r2c": cells * 8 + Hl * cs,
-                 "product_c2r": Hl * cs + Hl * rs + cells * rs}
-    elif d == 2:
-        table = {"kspec_r2c": nb[0] * Hl * cs, "hist_kspec": n * d * 8 + nb[0] * Hl * cs,
-                 "counts_r2c": cells * 8 + M[0] * Hl * cs,
-                 "conv_col": 2 * M[0] * Hl * cs + nb[0] * Hl * cs,
-                 "c2r": M[0] * Hl * cs + cells * rs}
-    else:
-        M0, M1 = M[0], M[1]
-        P1 = P[1]
-        table = {"kspec_r2c": nb[0] * nb[1] * Hl * cs,
-                 "hist_kspec": n * d * 8 + nb[0] * nb[1] * Hl * cs,
-                 "kspec_col2": nb[0] * nb[1] * Hl * cs + nb[0] * P1 * Hl * cs,
-                 "scan_kcol": nb[0] * nb[1] * Hl * cs + nb[0] * P1 * Hl * cs,
-                 "counts_r2c": cells * 8 + M0 * M1 * Hl * cs,
-                 "counts_col2": M0 * M1 * Hl * cs + M0 * P1 * Hl * cs,
-                 "conv_col1": 2 * M0 * P1 * Hl * cs + nb[0] * P1 * Hl * cs,
-                 "inv_col2": M0 * P1 * Hl * cs + M0 * M1 * Hl * cs,
-                 "c2r": M0 * M1 * Hl * cs + cells * rs}
-    return table[name]
+    if name in binning:
+        a, extra = binning[name]
+        return {"alg": a, "design": a + extra}
+    if name == "hist_kspec":
+        return {"alg": x_read + spec["kspec_r2c"], "design": x_read + spec["kspec_r2c"]}
+    if name == "scan_kcol":
+        return {"alg": spec["kspec_col2"], "design": spec["kspec_col2"]}
+    if name == "kfill":
+        return {"alg": int(np.prod(nb)) * rs, "design": int(np.prod(nb)) * rs}
+    if name in spec:
+        return {"alg": spec[name], "design": spec[name]}
+    a = conv[name]
+    return {"alg": a, "design": a + lagcols.get(name, 0)}
 
 
-CONV_KERNELS = {"kspec_r2c", "kspec_col2", "counts_r2c", "counts_col2", "conv_col", "conv_col1", "inv_col2", "c2r",
-                "product_c2r"}
+CONV_KERNELS = {"counts_r2c", "counts_col2", "conv_col", "conv_col1", "inv_col2", "c2r", "product_c2r"}
+SPEC_KERNELS = {"kspec_r2c", "kspec_col2"}
+
+
+def step_roofline(kern: dict, names, alg_bytes: int) -> dict:
+    """Bytes of a whole step of the path over the summed kernel-stamped times of its launches."""
+    us = sum(kern[k]["us"] for k in names if k in kern)
+    if us <= 0:
+        return None
+    gbs = alg_bytes / (us * 1e-6) / 1e9
+    return {"kernels": [k for k in names if k in kern], "us": round(us, 3), "alg_bytes": int(alg_bytes),
+            "achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
@@ -245,13 +287,22 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     for nm in names:
         us = float(np.mean(per[nm])) * 1e3
         b = kernel_bytes(nm, w, plan, prec)
-        kern[nm] = {"us": round(us, 3), "alg_bytes": int(b), "alg_GBs": round(b / (us * 1e-6) / 1e9, 1)}
+        kern[nm] = {"us": round(us, 3), "alg_bytes": int(b["alg"]), "alg_GBs": round(b["alg"] / (us * 1e-6) / 1e9, 1),
+                    "design_bytes": int(b["design"])}
         hbm = measured_traffic(name, nm) if prec == "f32" else None
         if hbm is not None:
             kern[nm]["hbm_bytes"] = hbm
-    conv_us = sum(v["us"] for k, v in kern.items() if k in CONV_KERNELS)
-    bin_us = sum(v["us"] for k, v in kern.items() if k not in CONV_KERNELS)
+    conv_names = [k for k in names if k in CONV_KERNELS]
+    bin_names = [k for k in names if k not in CONV_KERNELS and k not in SPEC_KERNELS]
+    conv_us = sum(kern[k]["us"] for k in conv_names)
+    bin_us = sum(kern[k]["us"] for k in bin_names)
     cells = int(np.prod(w.M))
+    conv_alg = sum(conv_method_bytes(w.d, w.M, plan["P"], prec).values())
+    bin_alg = w.n * w.d * 8 + cells * 8
+    steps_roof = {"binning": step_roofline(kern, bin_names, bin_alg),
+                  "fft_convolution": step_roofline(kern, conv_names, conv_alg)}
+    if steps_roof["binning"] and "hist_kspec" in kern:
+        steps_roof["binning"]["note"] = "hist_kspec also runs the kernel spectrum's row pass beside the histogram"
     return {
         "workload": name, "prec": prec, "n": w.n, "M": list(w.M), "L": list(plan["L"]), "P": list(plan["P"]),
         "ms_per_step": ms_step, "ms_per_step_traced": (u1 - u0) * 1e3 / steps, "gpu_ms_per_step_traced": gpu_step_ms,
@@ -260,6 +311,7 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         "samples_per_s": w.n / (ms_step * 1e-3), "grid_pts_per_s": cells / (ms_step * 1e-3),
         "conv_us": round(conv_us, 3), "conv_grid_pts_per_s": cells / (conv_us * 1e-6),
         "bin_us": round(bin_us, 3), "bin_samples_per_s": w.n / (bin_us * 1e-6), "kernels": kern,
+        "steps": steps_roof,
     }
 
 
@@ -333,15 +385,18 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
     for e in evs:
         hip.destroy(e)
     T.close()
-    alg = {}
+    alg, design = {}, {}
     for w in wl:
         plan = K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M))
         for nm in set(per):
-            alg[nm] = alg.get(nm, 0) + kernel_bytes(nm, w, plan, "f32")
+            b = kernel_bytes(nm, w, plan, "f32")
+            alg[nm] = alg.get(nm, 0) + b["alg"]
+            design[nm] = design.get(nm, 0) + b["design"]
     kern = {}
     for nm, v in per.items():
         us = float(np.sum(v)) / reps * 1e3        # a name can repeat (one launch per padded length)
-        kern[nm] = {"us": round(us, 3), "alg_bytes": int(alg[nm]), "alg_GBs": round(alg[nm] / (us * 1e-6) / 1e9, 1)}
+        kern[nm] = {"us": round(us, 3), "alg_bytes": int(alg[nm]), "alg_GBs": round(alg[nm] / (us * 1e-6) / 1e9, 1),
+                    "design_bytes": int(design[nm])}
     n_tot = int(sum(w.n for w in wl))
     cells = int(sum(np.prod(w.M) for w in wl))
     alg_tot = sum(v["alg_bytes"] for v in kern.values())
@@ -356,23 +411,60 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
         "ms_per_item_calls": round(loop_ms, 4), "speedup_vs_item_calls": round(loop_ms / best, 2),
         "item_calls_bit_identical": bool(same),
         "alg_bytes_per_batch": int(alg_tot), "alg_GBs": round(alg_tot / (best * 1e-3) / 1e9, 1),
-        "hbm_frac": round(alg_tot / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "kernels": kern,
+        "hbm_frac": round(alg_tot / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "design_bytes_per_batch": int(sum(v["design_bytes"] for v in kern.values())), "kernels": kern,
     }
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(W, name: str, reps: int):
+    """The FP64 oracle on the host, over the same workload, in three legs: (i) the direct
+    Eq. (7) sum (the oracle's primary result; `value`), single thread; (ii) the oracle's
+    FFT form with NumPy's single-threaded FFT; (iii) the same FFT form through
+    scipy.fft with one worker per host core. Each leg includes the oracle's binning and
+    lag weights."""
     import oracle as O
     w = W.WORKLOADS[name]()
-    ts = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method="direct")
-        ts.append(time.perf_counter() - t0)
-    t = float(np.median(ts))
-    return {"value": w.n / t, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full FP64 oracle pass{'es' if reps != 1 else ''} over the {name} workload (n={w.n}, grid "
-                      f"{'x'.join(map(str, w.M))}): fixed-point binning, lag weights, direct Eq. (7); "
-                      f"median {t:.2f} s per pass, single thread"}
+    ncpu = os.cpu_count() or 1
+
+    def leg(method, workers, r):
+        ts = []
+        for _ in range(r):
+            t0 = time.perf_counter()
+            O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method=method, workers=workers)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    t_direct = leg("direct", None, reps)
+    fft_reps = max(1, reps // 3)
+    t_fft = leg("fft", None, fft_reps)
+    t_fft_mt = leg("fft", ncpu, fft_reps)
+    legs = {
+        "direct_1thread": {"s_per_pass": round(t_direct, 4), "samples_per_s": round(w.n / t_direct, 1), "cores": 1,
+                           "passes": reps},
+        "fft_numpy_1thread": {"s_per_pass": round(t_fft, 4), "samples_per_s": round(w.n / t_fft, 1), "cores": 1,
+                              "passes": fft_reps},
+        f"fft_scipy_{ncpu}workers": {"s_per_pass": round(t_fft_mt, 4), "samples_per_s": round(w.n / t_fft_mt, 1),
+                                     "cores": ncpu, "passes": fft_reps},
+    }
+    return {"value": round(w.n / t_direct, 1), "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "host_cpu": _cpu_model(), "host_cpu_count": ncpu, "legs": legs,
+            "sample": f"{reps} full FP64 oracle passes over the {name} workload (n={w.n}, grid "
+                      f"{'x'.join(map(str, w.M))}): fixed-point binning, lag weights, direct Eq. (7); median "
+                      f"{t_direct:.2f} s per pass on one thread (value); beside it the oracle's FFT form "
+                      f"(Eq. 12-14) with NumPy ({t_fft:.2f} s) and with scipy.fft on {ncpu} workers "
+                      f"({t_fft_mt:.2f} s), {fft_reps} passes each"}
 
 
 def main():
@@ -400,17 +492,26 @@ def main():
                                                             "ms_per_step_graph", "ms_per_step_reused_spectrum",
                                                             "samples_per_s",
                                                             "grid_pts_per_s", "conv_us", "conv_grid_pts_per_s",
-                                                            "bin_us", "bin_samples_per_s", "kernels")}
+                                                            "bin_us", "bin_samples_per_s", "kernels", "steps")}
         if a.batch > 0 and "batch" in chosen:
             variants[f"batch2d_{a.batch}_f32"] = measure_batch(K, W, hip, a.batch, max(20, a.steps // 4), 5)
-    # roofline of the dominant kernel of the main workload
+    # roofline of the dominant kernel of the main workload (method bytes per launch over its
+    # kernel-stamped average duration), and of the two steps of the path
     kern = main_run["kernels"]
     dom = max(kern, key=lambda k: kern[k]["us"])
     ach = kern[dom]["alg_bytes"] / (kern[dom]["us"] * 1e-6) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(a.workload, dom) if a.prec == "f32" else None,
-            "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_us": kern[dom]["us"]}
+            "alg_bytes_per_launch": kern[dom]["alg_bytes"], "design_bytes_per_launch": kern[dom]["design_bytes"],
+            "avg_launch_us": kern[dom]["us"], "steps": main_run["steps"]}
+    conv_step = main_run["steps"]["fft_convolution"]
+    if conv_step:
+        roof["fft_convolution_target_frac"] = 0.5
+        roof["fft_convolution_gap_to_target"] = round(0.5 - conv_step["frac"], 4)
+    for key, v in variants.items():
+        if "steps" in v:
+            roof[f"steps_{key}"] = v["steps"]
     if a.copy_mb:
         src = torch.ones(a.copy_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -436,6 +537,12 @@ def main():
         "gpu_ms_per_step_traced": round(main_run["gpu_ms_per_step_traced"], 5),
         "kernels": kern, "roofline": roof, "cpu_baseline": cpu, "variants": variants,
     }
+    # the same workload with FP64 transforms (the precision the paper computes in), beside the headline
+    f64 = variants.get(f"{a.workload}_f64")
+    if a.prec == "f32" and f64:
+        line["fp64_same_workload"] = {"ms_per_step": round(f64["ms_per_step"], 5),
+                                      "samples_per_s": round(f64["samples_per_s"], 1),
+                                      "grid_pts_per_s": round(f64["grid_pts_per_s"], 1)}
     print(json.dumps(line))
 
 

@@ -129,6 +129,20 @@ typedef struct kde_plan {
     size_t lscv_ws_bytes;     /* workspace needed by kde_lscv (0 when n < 2) */
 } kde_plan;
 
+/* Grid box from the data (Eq. 3-4; the paper asks for the box [g_k1, g_kM_k]
+ * to contain the data's coordinates on axis k, Section 2): on host memory, no
+ * device work.
+ *     lo_k = min_i X_ik - nsd sqrt(H_kk),   hi_k = max_i X_ik + nsd sqrt(H_kk),
+ * M_k = M on every axis, in FP64 (each bound one square root, one product and
+ * one sum, rounded in that order). X: host, n x d FP64 row-major; samples with
+ * a non-finite coordinate are ignored (binning drops them). H: host, d x d
+ * FP64, checked as kde_plan_query checks it. nsd >= 0 and finite (the
+ * workloads use 3). *out receives d, M, lo and hi.
+ * Errors: KDE_ERR_ARG (null pointer, n < 1, d not in {1,2,3}, M < 2, bad nsd,
+ * no finite sample, or a box with hi_k <= lo_k), KDE_ERR_NOT_SPD (H). */
+int kde_grid_from_data(const double* X, int64_t n, int32_t d, const double* H, double nsd, int64_t M,
+                       kde_grid* out);
+
 /* Plan one problem on the host (no device work, no HIP call).
  * Validates H (Section 1: symmetric positive definite), the grid and the
  * options; computes delta (Eq. 4), lambda_max and L (Eq. 15), the padded
@@ -303,6 +317,27 @@ int kde_batch_eval(const kde_batch* b, hipStream_t stream);
 int kde_batch_tune(kde_batch* b, int32_t reps, hipStream_t stream);
 
 void kde_batch_destroy(kde_batch* b);
+
+/* Batched LSCV objective (bandwidth selection through the binned FFT method,
+ * the use Section 5 points to): one kde_lscv per item, all computed together.
+ * Each item becomes two convolutions (2H, then H) of its counts with FP64 dot
+ * products, as in kde_lscv, and the batch ends with one launch that combines
+ * each item's two dots on the device into item.out. The densities and dots
+ * live in the batch workspace. The result is bit-identical to kde_lscv of the
+ * item with the same params. Validates every item as kde_lscv would (n >= 2,
+ * non-null counts and out, H and 2H within the planner's limits) and returns
+ * the first failing status. The returned batch is used with kde_batch_query
+ * (which counts two items per problem), kde_batch_bind, kde_batch_eval (which
+ * then writes every item.out), kde_batch_tune and kde_batch_destroy. */
+typedef struct kde_lscv_item {
+    const uint64_t* counts;   /* device, prod M_k uint64 fixed-point counts (kde_bin) */
+    int64_t n;                /* sample count, >= 2 */
+    double H[9];              /* bandwidth matrix, d x d row-major in the first d*d entries */
+    kde_grid grid;
+    double* out;              /* device, 3 doubles: {LSCV, first term, second term} */
+} kde_lscv_item;
+
+int kde_lscv_batch_create(const kde_lscv_item* items, int32_t count, const kde_params* params, kde_batch** out);
 
 /* Static description of a status code. */
 const char* kde_strerror(int status);

@@ -239,7 +239,7 @@ def _pow2_at_least(x: int) -> int:
     return p
 
 
-def conv_fft_corrected(c, k, L, P=None) -> np.ndarray:
+def conv_fft_corrected(c, k, L, P=None, workers=None) -> np.ndarray:
     """Corrected FFT algorithm, Eq. (12)-(14), with the discrete convolution theorem (Eq. 10).
 
     k_new holds the whole signed lag box at its top-left corner (lag -L_k at
@@ -247,7 +247,8 @@ def conv_fft_corrected(c, k, L, P=None) -> np.ndarray:
     offset M_k - 1), both zero padded to P_k. The estimate is read at
     0-based positions j + L_k + M_k - 1; for L_k = M_k - 1 that is the 1-based
     window (2M_k - 1) : (3M_k - 2) of Eq. (14). numpy's inverse FFT already
-    divides by prod P_k.
+    divides by prod P_k. ``workers``: run the same transforms through scipy.fft with that
+    many threads (used to time the oracle on several host cores).
     """
     c = np.asarray(c, dtype=np.float64)
     M = c.shape
@@ -258,7 +259,11 @@ def conv_fft_corrected(c, k, L, P=None) -> np.ndarray:
     k_new[tuple(slice(0, 2 * L[a] + 1) for a in range(d))] = k
     c_new = np.zeros(P)
     c_new[tuple(slice(M[a] - 1, 2 * M[a] - 1) for a in range(d))] = c
-    s = np.fft.ifftn(np.fft.fftn(c_new) * np.fft.fftn(k_new)).real
+    if workers:
+        import scipy.fft as sf
+        s = sf.ifftn(sf.fftn(c_new, workers=workers) * sf.fftn(k_new, workers=workers), workers=workers).real
+    else:
+        s = np.fft.ifftn(np.fft.fftn(c_new) * np.fft.fftn(k_new)).real
     return s[tuple(slice(L[a] + M[a] - 1, L[a] + 2 * M[a] - 1) for a in range(d))].copy()
 
 
@@ -341,7 +346,7 @@ def plan(H, lo, hi, M, n, tau: float = TAU_DEFAULT, L=None, Q=None, extent: str 
 
 
 def kde_binned(X, H, lo, hi, M, tau: float = TAU_DEFAULT, L=None, Q=None, method: str = "direct",
-               extent: str = "eigen"):
+               extent: str = "eigen", workers=None):
     """Binned estimate on the grid: linear binning, weights on the lag box, Eq. (7).
 
     Returns (density, info) where info carries counts, n_dropped, L, delta.
@@ -357,7 +362,7 @@ def kde_binned(X, H, lo, hi, M, tau: float = TAU_DEFAULT, L=None, Q=None, method
     if method == "direct":
         f = conv_direct(c, k, p["L"])
     elif method == "fft":
-        f = conv_fft_corrected(c, k, p["L"])
+        f = conv_fft_corrected(c, k, p["L"], workers=workers)
     else:
         raise ValueError(method)
     info = dict(p)

@@ -130,6 +130,43 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
     return true;
 }
 
+// H (d x d, row-major) must be finite, symmetric (|H - H'| <= 1e-12 max|H|)
+// and positive definite (Section 1): Hs = (H + H') / 2 and its Cholesky
+// factor R (lower triangular, Hs = R R').
+int factor_bandwidth(const double* H, int d, double (&Hs)[3][3], double (&R)[3][3]) {
+    double hmax = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            const double v = H[i * d + j];
+            if (!std::isfinite(v)) return KDE_ERR_NOT_SPD;
+            hmax = std::fmax(hmax, std::fabs(v));
+        }
+    if (!(hmax > 0.0)) return KDE_ERR_NOT_SPD;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            if (std::fabs(H[i * d + j] - H[j * d + i]) > 1e-12 * hmax) return KDE_ERR_NOT_SPD;
+            Hs[i][j] = 0.5 * (H[i * d + j] + H[j * d + i]);
+        }
+    for (int j = 0; j < d; ++j) {
+        double s = Hs[j][j];
+        for (int k = 0; k < j; ++k) s -= R[j][k] * R[j][k];
+        if (!(s > 0.0)) return KDE_ERR_NOT_SPD;
+        R[j][j] = std::sqrt(s);
+        for (int i = j + 1; i < d; ++i) {
+            double t = Hs[i][j];
+            for (int k = 0; k < j; ++k) t -= R[i][k] * R[j][k];
+            R[i][j] = t / R[j][j];
+        }
+    }
+    return KDE_OK;
+}
+
+#define KDE_PLAN_CHECK(expr)           \
+    do {                               \
+        const int rc_ = (expr);        \
+        if (rc_ != KDE_OK) return rc_; \
+    } while (0)
+
 // Validation and derived quantities. need_H: validate and factor H;
 // n_min: the smallest admissible sample count (1 where Eq. 1 divides by n).
 int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_grid* g,
@@ -197,31 +234,8 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     // H: finite, symmetric, positive definite
     if (!H) return KDE_ERR_ARG;
     double Hs[3][3] = {};
-    double hmax = 0.0;
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < d; ++j) {
-            const double v = H[i * d + j];
-            if (!std::isfinite(v)) return KDE_ERR_NOT_SPD;
-            hmax = std::fmax(hmax, std::fabs(v));
-        }
-    if (!(hmax > 0.0)) return KDE_ERR_NOT_SPD;
-    for (int i = 0; i < d; ++i)
-        for (int j = 0; j < d; ++j) {
-            if (std::fabs(H[i * d + j] - H[j * d + i]) > 1e-12 * hmax) return KDE_ERR_NOT_SPD;
-            Hs[i][j] = 0.5 * (H[i * d + j] + H[j * d + i]);
-        }
     double R[3][3] = {};
-    for (int j = 0; j < d; ++j) {
-        double s = Hs[j][j];
-        for (int k = 0; k < j; ++k) s -= R[j][k] * R[j][k];
-        if (!(s > 0.0)) return KDE_ERR_NOT_SPD;
-        R[j][j] = std::sqrt(s);
-        for (int i = j + 1; i < d; ++i) {
-            double t = Hs[i][j];
-            for (int k = 0; k < j; ++k) t -= R[i][k] * R[j][k];
-            R[i][j] = t / R[j][j];
-        }
-    }
+    KDE_PLAN_CHECK(factor_bandwidth(H, d, Hs, R));
     double det = 1.0;
     for (int k = 0; k < d; ++k) det *= R[k][k] * R[k][k];
     // inverse of the lower-triangular factor, then H^-1 = R^-T R^-1
@@ -950,6 +964,10 @@ struct kde_batch {
     int narrow_mask = 0;           // bit log2(P): narrow strided passes of length P
     std::vector<Plan> plans;
     std::vector<size_t> inst_off;  // per item: offset of its eval workspace in ws
+    std::vector<char> internal;    // per item: density and dot live in the workspace (LSCV batches)
+    // LSCV batches: problem k combines the dots of items 2k (2H) and 2k + 1 (H)
+    std::vector<kde::LscvJob> lscv;
+    size_t lscv_tab_off = 0;       // offset of the device copy of `lscv` in ws
     size_t table_cap = 0, ws_bytes = 0;
     // the current configuration, laid out for ws
     std::vector<Pass> passes;
@@ -964,6 +982,38 @@ namespace {
 constexpr int kTuneTiles2[][3] = {{0, 0, 0}, {16, 64, 0}, {64, 16, 0}, {64, 64, 0}, {16, 16, 0}};
 constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 16, 16}, {4, 16, 16}, {16, 16, 16}, {4, 32, 32}};
 constexpr int kTuneTiles1[][3] = {{0, 0, 0}, {512, 0, 0}, {2048, 0, 0}, {4096, 0, 0}};
+
+// Workspace of one batch item, relative to its base: the counts and binning
+// workspace (items that bin), the convolution workspace, the dot partials
+// (items with a dot) and, for items whose outputs are internal (LSCV
+// batches), the density and the dot.
+struct ItemLayout {
+    size_t counts = 0, bin = 0, conv = 0, partial = 0, density = 0, dot = 0, total = 0;
+};
+
+ItemLayout item_layout(const kde_batch_item& it, const Plan& pl, bool internal) {
+    ItemLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    if (!it.counts) {
+        L.counts = take(pl.counts_bytes);
+        L.bin = take(pl.pub.bin_ws_bytes);
+    }
+    L.conv = take(pl.pub.conv_ws_bytes);
+    int64_t cells = 1;
+    for (int k = 0; k < pl.pub.d; ++k) cells *= pl.M[k];
+    if (it.dot || internal) L.partial = take(static_cast<size_t>(kde::dot_blocks(cells)) * sizeof(double));
+    if (internal) {
+        L.density = take(pl.pub.density_bytes);
+        L.dot = take(sizeof(double));
+    }
+    L.total = off;
+    return L;
+}
 
 kde_params batch_params(const kde_batch& b, const int tile[3]) {
     kde_params q = b.prm;
@@ -1012,18 +1062,21 @@ int build_groups(kde_batch& b, char* ws, std::vector<Pass>& passes, std::vector<
     for (int i = 0; i < count; ++i) {
         const kde_batch_item& it = b.items[i];
         const Plan& pl = b.plans[i];
+        const ItemLayout lay = item_layout(it, pl, b.internal[i] != 0);
         char* base = ws + b.inst_off[i];
-        uint64_t* own_counts = reinterpret_cast<uint64_t*>(base);
+        uint64_t* own_counts = reinterpret_cast<uint64_t*>(base + lay.counts);
         const uint64_t* counts = it.counts ? it.counts : own_counts;
-        char* bin_ws = base + align_up(pl.counts_bytes);
-        char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
-        auto* partial = reinterpret_cast<double*>(conv_ws + align_up(pl.pub.conv_ws_bytes));
+        char* bin_ws = base + lay.bin;
+        char* conv_ws = base + lay.conv;
+        auto* partial = reinterpret_cast<double*>(base + lay.partial);
+        void* density = b.internal[i] ? static_cast<void*>(base + lay.density) : it.density;
+        double* dot = b.internal[i] ? reinterpret_cast<double*>(base + lay.dot) : it.dot;
         Collect c0(ph[0][i]), c1(ph[1][i]), c2(ph[2][i]);
         KDE_CHECK(run_kspec(pl, conv_ws, b.narrow_mask, c0));
         if (!it.counts) KDE_CHECK(run_bin(pl, it.X, it.n, &it.grid, own_counts, it.n_dropped, bin_ws, c1));
         KDE_CHECK(run_counts_fwd(pl, counts, &it.grid, conv_ws, b.narrow_mask, c1));
-        KDE_CHECK(run_product_inv(pl, &it.grid, it.density, conv_ws, b.narrow_mask, c2));
-        if (it.dot) KDE_CHECK(run_dot(pl, counts, it.density, partial, it.dot, c2));
+        KDE_CHECK(run_product_inv(pl, &it.grid, density, conv_ws, b.narrow_mask, c2));
+        if (dot) KDE_CHECK(run_dot(pl, counts, density, partial, dot, c2));
     }
     for (int phase = 0; phase < 3; ++phase) {
         // all (order, kernel) keys of this phase, by order then first appearance
@@ -1136,6 +1189,20 @@ int rebind(kde_batch& b, hipStream_t s) {
     KDE_CHECK(build_groups(b, b.ws, b.passes, b.groups, tb));
     if (tb > b.table_cap) return KDE_ERR_WS;
     fill_table(b.passes, b.groups, b.table, tb);
+    if (!b.lscv.empty()) {
+        // the combination reads the dots that items 2k and 2k + 1 write into their workspaces
+        for (size_t k = 0; k < b.lscv.size(); ++k)
+            for (int t = 0; t < 2; ++t) {
+                const size_t i = 2 * k + t;
+                const ItemLayout lay = item_layout(b.items[i], b.plans[i], true);
+                const double* dot = reinterpret_cast<const double*>(b.ws + b.inst_off[i] + lay.dot);
+                (t == 0 ? b.lscv[k].dot2H : b.lscv[k].dotH) = dot;
+            }
+        const size_t bytes = b.lscv.size() * sizeof(kde::LscvJob);
+        b.table.resize(b.lscv_tab_off + bytes, 0);
+        std::memcpy(b.table.data() + b.lscv_tab_off, b.lscv.data(), bytes);
+        tb = b.table.size();
+    }
     if (tb > 0) {
         KDE_TRY(hipMemcpyAsync(b.ws, b.table.data(), tb, hipMemcpyHostToDevice, s));
         KDE_TRY(hipStreamSynchronize(s));
@@ -1144,9 +1211,105 @@ int rebind(kde_batch& b, hipStream_t s) {
     return KDE_OK;
 }
 
+// Plans the items, sizes every item's workspace for the largest binning tile
+// shape the autotuner may pick, and reserves the launch tables (and the
+// LSCV job table) at the head of the workspace.
+int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& internal, std::vector<kde::LscvJob>&& jobs,
+                 const kde_params* params, kde_batch** out) {
+    auto* b = new (std::nothrow) kde_batch;
+    if (!b) return KDE_ERR_ARG;
+    const int count = static_cast<int>(items.size());
+    b->items = std::move(items);
+    b->internal = std::move(internal);
+    b->lscv = std::move(jobs);
+    if (params) {
+        b->prm = *params;
+        b->has_prm = true;
+    }
+    for (int k = 0; k < 3; ++k) b->tile[k] = params ? params->tile[k] : 0;
+    const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
+    std::vector<size_t> need(count, 0);
+    size_t cap = 0;
+    int rc = KDE_OK;
+    for (const auto& c : cands) {
+        for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+        rc = layout_batch(*b);
+        if (rc != KDE_OK) break;
+        for (int i = 0; i < count; ++i)
+            need[i] = std::max(need[i], item_layout(b->items[i], b->plans[i], b->internal[i] != 0).total);
+    }
+    if (rc == KDE_OK) {
+        b->inst_off.assign(count, 0);
+        size_t off_items = 0;
+        for (int i = 0; i < count; ++i) {
+            b->inst_off[i] = off_items;
+            off_items += align_up(need[i]);
+        }
+        for (const auto& c : cands) {
+            for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+            size_t tb = 0;
+            rc = layout_batch(*b);
+            if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
+            if (rc != KDE_OK) break;
+            cap = std::max(cap, tb);
+        }
+        b->lscv_tab_off = align_up(cap);
+        b->table_cap = align_up(b->lscv_tab_off + b->lscv.size() * sizeof(kde::LscvJob));
+        for (int i = 0; i < count; ++i) b->inst_off[i] += b->table_cap;
+        b->ws_bytes = b->table_cap + off_items;
+    }
+    if (rc == KDE_OK) {
+        for (int k = 0; k < 3; ++k) b->tile[k] = cands[0][k];
+        rc = layout_batch(*b);
+        size_t tb = 0;
+        if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
+    }
+    if (rc != KDE_OK) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return KDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int kde_grid_from_data(const double* X, int64_t n, int32_t d, const double* H, double nsd, int64_t M,
+                       kde_grid* out) {
+    if (!X || !H || !out || n < 1 || d < 1 || d > 3 || M < 2 || M > (int64_t(1) << 24)) return KDE_ERR_ARG;
+    if (!std::isfinite(nsd) || nsd < 0.0) return KDE_ERR_ARG;
+    double Hs[3][3] = {}, R[3][3] = {};
+    const int rc = factor_bandwidth(H, d, Hs, R);
+    if (rc != KDE_OK) return rc;
+    double mn[3], mx[3];
+    bool any = false;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* x = X + i * d;
+        bool finite = true;
+        for (int k = 0; k < d; ++k) finite = finite && std::isfinite(x[k]);
+        if (!finite) continue;
+        for (int k = 0; k < d; ++k) {
+            mn[k] = any ? std::fmin(mn[k], x[k]) : x[k];
+            mx[k] = any ? std::fmax(mx[k], x[k]) : x[k];
+        }
+        any = true;
+    }
+    if (!any) return KDE_ERR_ARG;
+    kde_grid g{};
+    g.d = d;
+    for (int k = 0; k < d; ++k) {
+        const double s = std::sqrt(H[k * d + k]);
+        const double w = nsd * s;   // separate statements: no contraction into a fused multiply-add
+        g.lo[k] = mn[k] - w;
+        g.hi[k] = mx[k] + w;
+        g.M[k] = M;
+        if (!std::isfinite(g.lo[k]) || !std::isfinite(g.hi[k]) || !(g.hi[k] > g.lo[k])) return KDE_ERR_ARG;
+    }
+    *out = g;
+    return KDE_OK;
+}
 
 int kde_plan_query(const double* H, int64_t n, const kde_grid* grid, const kde_params* params, kde_plan* out) {
     if (!out) return KDE_ERR_ARG;
@@ -1484,69 +1647,44 @@ int kde_batch_create(const kde_batch_item* items, int32_t count, const kde_param
     if (!out) return KDE_ERR_ARG;
     *out = nullptr;
     if (!items || count < 1) return KDE_ERR_ARG;
-    auto* b = new (std::nothrow) kde_batch;
-    if (!b) return KDE_ERR_ARG;
-    b->items.assign(items, items + count);
-    if (params) {
-        b->prm = *params;
-        b->has_prm = true;
+    for (int32_t i = 0; i < count; ++i)
+        if ((!items[i].X && !items[i].counts) || !items[i].density) return KDE_ERR_ARG;
+    return batch_create(std::vector<kde_batch_item>(items, items + count), std::vector<char>(count, 0), {}, params,
+                        out);
+}
+
+int kde_lscv_batch_create(const kde_lscv_item* items, int32_t count, const kde_params* params, kde_batch** out) {
+    if (!out) return KDE_ERR_ARG;
+    *out = nullptr;
+    if (!items || count < 1) return KDE_ERR_ARG;
+    std::vector<kde_batch_item> inner;
+    std::vector<kde::LscvJob> jobs;
+    inner.reserve(2 * static_cast<size_t>(count));
+    jobs.reserve(count);
+    for (int32_t k = 0; k < count; ++k) {
+        const kde_lscv_item& it = items[k];
+        if (!it.counts || !it.out) return KDE_ERR_ARG;
+        Plan p1, p2;
+        LscvLayout L;
+        const int rc = lscv_plans(it.H, it.n, &it.grid, params, &p1, &p2, &L);
+        if (rc != KDE_OK) return rc;
+        // first term with 2H, second with H, as kde_lscv computes them
+        kde_batch_item a{};
+        a.n = it.n;
+        a.grid = it.grid;
+        a.counts = it.counts;
+        const int d = it.grid.d;
+        for (int i = 0; i < d * d; ++i) a.H[i] = 2.0 * it.H[i];
+        inner.push_back(a);
+        for (int i = 0; i < d * d; ++i) a.H[i] = it.H[i];
+        inner.push_back(a);
+        kde::LscvJob j{};
+        j.n = static_cast<double>(it.n);
+        j.phi0 = p1.pub.norm * static_cast<double>(it.n);   // phi_H(0) = n k_0
+        j.out = it.out;
+        jobs.push_back(j);
     }
-    for (const auto& it : b->items)
-        if ((!it.X && !it.counts) || !it.density) {
-            delete b;
-            return KDE_ERR_ARG;
-        }
-    for (int k = 0; k < 3; ++k) b->tile[k] = params ? params->tile[k] : 0;
-    // workspace: per item the largest eval workspace over the binning tile
-    // shapes the autotuner may pick; table region: the largest over the same
-    const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
-    std::vector<size_t> need(count, 0);
-    size_t cap = 0;
-    int rc = KDE_OK;
-    for (const auto& c : cands) {
-        for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
-        rc = layout_batch(*b);
-        if (rc != KDE_OK) break;
-        for (int i = 0; i < count; ++i) {
-            const Plan& pl = b->plans[i];
-            int64_t cells = 1;
-            for (int k = 0; k < pl.pub.d; ++k) cells *= pl.M[k];
-            // eval workspace (counts, binning, convolution) then the dot partials
-            const size_t dot = b->items[i].dot ? static_cast<size_t>(kde::dot_blocks(cells)) * sizeof(double) : 0;
-            need[i] = std::max(need[i], align_up(pl.pub.eval_ws_bytes) + dot);
-        }
-    }
-    if (rc == KDE_OK) {
-        b->inst_off.assign(count, 0);
-        size_t off_items = 0;
-        for (int i = 0; i < count; ++i) {
-            b->inst_off[i] = off_items;
-            off_items += align_up(need[i]);
-        }
-        for (const auto& c : cands) {
-            for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
-            size_t tb = 0;
-            rc = layout_batch(*b);
-            if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
-            if (rc != KDE_OK) break;
-            cap = std::max(cap, tb);
-        }
-        b->table_cap = align_up(cap);
-        for (int i = 0; i < count; ++i) b->inst_off[i] += b->table_cap;
-        b->ws_bytes = b->table_cap + off_items;
-    }
-    if (rc == KDE_OK) {
-        for (int k = 0; k < 3; ++k) b->tile[k] = cands[0][k];
-        rc = layout_batch(*b);
-        size_t tb = 0;
-        if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
-    }
-    if (rc != KDE_OK) {
-        delete b;
-        return rc;
-    }
-    *out = b;
-    return KDE_OK;
+    return batch_create(std::move(inner), std::vector<char>(inner.size(), 1), std::move(jobs), params, out);
 }
 
 int kde_batch_query(const kde_batch* b, kde_batch_info* info) {
@@ -1575,10 +1713,18 @@ int kde_batch_eval(const kde_batch* b, hipStream_t stream) {
     const kde_params* prm = b->has_prm ? &b->prm : nullptr;
     Tracer tr(prm, stream);
     KDE_CHECK(tr.start());
-    const int r = run_phases(
+    int r = run_phases(
         stream, tr, true, [&](hipStream_t s) { return run_batch_phase(*b, 0, s, tr); },
         [&](hipStream_t s) { return run_batch_phase(*b, 1, s, tr); },
         [&](hipStream_t s) { return run_batch_phase(*b, 2, s, tr); });
+    if (r == KDE_OK && !b->lscv.empty()) {
+        const auto* jobs = reinterpret_cast<const kde::LscvJob*>(b->ws + b->lscv_tab_off);
+        r = tr.pass("lscv_combine", [&] {
+            return kde::launch_lscv_combine_batch(jobs, static_cast<int>(b->lscv.size()), stream) == hipSuccess
+                       ? KDE_OK
+                       : KDE_ERR_HIP;
+        });
+    }
     tr.finish();
     return r;
 }

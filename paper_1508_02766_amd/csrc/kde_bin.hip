@@ -22,8 +22,9 @@
 //              one segment is stored with plain writes, the segments of
 //              other tiles are added to the counts with 64-bit integer
 //              atomics (one per nonzero cell and segment; exact in any order)
-//   The accumulate workgroups rebuild the segment -> tile map from the tile
-//   totals in LDS, so no pass ends waiting on one workgroup's bookkeeping.
+//   The scatter's workgroup 0 also writes the accumulation's work list (one
+//   descriptor per segment: tile, record range, shared flag), which each
+//   accumulation workgroup reads with one load.
 //   A sample whose corners straddle a tile edge gets one record per tile it
 //   touches, so every cell belongs to exactly one tile.
 // * atomic (fallback when a record does not fit in 64 bits or the grid needs

@@ -295,6 +295,16 @@ hipError_t launch_dot_batch(int prec, bool final_stage, const BatchMap& m, hipSt
 // out[0..2] = {LSCV, dots[0] / n, 2 (dots[1] - phi0) / (n - 1)}.
 hipError_t launch_lscv_combine(const double* dots, double n, double phi0, double* out, hipStream_t s);
 
+// The same combination for `count` problems of a batch (one thread each).
+struct LscvJob {
+    const double* dot2H;    // sum_j c_j f_j with bandwidth 2H
+    const double* dotH;     // the same with H
+    double n;
+    double phi0;            // phi_H(0) = n k_0
+    double* out;            // {LSCV, first term, second term}
+};
+hipError_t launch_lscv_combine_batch(const LscvJob* jobs, int count, hipStream_t s);
+
 // Learned bandwidth proposal network (kde_mlp.hip): 32 -> 128 -> 128 -> 128 -> 16.
 constexpr int kMlpIn = 24, kMlpInPad = 32, kMlpHid = 128, kMlpOut = 3, kMlpOutPad = 16, kMlpRows = 64;
 // FP32 parameter vector: W1 (k-major, 32 x 128), b1, W2, b2, W3, b3, W4 (128 x 16), b4

@@ -82,6 +82,17 @@ __global__ __launch_bounds__(64) void lscv_combine_kernel(const double* __restri
     out[2] = t2;
 }
 
+__global__ __launch_bounds__(64) void lscv_combine_batch_kernel(const LscvJob* __restrict__ jobs, int count) {
+    const int k = static_cast<int>(blockIdx.x) * 64 + static_cast<int>(threadIdx.x);
+    if (k >= count) return;
+    const LscvJob j = jobs[k];
+    const double t1 = j.dot2H[0] / j.n;
+    const double t2 = 2.0 * (j.dotH[0] - j.phi0) / (j.n - 1.0);
+    j.out[0] = t1 - t2;
+    j.out[1] = t1;
+    j.out[2] = t2;
+}
+
 }  // namespace
 
 int64_t dot_blocks(int64_t cells) { return (cells + kDotChunk - 1) / kDotChunk; }
@@ -112,6 +123,12 @@ hipError_t launch_dot_batch(int prec, bool final_stage, const BatchMap& m, hipSt
 
 hipError_t launch_lscv_combine(const double* dots, double n, double phi0, double* out, hipStream_t s) {
     KDE_LAUNCH(lscv_combine_kernel, dim3(1), dim3(64), 0, s, dots, n, phi0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lscv_combine_batch(const LscvJob* jobs, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    KDE_LAUNCH(lscv_combine_batch_kernel, dim3(static_cast<unsigned>((count + 63) / 64)), dim3(64), 0, s, jobs, count);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@ Argument marshalling only: every step of the estimate runs in the library's
 HIP kernels. PyTorch supplies device memory (tensors) and the current stream.
 The names and semantics follow include/kde.h:
 
+    kde_grid_from_data(X, H, M, nsd)            -> KdeGrid (host, data range +- nsd sqrt(H_kk))
     kde_plan_query(H, n, grid, **opts)          -> dict (host planner, no device work)
     kde_bin(X, grid, **opts)                    -> (counts, n_dropped)
     kde_kernel_grid(H, n, grid, **opts)         -> lag-box weights
@@ -11,6 +12,7 @@ The names and semantics follow include/kde.h:
     kde_eval(X, H, grid, **opts)                -> (density, n_dropped)
     kde_lscv(counts, n, H, grid, **opts)        -> LSCV objective and its two terms
     KdeBatch(items, **opts)                     -> kde_batch_create / _bind / _eval / _tune
+    KdeLscvBatch(problems, **opts)              -> kde_lscv_batch_create, then the same calls
     kde_strerror(code)                          -> str
 
 ``grid`` is ``(lo, hi, M)`` (per-axis sequences) or a ``KdeGrid``. Options:
@@ -72,6 +74,11 @@ class KdeBatchItem(ctypes.Structure):
                 ("dot", ctypes.c_void_p)]
 
 
+class KdeLscvItem(ctypes.Structure):
+    _fields_ = [("counts", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * 9), ("grid", KdeGrid),
+                ("out", ctypes.c_void_p)]
+
+
 class KdeBatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("launches", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t),
                 ("tile", ctypes.c_int32 * 3), ("narrow_mask", ctypes.c_int32)]
@@ -84,9 +91,10 @@ class KdeMlpInfo(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_mlp_query", "kde_mlp_load", "kde_mlp_forward",
+EXPORTS = ("kde_grid_from_data", "kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_mlp_query", "kde_mlp_load", "kde_mlp_forward",
            "kde_mlp_grad", "kde_mlp_train_step", "kde_batch_create",
            "kde_batch_query", "kde_batch_bind", "kde_batch_eval", "kde_batch_tune", "kde_batch_destroy",
+           "kde_lscv_batch_create",
            "kde_strerror")
 
 
@@ -104,6 +112,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(_LIB_PATH)
         vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
         G, Pp = ctypes.POINTER(KdeGrid), ctypes.POINTER(KdeParams)
+        L.kde_grid_from_data.argtypes = [vp, i64, ctypes.c_int32, vp, ctypes.c_double, i64, G]
         L.kde_plan_query.argtypes = [vp, i64, G, Pp, ctypes.POINTER(KdePlan)]
         L.kde_bin.argtypes = [vp, i64, G, Pp, vp, vp, vp, sz, vp]
         L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
@@ -116,6 +125,7 @@ def lib() -> ctypes.CDLL:
         L.kde_mlp_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]
         L.kde_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, ctypes.c_int32, vp, vp, sz, vp]
         L.kde_batch_create.argtypes = [ctypes.POINTER(KdeBatchItem), ctypes.c_int32, Pp, ctypes.POINTER(vp)]
+        L.kde_lscv_batch_create.argtypes = [ctypes.POINTER(KdeLscvItem), ctypes.c_int32, Pp, ctypes.POINTER(vp)]
         L.kde_batch_query.argtypes = [vp, ctypes.POINTER(KdeBatchInfo)]
         L.kde_batch_bind.argtypes = [vp, vp, sz, vp]
         L.kde_batch_eval.argtypes = [vp, vp]
@@ -226,6 +236,25 @@ def _ptr(t) -> ctypes.c_void_p:
 # ---------------------------------------------------------------------------
 # entry points
 # ---------------------------------------------------------------------------
+
+def kde_grid_from_data(X, H, M: int, nsd: float = 3.0) -> KdeGrid:
+    """Grid box around host samples X (n, d): data range widened by nsd sqrt(H_kk) per side."""
+    Xn = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+    if Xn.ndim != 2:
+        raise ValueError("X must be (n, d)")
+    n, d = Xn.shape
+    Hn, Hp = _H(H, d)
+    g = KdeGrid()
+    _check(lib().kde_grid_from_data(Xn.ctypes.data_as(ctypes.c_void_p), n, d, Hp, float(nsd), int(M),
+                                    ctypes.byref(g)), "kde_grid_from_data")
+    return g
+
+
+def grid_tuple(g: KdeGrid):
+    """(lo, hi, M) of a KdeGrid as NumPy arrays and a tuple."""
+    return (np.array([g.lo[k] for k in range(g.d)]), np.array([g.hi[k] for k in range(g.d)]),
+            tuple(int(g.M[k]) for k in range(g.d)))
+
 
 def kde_plan_query(H, n: int, grid, **opts) -> dict:
     """Host plan; with H None only the binning quantities are filled (n >= 0)."""
@@ -540,6 +569,55 @@ class KdeBatch:
             self.close()
         except Exception:
             pass
+
+
+class KdeLscvBatch:
+    """LSCV objectives of many problems in one batched pipeline (kde_lscv_batch_create).
+
+    ``problems`` is a sequence of ``(counts, n, H, grid)`` with fixed-point
+    counts (uint64 CUDA tensor, as kde_bin writes them). ``self.out`` (float64,
+    problems x 3) receives {LSCV, first term, second term} of every problem at
+    each ``eval()``, bit-identical to kde_lscv of the same problem.
+    """
+
+    def __init__(self, problems, **opts):
+        arr = (KdeLscvItem * len(problems))()
+        p, keep = _params(**opts)
+        dev = problems[0][0].device
+        self.out = torch.empty((len(problems), 3), dtype=torch.float64, device=dev)
+        self._counts = []
+        base = self.out.data_ptr()
+        for i, (C, n, H, grid) in enumerate(problems):
+            if not (C.is_cuda and C.dtype in (torch.uint64, torch.int64) and C.is_contiguous()):
+                raise TypeError("counts must be a contiguous uint64 CUDA tensor")
+            if C.device != dev:
+                raise ValueError("all problems of a batch must be on one device")
+            g = _grid(grid)
+            Hn = np.asarray(H, dtype=np.float64)
+            if Hn.size != g.d * g.d:
+                raise ValueError("H must be d x d")
+            it = arr[i]
+            it.counts = C.data_ptr()
+            it.n = int(n)
+            it.H[:g.d * g.d] = Hn.ravel().tolist()
+            it.grid = g
+            it.out = base + 24 * i
+            self._counts.append(C)
+        self.device = dev
+        self._params, self._keep, self._items = p, keep, arr
+        h = ctypes.c_void_p(0)
+        _check(lib().kde_lscv_batch_create(arr, len(problems), ctypes.byref(p), ctypes.byref(h)),
+               "kde_lscv_batch_create")
+        self._h = h
+        self.ws = torch.empty(max(self.info()["ws_bytes"], 1), dtype=torch.uint8, device=dev)
+        _check(lib().kde_batch_bind(self._h, _ptr(self.ws), self.ws.numel(), _stream(dev)), "kde_batch_bind")
+
+    info = KdeBatch.info
+    eval = KdeBatch.eval
+    tune = KdeBatch.tune
+    trace = KdeBatch.trace
+    close = KdeBatch.close
+    __del__ = KdeBatch.__del__
 
 
 def mlp_query(batch: int = 0) -> dict:

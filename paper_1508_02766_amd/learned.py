@@ -69,8 +69,8 @@ def from_target(t, X) -> np.ndarray:
 def grid_for(X, M: int = 256):
     """Grid box: the data range widened by 3 marginal normal-scale bandwidth SDs."""
     c, L = frame(X)
-    s = np.sqrt(np.diag(c * L @ L.T))
-    return (X.min(axis=0) - 3 * s, X.max(axis=0) + 3 * s, (M, M))
+    H = c * L @ L.T
+    return K.grid_tuple(K.kde_grid_from_data(X, 0.5 * (H + H.T), M, 3.0))
 
 
 def mixtures(count: int, seed: int, n_range=(1e3, 1e5)):

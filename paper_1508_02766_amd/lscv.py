@@ -1,8 +1,8 @@
 """Plain least-squares cross-validation (LSCV) bandwidth search.
 
-The objective is evaluated on the GPU (``kde_lscv`` for one problem, the
-batched pipeline with counts items and dot products for many); this module
-holds only the host-side search: a Nelder-Mead simplex over the Cholesky
+The objective is evaluated on the GPU (``kde_lscv`` for one problem,
+``kde_lscv_batch_create`` for many, each combining its terms on the device);
+this module holds only the host-side search: a Nelder-Mead simplex over the Cholesky
 coordinates of H, started from the normal-scale matrix.
 
 Coordinates: H = R R' with R lower triangular, theta = (log R_11, R_21,
@@ -174,31 +174,24 @@ def lscv_search(X: torch.Tensor, grid, H0=None, iters: int = 100, step: float = 
 
 
 def lscv_values_batch(problems, min_bins: float = 1.0, **opts) -> np.ndarray:
-    """LSCV(H) of many (counts, n, H, grid) problems through one batched pipeline:
-    two items per problem (2H and H) with dot products; inadmissible H give +inf."""
-    items, idx, phi0 = [], [], []
+    """LSCV(H) of many (counts, n, H, grid) problems through one batched pipeline
+    (kde_lscv_batch_create: two convolutions and dots per problem, combined on
+    the device); inadmissible H give +inf."""
+    items, idx = [], []
     out = np.full(len(problems), math.inf)
     for p, (C, n, H, grid) in enumerate(problems):
         H = np.asarray(H, dtype=np.float64)
-        ok, f0 = _admissible_phi0(H, n, grid, opts, min_bins)
-        if not ok:
+        if not _admissible(H, n, grid, opts, min_bins):
             continue
-        items.append((C, n, 2.0 * H, grid))
         items.append((C, n, H, grid))
         idx.append(p)
-        phi0.append(f0)
     if not items:
         return out
-    B = K.KdeBatch(items, dots=True, **opts)
+    B = K.KdeLscvBatch(items, **opts)
     B.eval()
-    dots = B.dots.cpu().numpy()
+    vals = B.out[:, 0].cpu().numpy()
     B.close()
-    for k, p in enumerate(idx):
-        n = problems[p][1]
-        # the same operations, in the same order, as the device combine of kde_lscv
-        t1 = dots[2 * k] / float(n)
-        t2 = 2.0 * (dots[2 * k + 1] - phi0[k]) / (float(n) - 1.0)
-        out[p] = t1 - t2
+    out[np.asarray(idx)] = vals
     return out
 
 

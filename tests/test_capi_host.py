@@ -330,3 +330,91 @@ def test_bench_counter_record_names_the_sources():
         assert bench.measured_traffic("mix2d_512", "bin_scatter") > 0
     else:
         assert bench.measured_traffic("mix2d_512", "bin_scatter") is None
+
+
+# --------------------------------------------------------------------------
+# grid rule (Eq. 3-4 with the data-range reading) and batched LSCV planning
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["mix2d_small", "mix2d_512", "mix3d_128"])
+def test_grid_from_data_matches_workload_boxes(name):
+    """The library's grid rule reproduces the boxes the workloads use, bit for bit."""
+    w = W.WORKLOADS[name]()
+    g = K.kde_grid_from_data(w.X, w.H, w.M[0], 3.0)
+    lo, hi, M = K.grid_tuple(g)
+    assert np.array_equal(lo, w.lo) and np.array_equal(hi, w.hi) and M == tuple(w.M)
+
+
+def test_grid_from_data_hand_values():
+    X = np.array([[0.0, 1.0], [2.0, -1.0], [1.0, 5.0], [np.nan, 100.0], [1.0, np.inf]])
+    H = np.array([[0.25, 0.1], [0.1, 4.0]])
+    lo, hi, M = K.grid_tuple(K.kde_grid_from_data(X, H, 40, 2.0))
+    # non-finite samples ignored; sqrt(H_kk) = 0.5 and 2, times 2
+    assert np.array_equal(lo, [0.0 - 1.0, -1.0 - 4.0]) and np.array_equal(hi, [2.0 + 1.0, 5.0 + 4.0])
+    assert M == (40, 40)
+    lo, hi, _ = K.grid_tuple(K.kde_grid_from_data(X[:3, :1], [[0.04]], 8, 0.0))
+    assert lo[0] == 0.0 and hi[0] == 2.0
+
+
+def test_grid_from_data_errors():
+    lib = K.lib()
+    H = np.array([[0.09, 0.06], [0.06, 0.08]])
+    X = np.array([[0.0, 1.0], [2.0, -1.0]])
+    Xp, Hp = X.ctypes.data_as(ctypes.c_void_p), H.ctypes.data_as(ctypes.c_void_p)
+    g = KB.KdeGrid()
+    call = lambda Xq, n, d, Hq, nsd, M, out: lib.kde_grid_from_data(Xq, n, d, Hq, nsd, M, out)
+    assert call(Xp, 2, 2, Hp, 3.0, 64, ctypes.byref(g)) == 0 and g.d == 2
+    assert call(None, 2, 2, Hp, 3.0, 64, ctypes.byref(g)) == -1          # no samples
+    assert call(Xp, 0, 2, Hp, 3.0, 64, ctypes.byref(g)) == -1            # n < 1
+    assert call(Xp, 2, 4, Hp, 3.0, 64, ctypes.byref(g)) == -1            # d outside {1, 2, 3}
+    assert call(Xp, 2, 2, Hp, 3.0, 1, ctypes.byref(g)) == -1             # M < 2
+    assert call(Xp, 2, 2, Hp, -1.0, 64, ctypes.byref(g)) == -1           # negative nsd
+    assert call(Xp, 2, 2, Hp, float("nan"), 64, ctypes.byref(g)) == -1
+    assert call(Xp, 2, 2, Hp, 3.0, 64, None) == -1
+    one = np.array([[1.0, 1.0]])
+    assert call(one.ctypes.data_as(ctypes.c_void_p), 1, 2, Hp, 0.0, 64, ctypes.byref(g)) == -1   # hi == lo
+    nanX = np.full((3, 2), np.nan)
+    assert call(nanX.ctypes.data_as(ctypes.c_void_p), 3, 2, Hp, 3.0, 64, ctypes.byref(g)) == -1  # no finite sample
+    bad = np.array([[0.09, 0.2], [0.2, 0.08]])
+    assert call(Xp, 2, 2, bad.ctypes.data_as(ctypes.c_void_p), 3.0, 64, ctypes.byref(g)) == -2
+
+
+def _lscv_items(probs):
+    arr = (KB.KdeLscvItem * len(probs))()
+    for i, (n, H, grid) in enumerate(probs):
+        g = KB.make_grid(*grid)
+        arr[i].counts = 0x10000 + i * 0x1000
+        arr[i].n = n
+        Hn = np.asarray(H, dtype=np.float64).reshape(g.d, g.d)
+        arr[i].H[:g.d * g.d] = Hn.ravel().tolist()
+        arr[i].grid = g
+        arr[i].out = 0x90000 + i * 0x100
+    return arr
+
+
+def test_lscv_batch_plan_and_errors():
+    lib = K.lib()
+    H2 = [[0.09, 0.06], [0.06, 0.08]]
+    g64, g128 = ((-3, -3), (3, 3), (64, 64)), ((-3, -3), (3, 3), (128, 128))
+    arr = _lscv_items([(1000, H2, g64), (5000, H2, g128), (2000, np.array(H2) * 2, g64)])
+    h = ctypes.c_void_p()
+    assert lib.kde_lscv_batch_create(arr, 3, None, ctypes.byref(h)) == 0
+    info = KB.KdeBatchInfo()
+    assert lib.kde_batch_query(h, ctypes.byref(info)) == 0
+    # two convolutions per problem: the workspace holds at least each problem's kde_lscv workspace
+    need = sum(K.kde_plan_query(H, n, g)["lscv_ws_bytes"] for n, H, g in [(1000, H2, g64), (5000, H2, g128)])
+    assert info.count == 6 and info.ws_bytes >= need
+    assert lib.kde_batch_eval(h, None) == -1          # not bound
+    lib.kde_batch_destroy(h)
+    assert lib.kde_lscv_batch_create(arr, 0, None, ctypes.byref(h)) == -1
+    assert lib.kde_lscv_batch_create(None, 1, None, ctypes.byref(h)) == -1
+    one = _lscv_items([(1, H2, g64)])                  # n < 2
+    assert lib.kde_lscv_batch_create(one, 1, None, ctypes.byref(h)) == -1
+    nocounts = _lscv_items([(1000, H2, g64)])
+    nocounts[0].counts = 0
+    assert lib.kde_lscv_batch_create(nocounts, 1, None, ctypes.byref(h)) == -1
+    noout = _lscv_items([(1000, H2, g64)])
+    noout[0].out = 0
+    assert lib.kde_lscv_batch_create(noout, 1, None, ctypes.byref(h)) == -1
+    bad = _lscv_items([(1000, H2, g64), (1000, [[1, 2], [2, 1]], g64)])
+    assert lib.kde_lscv_batch_create(bad, 2, None, ctypes.byref(h)) == -2

@@ -40,6 +40,9 @@ def _assert_matches_single(B, items, **opts):
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_matches_single_bit_identical(prec):
     wl = W.batch2d(20, seed_offset=11, n_range=(1e3, 6e4), sides=(64, 128, 256))
+    # grid side 512 (P = 1024 on both axes, the largest batched lengths) at the full
+    # sample count, and a second 512^2 item of another size
+    wl += [W.mix2d_512(), W.mix2d_512(n=300_000, seed_offset=5)]
     items = _items(wl)
     B = K.KdeBatch(items, n_dropped=True, prec=prec)
     B.eval()
@@ -54,6 +57,7 @@ def test_batch_matches_single_bit_identical(prec):
 
 def test_batch_matches_oracle():
     wl = W.batch2d(6, seed_offset=12, n_range=(500, 4000), sides=(64, 96))
+    wl.append(W.mix2d_512(n=100_000, seed_offset=7))        # 512^2: P = 1024 row and column passes
     items = _items(wl)
     B = K.KdeBatch(items, prec="f32")
     B.eval()

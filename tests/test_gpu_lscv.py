@@ -130,3 +130,43 @@ def test_lscv_search_batch_equals_single_searches():
         assert single["lscv"] == b["lscv"]
         assert np.array_equal(single["H"], b["H"])
         assert single["evals"] == b["evals"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_lscv_batch_bit_identical_to_single(prec):
+    """kde_lscv_batch_create: every problem's {LSCV, t1, t2}, combined on the device,
+    equals kde_lscv of that problem bit for bit (2-D of several sizes, 1-D and 3-D)."""
+    probs = []
+    for i, (d, M, n) in enumerate([(2, 64, 3000), (2, 128, 20_000), (2, 256, 50_000), (2, 512, 100_000),
+                                   (1, 300, 4000), (3, 24, 5000)]):
+        w = W.small_mixture(400 + i, d, n, M)
+        g = (w.lo, w.hi, w.M)
+        C, _ = K.kde_bin(_dev(w.X), g)
+        probs.append((C, w.n, w.H, g))
+    B = K.KdeLscvBatch(probs, prec=prec)
+    B.eval()
+    got = B.out.cpu().numpy()
+    for k, (C, n, H, g) in enumerate(probs):
+        ref = K.kde_lscv(C, n, H, g, prec=prec).cpu().numpy()
+        assert np.array_equal(got[k], ref), k
+        assert got[k][0] == got[k][1] - got[k][2]
+    # a second eval after tuning gives the same values
+    B.tune(reps=1)
+    B.out.zero_()
+    B.eval()
+    assert np.array_equal(B.out.cpu().numpy(), got)
+    B.close()
+
+
+def test_lscv_batch_matches_oracle_terms():
+    w = W.small_mixture(420, 2, 2500, 48)
+    g = (w.lo, w.hi, w.M)
+    C, _ = K.kde_bin(_dev(w.X), g)
+    B = K.KdeLscvBatch([(C, w.n, w.H, g), (C, w.n, 1.5 * w.H, g)], prec="f64")
+    B.eval()
+    got = B.out.cpu().numpy()
+    for k, s in enumerate((1.0, 1.5)):
+        v, t1, t2 = O.lscv_binned_terms(w.X, s * w.H, w.lo, w.hi, w.M)
+        assert got[k][1] == pytest.approx(t1, rel=1e-11)
+        assert got[k][2] == pytest.approx(t2, rel=1e-11)
+    B.close()

@@ -2,11 +2,16 @@
 accumulation) against the FP64 network oracle that rounds the same operands
 to BF16.
 
-Bars: outputs and gradients within a relative norm of 2e-3 (the kernels
-accumulate in FP32 and may round an activation to the neighbouring BF16 value
-where the FP64 value sits next to a rounding boundary); the Adam step equal to
-the oracle's on every coordinate whose gradient is not at the noise level;
-bit-identical repeated gradients (fixed-order reductions).
+Bars: every output and every gradient entry within 2^-9 (half a BF16 unit in
+the last place) of the largest magnitude of its block (the outputs, or one
+weight or bias block): the kernels accumulate in FP32 and may round an
+activation to the neighbouring BF16 value where the FP64 value sits next to a
+rounding boundary, which moves a downstream product term by at most one BF16
+unit of that term; an emulation of FP32 accumulation shows such entries below
+5e-5 of the block maximum at these sizes. Gradients of the zero padding (input
+rows >= 24 of W1, output columns >= 3 of W4 and b4) are exactly zero. The Adam
+step equals the oracle's on every coordinate whose gradient is not at the noise
+level; repeated gradients are bit-identical (fixed-order reductions).
 """
 import numpy as np
 import pytest
@@ -41,8 +46,12 @@ def _data(seed, B):
     return X, T
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+TOL = 2.0 ** -9
+
+
+def _elementwise(got, ref):
+    """Largest entry-wise error relative to the largest reference magnitude."""
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
 
 
 @pytest.mark.parametrize("B", [1, 64, 200, 1000])
@@ -52,7 +61,8 @@ def test_forward_matches_oracle(B):
     net = K.MlpNet(th)
     Y = net.forward(torch.as_tensor(X, device=DEV)).cpu().numpy()
     y, _ = N.forward(th, X.astype(np.float64))
-    assert _rel(Y, y[:, :3]) < 2e-3
+    assert Y.shape == (B, 3)
+    assert _elementwise(Y, y[:, :3]) <= TOL
 
 
 @pytest.mark.parametrize("B", [37, 256, 1000])
@@ -68,11 +78,15 @@ def test_gradient_matches_oracle(B):
     for k, n in N.SHAPES:           # each weight block and bias block separately
         for size in (k * n, n):
             blk, ref = g[o:o + size], gref[o:o + size]
-            if np.linalg.norm(ref) > 0:
-                assert _rel(blk, ref) < 2e-3, (k, n, size)
+            if np.any(ref != 0):
+                assert _elementwise(blk, ref) <= TOL, (k, n, size)
             else:
                 assert np.all(blk == 0)
             o += size
+    # the zero padding stays out of the gradient exactly
+    blocks = N.unpack(g)
+    assert np.all(blocks[0][0][N.N_IN:, :] == 0)
+    assert np.all(blocks[3][0][:, N.N_OUT:] == 0) and np.all(blocks[3][1][N.N_OUT:] == 0)
 
 
 def test_gradient_is_deterministic():

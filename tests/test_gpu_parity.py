@@ -3,8 +3,9 @@
 Bars: grid counts bit-exact (integer fixed point); lag weights within 2e-6 of
 k_0 in FP32 and 1e-14 in FP64; densities within 1e-5 of the grid maximum in
 FP32 and 1e-12 in FP64. Sizes span several FFT tiles with ragged tails; the
-full-size workloads are compared in full (2-D) or on sampled grid points the
-oracle evaluates one by one (3-D).
+full-size workloads are compared on every cell (2-D against the direct sum,
+3-D against the oracle's FFT form of Eq. 7), the 3-D one also on sampled grid
+points the oracle evaluates one by one.
 """
 import numpy as np
 import pytest
@@ -310,6 +311,60 @@ def test_eval_3d_128_sampled(ref3d128, prec):
     # total mass: at most the normal tail beyond tau is lost
     mass = got.sum(dtype=np.float64) * np.prod(p["delta"])
     assert 0.99 <= mass <= 1.0 + 1e-4
+
+
+def _smooth_at_least(x: int) -> int:
+    """Smallest 2^a 3^b >= x (a length numpy's FFT handles quickly)."""
+    best = 1 << (x - 1).bit_length()
+    p3 = 1
+    while p3 < best:
+        v = p3
+        while v < x:
+            v *= 2
+        best = min(best, v)
+        p3 *= 3
+    return best
+
+
+@pytest.fixture(scope="module")
+def full3d128(ref3d128):
+    """The whole 128^3 estimate from the oracle's FFT form of Eq. (7) (the paper's layout,
+    Eq. 12-14, with P_k >= 2 M_k + 2 L_k - 1, pinned on the CPU to the direct sum)."""
+    w, p, counts, c, k = ref3d128
+    P = tuple(_smooth_at_least(2 * m + 2 * l - 1) for m, l in zip(w.M, p["L"]))
+    return O.conv_fft_corrected(c, k, p["L"], P=P)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_3d_128_full_grid(ref3d128, full3d128, prec):
+    """Every one of the 2.1M cells of the 3-D estimate (P = 256 on all three axes)
+    element by element against the oracle."""
+    w, p, counts, c, k = ref3d128
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert got.shape == full3d128.shape
+    assert _rel(got, full3d128) <= TOL[prec], _rel(got, full3d128)
+    # the FFT form itself agrees with the direct sum where the latter is evaluated
+    pts = [(64, 64, 64), (0, 0, 0), (127, 3, 90), (17, 127, 0)]
+    ref = O.conv_direct_at(c, k, p["L"], pts)
+    assert np.max(np.abs(np.array([full3d128[q] for q in pts]) - ref)) <= 1e-14 * full3d128.max()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("d,M", [(2, (64, 48)), (3, (24, 20, 30)), (1, (200,))])
+def test_eval_with_dropped_samples(prec, d, M):
+    """A grid box narrower than the data: samples outside it are dropped and counted, and
+    the estimate keeps the total n in the 1/n of Eq. (1)."""
+    w = W.small_mixture(600 + d, d, 20_000, M)
+    span = w.hi - w.lo
+    lo, hi = w.lo + 0.2 * span, w.hi - 0.15 * span
+    f, info = O.kde_binned(w.X, w.H, lo, hi, w.M)
+    assert info["n_dropped"] > 0
+    got, nd = K.kde_eval(_dev(w.X), w.H, (lo, hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    assert int(nd.cpu().numpy()[0]) == info["n_dropped"]
+    assert _rel(got.cpu().numpy(), f) <= TOL[prec]
 
 
 def test_eval_3d_128_bins_exact_inside_eval(ref3d128):

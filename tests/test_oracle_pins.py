@@ -277,6 +277,20 @@ def test_corrected_fft_equals_direct(d):
     assert np.max(np.abs(f - g)) <= 1e-13 * np.max(f)
 
 
+def test_corrected_fft_lengths_not_powers_of_two():
+    """The corrected layout (Eq. 12-14) is exact for any P_k with no wrap-around at all,
+    P_k >= 2 M_k + 2 L_k - 1 (at that odd length and at a 3-smooth one), and still at the
+    shortest length that holds the window, P_k = 2 M_k + L_k - 1: the linear convolution
+    then wraps only onto indices below the window."""
+    w = W.small_mixture(seed=44, d=3, n=3000, M=(14, 11, 9))
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+    ML = list(zip(w.M, info["L"]))
+    need = tuple(2 * m + 2 * l - 1 for m, l in ML)
+    for P in (need, tuple(3 * ((x + 2) // 3) for x in need), tuple(2 * m + l - 1 for m, l in ML)):
+        g = O.conv_fft_corrected(info["c"], info["k"], info["L"], P=P)
+        assert np.max(np.abs(f - g)) <= 1e-13 * np.max(f), P
+
+
 def test_corrected_fft_extraction_window_full_box():
     """Eq. (14) window (2M-1):(3M-2) (1-based) with L = M - 1 and P >= 3M - 2."""
     rng = np.random.default_rng(8)
