@@ -979,6 +979,7 @@ struct kde_batch {
 
 namespace {
 
+constexpr int kAllNarrow = ((1 << 13) - 1) & ~((1 << 4) - 1);   // bits log2(P) for P = 16 .. 4096
 constexpr int kTuneTiles2[][3] = {{0, 0, 0}, {16, 64, 0}, {64, 16, 0}, {64, 64, 0}, {16, 16, 0}};
 constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 16, 16}, {4, 16, 16}, {16, 16, 16}, {4, 32, 32}};
 constexpr int kTuneTiles1[][3] = {{0, 0, 0}, {512, 0, 0}, {2048, 0, 0}, {4096, 0, 0}};
@@ -1245,13 +1246,21 @@ int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& intern
             b->inst_off[i] = off_items;
             off_items += align_up(need[i]);
         }
+        // the tables of every configuration the autotuner may bind: each tile shape with the
+        // strided passes wide or narrow (narrow shapes take more workgroups, so larger owner maps)
         for (const auto& c : cands) {
             for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
-            size_t tb = 0;
             rc = layout_batch(*b);
-            if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
             if (rc != KDE_OK) break;
-            cap = std::max(cap, tb);
+            for (const int mask : {0, kAllNarrow}) {
+                b->narrow_mask = mask;
+                size_t tb = 0;
+                rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
+                if (rc != KDE_OK) break;
+                cap = std::max(cap, tb);
+            }
+            b->narrow_mask = 0;
+            if (rc != KDE_OK) break;
         }
         b->lscv_tab_off = align_up(cap);
         b->table_cap = align_up(b->lscv_tab_off + b->lscv.size() * sizeof(kde::LscvJob));
