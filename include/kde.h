@@ -194,6 +194,24 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid,
              const kde_params* params, void* density, void* ws, size_t ws_bytes,
              uint64_t* n_dropped, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): kde_eval
+ * with its workspace taken from a fixed device array inside the library
+ * instead of a caller buffer. The caller still passes X, density and
+ * n_dropped (device, as for kde_eval). The library holds one array of
+ * KDE_NOALLOC_SCRATCH_BYTES on every GPU it runs on, until the process ends;
+ * the first call on a GPU looks up that GPU's copy (no allocation), and no
+ * call allocates or frees device memory. Everything runs in order on `stream`.
+ * Every call on a GPU uses the same array, which keeps the previous call's
+ * contents: calls that overlap on one GPU race (serialise them, e.g. on one
+ * stream). Returns KDE_ERR_WS when the problem's plan.eval_ws_bytes exceeds
+ * KDE_NOALLOC_SCRATCH_BYTES and KDE_ERR_ARG for reuse_spectrum (the array need
+ * not hold this problem's spectrum); otherwise the results are those of
+ * kde_eval with the same arguments. */
+#define KDE_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+int kde_eval_noalloc(const double* X, int64_t n, const double* H, const kde_grid* grid, const kde_params* params,
+                     void* density, uint64_t* n_dropped, hipStream_t stream);
+
 /* Least-squares cross-validation objective of H from fixed-point counts
  * (bandwidth selection, the use of the binned FFT method that Section 5 points
  * to). With phi_A the N(0, A) density, the objective

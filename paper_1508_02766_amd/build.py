@@ -35,6 +35,7 @@ SOURCES = {
     "kde_fft_batch.hip": ["-ffp-contract=off"],
     "kde_lscv.hip": ["-ffp-contract=off"],
     "kde_mlp.hip": ["-ffp-contract=off"],
+    "kde_static.hip": [],
     "kde_api.cpp": [],
 }
 

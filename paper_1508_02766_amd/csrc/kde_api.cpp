@@ -1281,6 +1281,47 @@ int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& intern
     return KDE_OK;
 }
 
+// The whole estimate of a planned problem into the workspace ws (counts,
+// binning workspace, convolution workspace); `overlap` allows the kernel
+// spectrum on the second stream where it does not ride in the binning launches.
+int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* grid, const kde_params* params,
+                 void* density, char* ws, uint64_t* n_dropped, bool overlap, hipStream_t stream) {
+    auto* counts = reinterpret_cast<uint64_t*>(ws);
+    char* bin_ws = ws + align_up(pl.counts_bytes);
+    char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
+    const bool reuse = params && params->reuse_spectrum;
+    // with tiled binning the spectrum rides in the binning launches: its row pass
+    // in the histogram's, its strided pass (3-D) in the scan's
+    std::vector<Pass> spec;
+    if (pl.tiled && !reuse) {
+        Collect c(spec);
+        KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
+        const size_t want = pl.pub.d == 3 ? 2 : 1;
+        if (spec.size() != want || spec[0].kind != kPassRowR2C || (want == 2 && spec[1].kind != kPassCols))
+            spec.clear();
+    }
+    Tracer tr(params, stream);
+    KDE_CHECK(tr.start());
+    const int r = run_phases(
+        stream, tr, overlap && pl.pub.d == 3 && spec.empty(),
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0],
+                              spec.size() == 2 ? &spec[1] : nullptr));
+            return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
+        },
+        [&](hipStream_t s) {
+            Direct e(s, tr);
+            return run_product_inv(pl, grid, density, conv_ws, -1, e);
+        });
+    tr.finish();
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1408,40 +1449,24 @@ int kde_eval(const double* X, int64_t n, const double* H, const kde_grid* grid, 
     if (!X || !density || !ws) return KDE_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return KDE_ERR_ARG;
     if (ws_bytes < pl.pub.eval_ws_bytes) return KDE_ERR_WS;
-    auto* counts = static_cast<uint64_t*>(ws);
-    char* bin_ws = static_cast<char*>(ws) + align_up(pl.counts_bytes);
-    char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
-    const bool reuse = params && params->reuse_spectrum;
-    // with tiled binning the spectrum rides in the binning launches: its row pass
-    // in the histogram's, its strided pass (3-D) in the scan's
-    std::vector<Pass> spec;
-    if (pl.tiled && !reuse) {
-        Collect c(spec);
-        KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
-        const size_t want = pl.pub.d == 3 ? 2 : 1;
-        if (spec.size() != want || spec[0].kind != kPassRowR2C || (want == 2 && spec[1].kind != kPassCols))
-            spec.clear();
-    }
-    Tracer tr(params, stream);
-    KDE_CHECK(tr.start());
-    const int r = run_phases(
-        stream, tr, pl.pub.d == 3 && spec.empty(),
-        [&](hipStream_t s) {
-            Direct e(s, tr);
-            return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
-        },
-        [&](hipStream_t s) {
-            Direct e(s, tr);
-            KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0],
-                              spec.size() == 2 ? &spec[1] : nullptr));
-            return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
-        },
-        [&](hipStream_t s) {
-            Direct e(s, tr);
-            return run_product_inv(pl, grid, density, conv_ws, -1, e);
-        });
-    tr.finish();
-    return r;
+    return eval_planned(pl, X, n, grid, params, density, static_cast<char*>(ws), n_dropped, true, stream);
+}
+
+int kde_eval_noalloc(const double* X, int64_t n, const double* H, const kde_grid* grid, const kde_params* params,
+                     void* density, uint64_t* n_dropped, hipStream_t stream) {
+    Plan pl;
+    const int rc = make_plan(H, n, 1, true, grid, params, &pl);
+    if (rc != KDE_OK) return rc;
+    if (!X || !density) return KDE_ERR_ARG;
+    // the scratch array keeps the previous call's contents, which need not be this problem's spectrum
+    if (params && params->reuse_spectrum) return KDE_ERR_ARG;
+    if (pl.pub.eval_ws_bytes > kde::kScratchBytes) return KDE_ERR_WS;
+    int dev = 0;
+    if (hipStreamGetDevice(stream, &dev) != hipSuccess) return KDE_ERR_HIP;
+    void* ws = nullptr;
+    if (kde::scratch_address(dev, &ws) != hipSuccess || !ws) return KDE_ERR_HIP;
+    // everything on the caller's stream (no second stream, which its first use would create)
+    return eval_planned(pl, X, n, grid, params, density, static_cast<char*>(ws), n_dropped, false, stream);
 }
 
 int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid* grid, const kde_params* params,

@@ -41,6 +41,11 @@ __device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t G) {
         }                                                                                          \
     } while (0)
 
+// Scratch array of kde_eval_noalloc (kde_static.hip): its size, and the device
+// address of `dev`'s copy (looked up once per device, with that device current).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+hipError_t scratch_address(int dev, void** out);
+
 constexpr int kMaxP = 4096;   // largest padded FFT length per axis
 constexpr int kMinP = 16;     // smallest (one radix-16 stage)
 

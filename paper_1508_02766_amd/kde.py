@@ -91,7 +91,8 @@ class KdeMlpInfo(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ("kde_grid_from_data", "kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval", "kde_lscv", "kde_mlp_query", "kde_mlp_load", "kde_mlp_forward",
+EXPORTS = ("kde_grid_from_data", "kde_plan_query", "kde_bin", "kde_kernel_grid", "kde_conv", "kde_eval",
+           "kde_eval_noalloc", "kde_lscv", "kde_mlp_query", "kde_mlp_load", "kde_mlp_forward",
            "kde_mlp_grad", "kde_mlp_train_step", "kde_batch_create",
            "kde_batch_query", "kde_batch_bind", "kde_batch_eval", "kde_batch_tune", "kde_batch_destroy",
            "kde_lscv_batch_create",
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
         L.kde_kernel_grid.argtypes = [vp, i64, G, Pp, vp, sz, vp]
         L.kde_conv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_eval.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp, vp]
+        L.kde_eval_noalloc.argtypes = [vp, i64, vp, G, Pp, vp, vp, vp]
         L.kde_lscv.argtypes = [vp, i64, vp, G, Pp, vp, vp, sz, vp]
         L.kde_mlp_query.argtypes = [i64, ctypes.POINTER(KdeMlpInfo)]
         L.kde_mlp_load.argtypes = [vp, vp, vp]
@@ -362,6 +364,24 @@ def kde_eval(X: torch.Tensor, H, grid, out=None, ws=None, n_dropped=None, **opts
     Hn, Hp = _H(H, g.d)
     _check(lib().kde_eval(_ptr(X), n, Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out), _ptr(ws), ws.numel(),
                           _ptr(n_dropped), _stream(dev)), "kde_eval")
+    _finish_trace(keep)
+    return out, n_dropped
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20     # KDE_NOALLOC_SCRATCH_BYTES
+
+
+def kde_eval_noalloc(X: torch.Tensor, H, grid, out: torch.Tensor, n_dropped=None, **opts):
+    """kde_eval with the library's fixed device scratch as workspace (no device
+    allocation in the library; out and n_dropped are the caller's)."""
+    g = _grid(grid)
+    _need_cuda(X, torch.float64, "X")
+    if X.dim() != 2 or X.shape[1] != g.d:
+        raise ValueError("X must be (n, d)")
+    p, keep = _params(**opts)
+    Hn, Hp = _H(H, g.d)
+    _check(lib().kde_eval_noalloc(_ptr(X), X.shape[0], Hp, ctypes.byref(g), ctypes.byref(p), _ptr(out),
+                                  _ptr(n_dropped), _stream(X.device)), "kde_eval_noalloc")
     _finish_trace(keep)
     return out, n_dropped
 
