@@ -42,12 +42,16 @@
 extern "C" {
 #endif
 
+/* Largest dimension d (Section 2 states the method for general d; the library
+ * builds d = 1, 2, 3 and 4). */
+#define KDE_MAX_D 4
+
 /* Arithmetic type of the FFT convolution and of densities / lag weights. */
 enum kde_precision { KDE_F32 = 1, KDE_F64 = 2 };
 
 enum kde_status {
     KDE_OK = 0,
-    KDE_ERR_ARG = -1,       /* null pointer, d not in {1,2,3}, M_k < 2, hi_k <= lo_k,
+    KDE_ERR_ARG = -1,       /* null pointer, d not in {1,2,3,4}, M_k < 2, hi_k <= lo_k,
                                non-finite box, n < 0 (n < 1 where the estimate divides by n),
                                bad override, bad precision */
     KDE_ERR_NOT_SPD = -2,   /* H not finite, not symmetric (|H - H'| > 1e-12 max|H|)
@@ -63,21 +67,22 @@ enum kde_status {
 typedef struct kde_grid {
     int32_t d;
     int32_t reserved;
-    int64_t M[3];
-    double lo[3];
-    double hi[3];
+    int64_t M[KDE_MAX_D];
+    double lo[KDE_MAX_D];
+    double hi[KDE_MAX_D];
 } kde_grid;
 
 /* Options; an all-zero struct (or a NULL pointer) means the defaults. */
 typedef struct kde_params {
     double tau;               /* Eq. (15) constant; <= 0 selects 3.7 (Section 4.2) */
-    int32_t L[3];             /* > 0: use this L_k instead of Eq. (15) (must be <= M_k - 1);
+    int32_t L[KDE_MAX_D];     /* > 0: use this L_k instead of Eq. (15) (must be <= M_k - 1);
                                  0: Eq. (15) */
     int32_t Q;                /* fixed-point bits of the binning weights; 0: floor(32 / d);
                                  else 1 <= Q and d Q <= 62 */
     int32_t prec;             /* KDE_F32 (also when 0) or KDE_F64 */
-    int32_t tile[3];          /* > 0: binning tile extent (cells, a power of two <= 4096) on
-                                 axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 32;
+    int32_t tile[KDE_MAX_D];  /* > 0: binning tile extent (cells, a power of two <= 4096) on
+                                 axis k instead of the default 1024 / 32 x 32 / 8 x 16 x 32 /
+                                 8 x 8 x 8 x 8;
                                  the product must stay <= 4096. Changes speed and workspace
                                  size, never the counts */
     int32_t extent;           /* lag-box half widths: 0 (default) Eq. (15), tau sqrt(lambda_max)
@@ -110,12 +115,12 @@ typedef struct kde_plan {
     int32_t d;
     int32_t Q;                /* fixed-point bits; counts are in units of 2^-(d Q) */
     int32_t prec;
-    int32_t L[3];             /* truncation per axis: Eq. (15), the marginal extent, or the
+    int32_t L[KDE_MAX_D];     /* truncation per axis: Eq. (15), the marginal extent, or the
                                  override */
-    int32_t P[3];             /* padded FFT length per axis: smallest power of two
+    int32_t P[KDE_MAX_D];     /* padded FFT length per axis: smallest power of two
                                  >= max(16, M_k + L_k) */
     int32_t reserved;
-    double delta[3];          /* bin width, Eq. (4) */
+    double delta[KDE_MAX_D];  /* bin width, Eq. (4) */
     double lambda_max;        /* largest eigenvalue of H */
     double det_H;             /* |H| */
     double norm;              /* n^-1 (2 pi)^-d/2 |H|^-1/2 = k_0 */
@@ -138,7 +143,7 @@ typedef struct kde_plan {
  * a non-finite coordinate are ignored (binning drops them). H: host, d x d
  * FP64, checked as kde_plan_query checks it. nsd >= 0 and finite (the
  * workloads use 3). *out receives d, M, lo and hi.
- * Errors: KDE_ERR_ARG (null pointer, n < 1, d not in {1,2,3}, M < 2, bad nsd,
+ * Errors: KDE_ERR_ARG (null pointer, n < 1, d not in {1,2,3,4}, M < 2, bad nsd,
  * no finite sample, or a box with hi_k <= lo_k), KDE_ERR_NOT_SPD (H). */
 int kde_grid_from_data(const double* X, int64_t n, int32_t d, const double* H, double nsd, int64_t M,
                        kde_grid* out);
@@ -281,7 +286,7 @@ int kde_mlp_train_step(void* state, const float* X, const float* T, int64_t B, f
 typedef struct kde_batch_item {
     const double* X;          /* device, n x d FP64 samples */
     int64_t n;                /* >= 1 */
-    double H[9];              /* bandwidth matrix, d x d row-major in the first d*d entries */
+    double H[KDE_MAX_D * KDE_MAX_D];   /* bandwidth matrix, d x d row-major in the first d*d entries */
     kde_grid grid;
     void* density;            /* device, prod M_k reals of the batch precision (output) */
     uint64_t* n_dropped;      /* device, may be NULL: samples outside the grid (as kde_bin) */
@@ -300,7 +305,7 @@ typedef struct kde_batch_info {
     int32_t count;            /* items */
     int32_t launches;         /* kernel launches per kde_batch_eval */
     size_t ws_bytes;          /* device workspace kde_batch_bind needs */
-    int32_t tile[3];          /* binning tile in use (the autotuner may change it) */
+    int32_t tile[KDE_MAX_D];  /* binning tile in use (the autotuner may change it) */
     int32_t narrow_mask;      /* bit log2(P): strided-axis passes of length P use 4 lines
                                  per workgroup (else the widest shape) */
 } kde_batch_info;
@@ -350,7 +355,7 @@ void kde_batch_destroy(kde_batch* b);
 typedef struct kde_lscv_item {
     const uint64_t* counts;   /* device, prod M_k uint64 fixed-point counts (kde_bin) */
     int64_t n;                /* sample count, >= 2 */
-    double H[9];              /* bandwidth matrix, d x d row-major in the first d*d entries */
+    double H[KDE_MAX_D * KDE_MAX_D];   /* bandwidth matrix, d x d row-major in the first d*d entries */
     kde_grid grid;
     double* out;              /* device, 3 doubles: {LSCV, first term, second term} */
 } kde_lscv_item;

@@ -59,8 +59,8 @@ TAU_DEFAULT = 3.7   # Section 4.2, after Eq. (15)
 def check_bandwidth(H) -> np.ndarray:
     """H must be a symmetric positive definite d x d matrix (Section 1, Eq. 1)."""
     H = np.asarray(H, dtype=np.float64)
-    if H.ndim != 2 or H.shape[0] != H.shape[1] or H.shape[0] not in (1, 2, 3):
-        raise ValueError("H must be d x d with d in {1, 2, 3}")
+    if H.ndim != 2 or H.shape[0] != H.shape[1] or H.shape[0] not in (1, 2, 3, 4):
+        raise ValueError("H must be d x d with d in {1, 2, 3, 4}")
     if not np.all(np.isfinite(H)):
         raise ValueError("H must be finite")
     if np.max(np.abs(H - H.T)) > 1e-12 * np.max(np.abs(H)):

@@ -4,7 +4,7 @@
 // Planner (Gramacki & Gramacki, arXiv 1508.02766):
 //   delta_k = (hi_k - lo_k) / (M_k - 1)                       Eq. (4)
 //   H = R R' (Cholesky), |H| = prod R_kk^2, H^-1 = R^-T R^-1  (K_H of Eq. 1)
-//   lambda_max(H): closed form for d <= 2, cyclic Jacobi for d = 3
+//   lambda_max(H): closed form for d <= 2, cyclic Jacobi for d >= 3
 //   L_k = min(M_k - 1, ceil(tau sqrt(lambda_max) / delta_k))  Eq. (15)
 //         (or tau sqrt(H_kk) with kde_params.extent = 1)
 //   P_k = smallest power of two >= max(16, M_k + L_k)          zero padding, Section 4.1
@@ -49,7 +49,7 @@ int64_t half_pitch(int P) { return (static_cast<int64_t>(P) / 2 + 1 + 15) / 16 *
 
 struct Layout {
     // offsets into the convolution workspace
-    size_t khat = 0, kt1 = 0, kt2 = 0, z1 = 0, z2 = 0, total = 0;
+    size_t khat = 0, kt1 = 0, kt2 = 0, kt3 = 0, z1 = 0, z2 = 0, z3 = 0, total = 0;
 };
 
 struct BinLayout {
@@ -59,8 +59,8 @@ struct BinLayout {
 
 struct Plan {
     kde_plan pub;
-    int64_t M[3];     // grid nodes per axis
-    double A[9];      // A_ab = delta_a delta_b (H^-1)_ab
+    int64_t M[kde::kMaxD];              // grid nodes per axis
+    double A[kde::kMaxD * kde::kMaxD];  // A_ab = delta_a delta_b (H^-1)_ab at [a kMaxD + b]
     double tau;
     Layout lay;
     size_t counts_bytes;
@@ -70,13 +70,13 @@ struct Plan {
 };
 
 // Tile geometry of the binning passes: 32 x 32 cells in 2-D, 8 x 16 x 32 in
-// 3-D, 1024 in 1-D, or the caller's tile (clamped to the grid), widened until
+// 3-D, 8^4 in 4-D, 1024 in 1-D, or the caller's tile (clamped to the grid), widened until
 // the tile count fits the sort's LDS counters. Returns false when the tiled
 // path cannot be used: too many cells per tile, records wider than 64 bits,
 // n 2^d >= 2^32, or more chunks than the gather's LDS tables hold.
 bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde::TileGeom* tg, BinLayout* bl) {
     kde::TileGeom g{};
-    static const int base[3][3] = {{1024, 0, 0}, {32, 32, 0}, {8, 16, 32}};
+    static const int base[kde::kMaxD][kde::kMaxD] = {{1024}, {32, 32}, {8, 16, 32}, {8, 8, 8, 8}};
     for (int k = 0; k < d; ++k) {
         int T = tile[k] > 0 ? tile[k] : base[d - 1][k];
         while (T > 1 && T / 2 >= M[k]) T /= 2;
@@ -138,7 +138,8 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
 // H (d x d, row-major) must be finite, symmetric (|H - H'| <= 1e-12 max|H|)
 // and positive definite (Section 1): Hs = (H + H') / 2 and its Cholesky
 // factor R (lower triangular, Hs = R R').
-int factor_bandwidth(const double* H, int d, double (&Hs)[3][3], double (&R)[3][3]) {
+int factor_bandwidth(const double* H, int d, double (&Hs)[kde::kMaxD][kde::kMaxD],
+                     double (&R)[kde::kMaxD][kde::kMaxD]) {
     double hmax = 0.0;
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
@@ -180,7 +181,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     std::memset(out, 0, sizeof(*out));
     kde_plan& p = out->pub;
     const int d = g->d;
-    if (d < 1 || d > 3) return KDE_ERR_ARG;
+    if (d < 1 || d > kde::kMaxD) return KDE_ERR_ARG;
     if (n < n_min) return KDE_ERR_ARG;
     p.d = d;
     for (int k = 0; k < d; ++k) out->M[k] = g->M[k];
@@ -193,7 +194,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     // options
     double tau = kTauDefault;
     int prec = KDE_F32, Q = 32 / d;
-    int Lovr[3] = {0, 0, 0}, tile[3] = {0, 0, 0};
+    int Lovr[kde::kMaxD] = {}, tile[kde::kMaxD] = {};
     int extent = 0;
     if (prm) {
         if (std::isnan(prm->tau) || std::isinf(prm->tau)) return KDE_ERR_ARG;
@@ -238,13 +239,13 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
 
     // H: finite, symmetric, positive definite
     if (!H) return KDE_ERR_ARG;
-    double Hs[3][3] = {};
-    double R[3][3] = {};
+    double Hs[kde::kMaxD][kde::kMaxD] = {};
+    double R[kde::kMaxD][kde::kMaxD] = {};
     KDE_PLAN_CHECK(factor_bandwidth(H, d, Hs, R));
     double det = 1.0;
     for (int k = 0; k < d; ++k) det *= R[k][k] * R[k][k];
     // inverse of the lower-triangular factor, then H^-1 = R^-T R^-1
-    double Ri[3][3] = {};
+    double Ri[kde::kMaxD][kde::kMaxD] = {};
     for (int j = 0; j < d; ++j) {
         Ri[j][j] = 1.0 / R[j][j];
         for (int i = j + 1; i < d; ++i) {
@@ -253,7 +254,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
             Ri[i][j] = -s / R[i][i];
         }
     }
-    double Hinv[3][3] = {};
+    double Hinv[kde::kMaxD][kde::kMaxD] = {};
     for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) {
             double s = 0.0;
@@ -267,38 +268,44 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     } else if (d == 2) {
         lam = 0.5 * (Hs[0][0] + Hs[1][1]) + std::hypot(0.5 * (Hs[0][0] - Hs[1][1]), Hs[0][1]);
     } else {
-        double a[3][3];
+        // cyclic Jacobi rotations (Golub & Van Loan, Section 8.5) until the
+        // off-diagonal mass is negligible; lambda_max is the largest diagonal entry
+        double a[kde::kMaxD][kde::kMaxD];
         std::memcpy(a, Hs, sizeof(a));
         for (int sweep = 0; sweep < 60; ++sweep) {
-            const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-            const double diag = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-            if (off <= 1e-36 * diag) break;
-            static const int pq[3][2] = {{0, 1}, {0, 2}, {1, 2}};
-            for (const auto& e : pq) {
-                const int P = e[0], Qi = e[1];
-                const double apq = a[P][Qi];
-                if (apq == 0.0) continue;
-                const double theta = (a[Qi][Qi] - a[P][P]) / (2.0 * apq);
-                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                a[P][P] -= t * apq;
-                a[Qi][Qi] += t * apq;
-                a[P][Qi] = a[Qi][P] = 0.0;
-                for (int r = 0; r < 3; ++r) {
-                    if (r == P || r == Qi) continue;
-                    const double arp = a[r][P], arq = a[r][Qi];
-                    a[r][P] = a[P][r] = c * arp - s * arq;
-                    a[r][Qi] = a[Qi][r] = s * arp + c * arq;
-                }
+            double off = 0.0, diag = 0.0;
+            for (int i = 0; i < d; ++i) {
+                diag += a[i][i] * a[i][i];
+                for (int j = i + 1; j < d; ++j) off += a[i][j] * a[i][j];
             }
+            if (off <= 1e-36 * diag) break;
+            for (int P = 0; P < d; ++P)
+                for (int Qi = P + 1; Qi < d; ++Qi) {
+                    const double apq = a[P][Qi];
+                    if (apq == 0.0) continue;
+                    const double theta = (a[Qi][Qi] - a[P][P]) / (2.0 * apq);
+                    const double t =
+                        (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                    const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                    a[P][P] -= t * apq;
+                    a[Qi][Qi] += t * apq;
+                    a[P][Qi] = a[Qi][P] = 0.0;
+                    for (int r = 0; r < d; ++r) {
+                        if (r == P || r == Qi) continue;
+                        const double arp = a[r][P], arq = a[r][Qi];
+                        a[r][P] = a[P][r] = c * arp - s * arq;
+                        a[r][Qi] = a[Qi][r] = s * arp + c * arq;
+                    }
+                }
         }
-        lam = std::fmax(a[0][0], std::fmax(a[1][1], a[2][2]));
+        lam = a[0][0];
+        for (int k = 1; k < d; ++k) lam = std::fmax(lam, a[k][k]);
     }
     p.lambda_max = lam;
     p.det_H = det;
     p.norm = 1.0 / (static_cast<double>(n) * std::pow(kTwoPi, 0.5 * d) * std::sqrt(det));
     for (int a = 0; a < d; ++a)
-        for (int b = 0; b < d; ++b) out->A[a * 3 + b] = p.delta[a] * p.delta[b] * Hinv[a][b];
+        for (int b = 0; b < d; ++b) out->A[a * kde::kMaxD + b] = p.delta[a] * p.delta[b] * Hinv[a][b];
 
     // truncation (Eq. 15) and padded lengths
     int64_t lag_count = 1;
@@ -341,11 +348,21 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     } else if (d == 2) {
         L.kt1 = take(static_cast<size_t>(n0 * Hl) * cs);
         L.z1 = take(static_cast<size_t>(M0 * Hl) * cs);
-    } else {
+    } else if (d == 3) {
         L.kt1 = take(static_cast<size_t>(n0 * n1 * Hl) * cs);
         L.kt2 = take(static_cast<size_t>(n0 * P1 * Hl) * cs);
         L.z1 = take(static_cast<size_t>(M0 * M1 * Hl) * cs);
         L.z2 = take(static_cast<size_t>(M0 * P1 * Hl) * cs);
+    } else {
+        // 4-D: spectrum [n0][n1][n2] -> [n0][n1][P2] -> [n0][P1][P2], counts
+        // [M0][M1][M2] -> [M0][M1][P2] -> [M0][P1][P2] (rows of Hl half-spectrum bins)
+        const int64_t M2 = g->M[2], P2 = p.P[2], n2 = 2 * p.L[2] + 1;
+        L.kt1 = take(static_cast<size_t>(n0 * n1 * n2 * Hl) * cs);
+        L.kt2 = take(static_cast<size_t>(n0 * n1 * P2 * Hl) * cs);
+        L.kt3 = take(static_cast<size_t>(n0 * P1 * P2 * Hl) * cs);
+        L.z1 = take(static_cast<size_t>(M0 * M1 * M2 * Hl) * cs);
+        L.z2 = take(static_cast<size_t>(M0 * M1 * P2 * Hl) * cs);
+        L.z3 = take(static_cast<size_t>(M0 * P1 * P2 * Hl) * cs);
     }
     L.total = off;
     p.conv_ws_bytes = L.total;
@@ -623,12 +640,12 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
 
 // Stage views of the convolution workspace.
 struct ConvBufs {
-    void *khat, *kt1, *kt2, *z1, *z2;
+    void *khat, *kt1, *kt2, *kt3, *z1, *z2, *z3;
 };
 
 ConvBufs conv_bufs(const Plan& pl, char* ws) {
     const Layout& L = pl.lay;
-    return {ws + L.khat, ws + L.kt1, ws + L.kt2, ws + L.z1, ws + L.z2};
+    return {ws + L.khat, ws + L.kt1, ws + L.kt2, ws + L.kt3, ws + L.z1, ws + L.z2, ws + L.z3};
 }
 
 Pass row_r2c_pass(const Plan& pl, int P, int kind, const void* in, const kde::GaussLag* gl, int64_t nrows,
@@ -694,10 +711,10 @@ int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
     const int d = p.d;
     const ConvBufs b = conv_bufs(pl, ws);
     kde::GaussLag gl{};
-    for (int i = 0; i < 9; ++i) gl.A[i] = pl.A[i];
+    for (int i = 0; i < kde::kMaxD * kde::kMaxD; ++i) gl.A[i] = pl.A[i];
     gl.norm = p.norm;
     gl.d = d;
-    for (int k = 0; k < 3; ++k) gl.L[k] = k < d ? p.L[k] : 0;
+    for (int k = 0; k < kde::kMaxD; ++k) gl.L[k] = k < d ? p.L[k] : 0;
     if (d == 1) {
         const int P0 = p.P[0];
         return emit(row_r2c_pass(pl, P0, kde::kRowGaussCirc, nullptr, &gl, 1, 0, p.L[0], b.khat, P0 / 2 + 1, 0,
@@ -708,6 +725,40 @@ int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
         const int64_t n0 = 2 * p.L[0] + 1;
         return emit(row_r2c_pass(pl, P1, kde::kRowGaussCirc, nullptr, &gl, n0, 0, p.L[1], b.kt1, half_pitch(P1), 0,
                                  "kspec_r2c"));
+    }
+    if (d == 4) {
+        const int P1 = p.P[1], P2 = p.P[2], P3 = p.P[3];
+        const int64_t H3 = P3 / 2 + 1, Hp = half_pitch(P3);
+        const int64_t n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1, n2 = 2 * p.L[2] + 1;
+        KDE_CHECK(emit(row_r2c_pass(pl, P3, kde::kRowGaussCirc, nullptr, &gl, n0 * n1 * n2, 0, p.L[3], b.kt1, Hp,
+                                    0, "kspec_r2c")));
+        // axis 2: [n0 n1][n2][Hp] -> [n0 n1][P2][Hp]
+        kde::ColArgs k2{};
+        k2.in = b.kt1;
+        k2.out = b.kt2;
+        k2.W = H3;
+        k2.outer = n0 * n1;
+        k2.in_os = n2 * Hp;
+        k2.in_ps = Hp;
+        k2.out_os = static_cast<int64_t>(P2) * Hp;
+        k2.out_ps = Hp;
+        k2.len = p.L[2];
+        KDE_CHECK(emit(cols_pass(pl, P2, kde::kColFwdCirc, k2, nmask, 1, "kspec_col3")));
+        // axis 1: [n0][n1][P2 Hp] -> [n0][P1][P2 Hp]; outer index (i0, w2)
+        kde::ColArgs k1{};
+        k1.in = b.kt2;
+        k1.out = b.kt3;
+        k1.W = H3;
+        k1.outer = n0 * P2;
+        k1.ob = P2;
+        k1.in_os1 = n1 * P2 * Hp;
+        k1.in_os = Hp;
+        k1.in_ps = P2 * Hp;
+        k1.out_os1 = static_cast<int64_t>(P1) * P2 * Hp;
+        k1.out_os = Hp;
+        k1.out_ps = P2 * Hp;
+        k1.len = p.L[1];
+        return emit(cols_pass(pl, P1, kde::kColFwdCirc, k1, nmask, 2, "kspec_col2"));
     }
     const int P1 = p.P[1], P2 = p.P[2];
     const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), n0 = 2 * p.L[0] + 1, n1 = 2 * p.L[1] + 1;
@@ -753,6 +804,37 @@ int run_counts_fwd(const Plan& pl, const uint64_t* counts, const kde_grid* g, ch
         f1.len = static_cast<int>(M1);
         KDE_CHECK(emit(cols_pass(pl, P1, kde::kColFwdPrefix, f1, nmask, 11, "counts_col2")));
     }
+    if (d == 4) {
+        const int P1 = p.P[1], P2 = p.P[2];
+        const int64_t M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
+        // axis 2: [M0 M1][M2][Hp] -> [M0 M1][P2][Hp]
+        kde::ColArgs f2{};
+        f2.in = b.z1;
+        f2.out = b.z2;
+        f2.W = Hl;
+        f2.outer = M0 * M1;
+        f2.in_os = M2 * Hp;
+        f2.in_ps = Hp;
+        f2.out_os = static_cast<int64_t>(P2) * Hp;
+        f2.out_ps = Hp;
+        f2.len = static_cast<int>(M2);
+        KDE_CHECK(emit(cols_pass(pl, P2, kde::kColFwdPrefix, f2, nmask, 11, "counts_col3")));
+        // axis 1: [M0][M1][P2 Hp] -> [M0][P1][P2 Hp]; outer index (i0, w2)
+        kde::ColArgs f1{};
+        f1.in = b.z2;
+        f1.out = b.z3;
+        f1.W = Hl;
+        f1.outer = M0 * P2;
+        f1.ob = P2;
+        f1.in_os1 = M1 * P2 * Hp;
+        f1.in_os = Hp;
+        f1.in_ps = P2 * Hp;
+        f1.out_os1 = static_cast<int64_t>(P1) * P2 * Hp;
+        f1.out_os = Hp;
+        f1.out_ps = P2 * Hp;
+        f1.len = static_cast<int>(M1);
+        KDE_CHECK(emit(cols_pass(pl, P1, kde::kColFwdPrefix, f1, nmask, 12, "counts_col2")));
+    }
     return KDE_OK;
 }
 
@@ -787,6 +869,57 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         ca.mout = static_cast<int>(M0);
         KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, ca, nmask, 20, "conv_col")));
         return emit(row_c2r_pass(pl, P1, b.z1, M0, Hp, nullptr, density, M1, static_cast<int>(M1), scale, 21, "c2r"));
+    }
+    if (d == 4) {
+        const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2], P3 = p.P[3];
+        const int64_t H3 = P3 / 2 + 1, Hp = half_pitch(P3);
+        const int64_t M0 = g->M[0], M1 = g->M[1], M2 = g->M[2], M3 = g->M[3];
+        // axis 0 over [M0][P1 P2][Hp], lines (w1 w2, w3), in place
+        kde::ColArgs cv{};
+        cv.in = b.z3;
+        cv.out = b.z3;
+        cv.kt = b.kt3;
+        cv.W = H3;
+        cv.outer = static_cast<int64_t>(P1) * P2;
+        cv.in_os = Hp;
+        cv.out_os = Hp;
+        cv.kt_os = Hp;
+        cv.in_ps = static_cast<int64_t>(P1) * P2 * Hp;
+        cv.out_ps = cv.in_ps;
+        cv.kt_ps = cv.in_ps;
+        cv.kt_len = p.L[0];
+        cv.len = static_cast<int>(M0);
+        cv.mout = static_cast<int>(M0);
+        KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, cv, nmask, 20, "conv_col1")));
+        // axis 1: [M0][P1][P2 Hp] -> [M0][M1][P2 Hp]; outer index (i0, w2)
+        kde::ColArgs i1{};
+        i1.in = b.z3;
+        i1.out = b.z2;
+        i1.W = H3;
+        i1.outer = M0 * P2;
+        i1.ob = P2;
+        i1.in_os1 = static_cast<int64_t>(P1) * P2 * Hp;
+        i1.in_os = Hp;
+        i1.in_ps = P2 * Hp;
+        i1.out_os1 = M1 * P2 * Hp;
+        i1.out_os = Hp;
+        i1.out_ps = P2 * Hp;
+        i1.mout = static_cast<int>(M1);
+        KDE_CHECK(emit(cols_pass(pl, P1, kde::kColInvPrefix, i1, nmask, 21, "inv_col2")));
+        // axis 2: [M0 M1][P2][Hp] -> [M0 M1][M2][Hp]
+        kde::ColArgs i2{};
+        i2.in = b.z2;
+        i2.out = b.z1;
+        i2.W = H3;
+        i2.outer = M0 * M1;
+        i2.in_os = static_cast<int64_t>(P2) * Hp;
+        i2.in_ps = Hp;
+        i2.out_os = M2 * Hp;
+        i2.out_ps = Hp;
+        i2.mout = static_cast<int>(M2);
+        KDE_CHECK(emit(cols_pass(pl, P2, kde::kColInvPrefix, i2, nmask, 22, "inv_col3")));
+        return emit(row_c2r_pass(pl, P3, b.z1, M0 * M1 * M2, Hp, nullptr, density, M3, static_cast<int>(M3), scale,
+                                 23, "c2r"));
     }
     const int P0 = p.P[0], P1 = p.P[1], P2 = p.P[2];
     const int64_t H2 = P2 / 2 + 1, Hp = half_pitch(P2), M0 = g->M[0], M1 = g->M[1], M2 = g->M[2];
@@ -936,7 +1069,7 @@ int lscv_plans(const double* H, int64_t n, const kde_grid* g, const kde_params* 
     if (n < 2 || !H || !g) return KDE_ERR_ARG;
     KDE_CHECK(make_plan(H, n, 1, true, g, prm, p1));
     const int d = p1->pub.d;
-    double H2[9] = {};
+    double H2[kde::kMaxD * kde::kMaxD] = {};
     for (int i = 0; i < d * d; ++i) H2[i] = 2.0 * H[i];
     KDE_CHECK(make_plan(H2, n, 1, true, g, prm, p2));
     int64_t cells = 1;
@@ -966,7 +1099,7 @@ struct kde_batch {
     std::vector<kde_batch_item> items;
     kde_params prm{};
     bool has_prm = false;
-    int tile[3] = {0, 0, 0};       // binning tile of the current configuration (0: default)
+    int tile[kde::kMaxD] = {};     // binning tile of the current configuration (0: default)
     int narrow_mask = 0;           // bit log2(P): narrow strided passes of length P
     std::vector<Plan> plans;
     std::vector<size_t> inst_off;  // per item: offset of its eval workspace in ws
@@ -986,9 +1119,11 @@ struct kde_batch {
 namespace {
 
 constexpr int kAllNarrow = ((1 << 13) - 1) & ~((1 << 4) - 1);   // bits log2(P) for P = 16 .. 4096
-constexpr int kTuneTiles2[][3] = {{0, 0, 0}, {16, 64, 0}, {64, 16, 0}, {64, 64, 0}, {16, 16, 0}};
-constexpr int kTuneTiles3[][3] = {{0, 0, 0}, {8, 16, 16}, {4, 16, 16}, {16, 16, 16}, {4, 32, 32}};
-constexpr int kTuneTiles1[][3] = {{0, 0, 0}, {512, 0, 0}, {2048, 0, 0}, {4096, 0, 0}};
+using TileShape = std::array<int, kde::kMaxD>;
+const TileShape kTuneTiles1[] = {{0}, {512}, {2048}, {4096}};
+const TileShape kTuneTiles2[] = {{0}, {16, 64}, {64, 16}, {64, 64}, {16, 16}};
+const TileShape kTuneTiles3[] = {{0}, {8, 16, 16}, {4, 16, 16}, {16, 16, 16}, {4, 32, 32}};
+const TileShape kTuneTiles4[] = {{0}, {4, 8, 8, 16}, {4, 4, 16, 16}, {8, 8, 8, 4}};
 
 // Workspace of one batch item, relative to its base: the counts and binning
 // workspace (items that bin), the convolution workspace, the dot partials
@@ -1022,13 +1157,13 @@ ItemLayout item_layout(const kde_batch_item& it, const Plan& pl, bool internal) 
     return L;
 }
 
-kde_params batch_params(const kde_batch& b, const int tile[3]) {
+kde_params batch_params(const kde_batch& b, const int tile[kde::kMaxD]) {
     kde_params q = b.prm;
-    for (int k = 0; k < 3; ++k) q.tile[k] = tile[k];
+    for (int k = 0; k < kde::kMaxD; ++k) q.tile[k] = tile[k];
     return q;
 }
 
-int plan_item(const kde_batch& b, const kde_batch_item& it, const int tile[3], Plan* pl) {
+int plan_item(const kde_batch& b, const kde_batch_item& it, const int tile[kde::kMaxD], Plan* pl) {
     const kde_params q = batch_params(b, tile);
     return make_plan(it.H, it.n, 1, true, &it.grid, &q, pl);
 }
@@ -1036,9 +1171,10 @@ int plan_item(const kde_batch& b, const kde_batch_item& it, const int tile[3], P
 // Binning tile shapes the autotuner tries, the first being the one in use at
 // creation: the caller's shape alone if params set one, the items differ in d
 // or none of them bins; otherwise the default and the alternatives for that d.
-std::vector<std::array<int, 3>> tile_candidates(const kde_batch& b) {
-    std::vector<std::array<int, 3>> c;
-    const bool fixed = b.has_prm && (b.prm.tile[0] || b.prm.tile[1] || b.prm.tile[2]);
+std::vector<TileShape> tile_candidates(const kde_batch& b) {
+    std::vector<TileShape> c;
+    bool fixed = false;
+    for (int k = 0; k < kde::kMaxD; ++k) fixed = fixed || (b.has_prm && b.prm.tile[k]);
     int d = b.items[0].grid.d;
     bool bins = false;
     for (const auto& it : b.items) {
@@ -1046,15 +1182,16 @@ std::vector<std::array<int, 3>> tile_candidates(const kde_batch& b) {
         bins = bins || !it.counts;
     }
     if (fixed || d == 0 || !bins) {   // caller's shape, mixed d, or nothing to bin
-        c.push_back({b.has_prm ? b.prm.tile[0] : 0, b.has_prm ? b.prm.tile[1] : 0, b.has_prm ? b.prm.tile[2] : 0});
+        TileShape t{};
+        for (int k = 0; k < kde::kMaxD; ++k) t[k] = b.has_prm ? b.prm.tile[k] : 0;
+        c.push_back(t);
         return c;
     }
-    auto add = [&](const int (*t)[3], size_t nt) {
-        for (size_t j = 0; j < nt; ++j) c.push_back({t[j][0], t[j][1], t[j][2]});
-    };
-    if (d == 1) add(kTuneTiles1, sizeof(kTuneTiles1) / sizeof(kTuneTiles1[0]));
-    if (d == 2) add(kTuneTiles2, sizeof(kTuneTiles2) / sizeof(kTuneTiles2[0]));
-    if (d == 3) add(kTuneTiles3, sizeof(kTuneTiles3) / sizeof(kTuneTiles3[0]));
+    auto add = [&](const TileShape* t, size_t nt) { c.insert(c.end(), t, t + nt); };
+    if (d == 1) add(kTuneTiles1, std::size(kTuneTiles1));
+    if (d == 2) add(kTuneTiles2, std::size(kTuneTiles2));
+    if (d == 3) add(kTuneTiles3, std::size(kTuneTiles3));
+    if (d == 4) add(kTuneTiles4, std::size(kTuneTiles4));
     return c;
 }
 
@@ -1233,13 +1370,13 @@ int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& intern
         b->prm = *params;
         b->has_prm = true;
     }
-    for (int k = 0; k < 3; ++k) b->tile[k] = params ? params->tile[k] : 0;
-    const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
+    for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = params ? params->tile[k] : 0;
+    const std::vector<TileShape> cands = tile_candidates(*b);
     std::vector<size_t> need(count, 0);
     size_t cap = 0;
     int rc = KDE_OK;
     for (const auto& c : cands) {
-        for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+        for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = c[k];
         rc = layout_batch(*b);
         if (rc != KDE_OK) break;
         for (int i = 0; i < count; ++i)
@@ -1255,7 +1392,7 @@ int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& intern
         // the tables of every configuration the autotuner may bind: each tile shape with the
         // strided passes wide or narrow (narrow shapes take more workgroups, so larger owner maps)
         for (const auto& c : cands) {
-            for (int k = 0; k < 3; ++k) b->tile[k] = c[k];
+            for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = c[k];
             rc = layout_batch(*b);
             if (rc != KDE_OK) break;
             for (const int mask : {0, kAllNarrow}) {
@@ -1274,7 +1411,7 @@ int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& intern
         b->ws_bytes = b->table_cap + off_items;
     }
     if (rc == KDE_OK) {
-        for (int k = 0; k < 3; ++k) b->tile[k] = cands[0][k];
+        for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = cands[0][k];
         rc = layout_batch(*b);
         size_t tb = 0;
         if (rc == KDE_OK) rc = build_groups(*b, nullptr, b->passes, b->groups, tb);
@@ -1299,7 +1436,7 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
     // with tiled binning the spectrum's row pass rides in the sort's launch and its
     // strided pass (3-D) in the plan's
     std::vector<Pass> spec;
-    if (pl.tiled && !reuse && pl.pub.P[pl.pub.d - 1] <= kde::kSortSpecMaxP &&
+    if (pl.tiled && !reuse && pl.pub.d <= 3 && pl.pub.P[pl.pub.d - 1] <= kde::kSortSpecMaxP &&
         (pl.pub.d < 3 || pl.pub.P[1] <= kde::kSortSpecMaxP)) {
         Collect c(spec);
         KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
@@ -1310,7 +1447,7 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
     Tracer tr(params, stream);
     KDE_CHECK(tr.start());
     const int r = run_phases(
-        stream, tr, overlap && pl.pub.d == 3 && spec.empty(),
+        stream, tr, overlap && pl.pub.d >= 3 && spec.empty(),
         [&](hipStream_t s) {
             Direct e(s, tr);
             return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
@@ -1335,12 +1472,12 @@ extern "C" {
 
 int kde_grid_from_data(const double* X, int64_t n, int32_t d, const double* H, double nsd, int64_t M,
                        kde_grid* out) {
-    if (!X || !H || !out || n < 1 || d < 1 || d > 3 || M < 2 || M > (int64_t(1) << 24)) return KDE_ERR_ARG;
+    if (!X || !H || !out || n < 1 || d < 1 || d > kde::kMaxD || M < 2 || M > (int64_t(1) << 24)) return KDE_ERR_ARG;
     if (!std::isfinite(nsd) || nsd < 0.0) return KDE_ERR_ARG;
-    double Hs[3][3] = {}, R[3][3] = {};
+    double Hs[kde::kMaxD][kde::kMaxD] = {}, R[kde::kMaxD][kde::kMaxD] = {};
     const int rc = factor_bandwidth(H, d, Hs, R);
     if (rc != KDE_OK) return rc;
-    double mn[3], mx[3];
+    double mn[kde::kMaxD], mx[kde::kMaxD];
     bool any = false;
     for (int64_t i = 0; i < n; ++i) {
         const double* x = X + i * d;
@@ -1431,7 +1568,7 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     Tracer tr(params, stream);
     KDE_CHECK(tr.start());
     const int r = run_phases(
-        stream, tr, pl.pub.d == 3,
+        stream, tr, pl.pub.d >= 3,
         [&](hipStream_t s) {
             Direct e(s, tr);
             return reuse ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
@@ -1499,7 +1636,7 @@ int kde_lscv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     for (int t = 0; t < 2; ++t) {
         const Plan& pl = *plans[t];
         KDE_CHECK(run_phases(
-            stream, tr, pl.pub.d == 3,
+            stream, tr, pl.pub.d >= 3,
             [&](hipStream_t s) {
                 Direct e(s, tr);
                 return run_kspec(pl, conv_ws, -1, e);
@@ -1733,7 +1870,7 @@ int kde_batch_query(const kde_batch* b, kde_batch_info* info) {
     std::memset(info, 0, sizeof(*info));
     info->count = static_cast<int32_t>(b->items.size());
     info->ws_bytes = b->ws_bytes;
-    for (int k = 0; k < 3; ++k) info->tile[k] = b->tile[k];
+    for (int k = 0; k < kde::kMaxD; ++k) info->tile[k] = b->tile[k];
     info->narrow_mask = b->narrow_mask;
     int launches = 0;
     for (const Group& g : b->groups) launches += g.batched ? 1 : static_cast<int>(g.members.size());
@@ -1790,26 +1927,27 @@ int kde_batch_tune(kde_batch* b, int32_t reps, hipStream_t stream) {
         return KDE_OK;
     };
     int rc = KDE_OK;
-    int best_tile[3] = {b->tile[0], b->tile[1], b->tile[2]};
+    int best_tile[kde::kMaxD];
+    std::memcpy(best_tile, b->tile, sizeof(best_tile));
     float best = 0.f;
     do {
         rc = time_config(&best);
         if (rc != KDE_OK) break;
         // binning tile shape
-        const std::vector<std::array<int, 3>> cands = tile_candidates(*b);
+        const std::vector<TileShape> cands = tile_candidates(*b);
         for (size_t j = 1; j < cands.size(); ++j) {
-            for (int k = 0; k < 3; ++k) b->tile[k] = cands[j][k];
+            for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = cands[j][k];
             rc = layout_batch(*b);
             float ms = 0.f;
             if (rc == KDE_OK) rc = time_config(&ms);
             if (rc != KDE_OK) break;
             if (ms < best) {
                 best = ms;
-                for (int k = 0; k < 3; ++k) best_tile[k] = cands[j][k];
+                for (int k = 0; k < kde::kMaxD; ++k) best_tile[k] = cands[j][k];
             }
         }
         if (rc != KDE_OK) break;
-        for (int k = 0; k < 3; ++k) b->tile[k] = best_tile[k];
+        for (int k = 0; k < kde::kMaxD; ++k) b->tile[k] = best_tile[k];
         rc = layout_batch(*b);
         if (rc != KDE_OK) break;
         // strided-pass shape, one padded length at a time

@@ -130,8 +130,10 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
         KDE_LAUNCH((bin_kernel<1>), g, blk, 0, s, X, n, c, cc, nd);
     else if (c.d == 2)
         KDE_LAUNCH((bin_kernel<2>), g, blk, 0, s, X, n, c, cc, nd);
-    else
+    else if (c.d == 3)
         KDE_LAUNCH((bin_kernel<3>), g, blk, 0, s, X, n, c, cc, nd);
+    else
+        KDE_LAUNCH((bin_kernel<4>), g, blk, 0, s, X, n, c, cc, nd);
     return hipGetLastError();
 }
 
@@ -184,14 +186,16 @@ int64_t bin_stage_batch_blocks(int stage, const TileGeom& g) { return bin_stage_
 hipError_t launch_bin_stage(int stage, const BinArgs& a, hipStream_t s) {
     if (a.c.d == 1) return bin_stage_d<1>(stage, a, s);
     if (a.c.d == 2) return bin_stage_d<2>(stage, a, s);
-    return bin_stage_d<3>(stage, a, s);
+    if (a.c.d == 3) return bin_stage_d<3>(stage, a, s);
+    return bin_stage_d<4>(stage, a, s);
 }
 
 hipError_t launch_bin_stage_batch(int stage, int d, const BatchMap& m, size_t lds, hipStream_t s) {
     if (m.count <= 0 || m.blocks == 0) return hipSuccess;
     if (d == 1) return bin_stage_batch_d<1>(stage, m, lds, s);
     if (d == 2) return bin_stage_batch_d<2>(stage, m, lds, s);
-    return bin_stage_batch_d<3>(stage, m, lds, s);
+    if (d == 3) return bin_stage_batch_d<3>(stage, m, lds, s);
+    return bin_stage_batch_d<4>(stage, m, lds, s);
 }
 
 }  // namespace kde

@@ -36,32 +36,37 @@ namespace {
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-__global__ __launch_bounds__(256) void kfill_kernel(R* __restrict__ lags, int64_t count, int L0, int L1,
-                                                    int L2, R a00, R a01, R a02, R a11, R a12, R a22,
-                                                    R norm) {
+struct KfillArgs {
+    R* lags;
+    int64_t count;
+    int L[kMaxD];
+    R A[kMaxD * kMaxD];
+    R norm;
+};
+
+// Lag-box entry i in row-major order over [-L_0, L_0] x ... (last axis fastest).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void kfill_kernel(KfillArgs<R, D> a) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+    if (i >= a.count) return;
     int64_t rem = i;
-    R l0 = 0, l1 = 0, l2 = 0;
-    if constexpr (D == 3) {
-        const int64_t n2 = 2 * L2 + 1, n1 = 2 * L1 + 1;
-        l2 = static_cast<R>(rem % n2 - L2);
-        rem /= n2;
-        l1 = static_cast<R>(rem % n1 - L1);
-        rem /= n1;
-        l0 = static_cast<R>(rem - L0);
-    } else if constexpr (D == 2) {
-        const int64_t n1 = 2 * L1 + 1;
-        l1 = static_cast<R>(rem % n1 - L1);
-        rem /= n1;
-        l0 = static_cast<R>(rem - L0);
-    } else {
-        l0 = static_cast<R>(rem - L0);
+    R l[D];
+#pragma unroll
+    for (int k = D - 1; k >= 0; --k) {
+        const int64_t n = 2 * a.L[k] + 1;
+        l[k] = static_cast<R>((k ? rem % n : rem) - a.L[k]);
+        rem /= n;
     }
-    R q = a00 * l0 * l0;
-    if constexpr (D >= 2) q = fmaR(a11 * l1, l1, fmaR(R(2) * a01 * l0, l1, q));
-    if constexpr (D == 3) q = fmaR(a22 * l2, l2, fmaR(R(2) * (fmaR(a02, l0, a12 * l1)), l2, q));
-    lags[i] = norm * fexp<R>(R(-0.5) * q);
+    // q = l'Al accumulated axis by axis: A_kk l_k^2 + 2 (sum_{b<k} A_bk l_b) l_k
+    R q = a.A[0] * l[0] * l[0];
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+        R cross = a.A[(k - 1) * kMaxD + k] * l[k - 1];
+#pragma unroll
+        for (int b = k - 2; b >= 0; --b) cross = fmaR(a.A[b * kMaxD + k], l[b], cross);
+        q = fmaR(a.A[k * kMaxD + k] * l[k], l[k], fmaR(R(2) * cross, l[k], q));
+    }
+    a.lags[i] = a.norm * fexp<R>(R(-0.5) * q);
 }
 
 // ---------------------------------------------------------------------------
@@ -78,12 +83,13 @@ __global__ __launch_bounds__((RowShape<P, NARROW, kRowPassInv>::THREADS)) void r
     rows_c2r_body<R, P, MULT, NARROW>(a, blockIdx.x);
 }
 
-// The (x, y) workgroup grid is walked in XCD-major order (xcd_major).
+// A one-dimensional grid over (line block, outer index), line blocks fastest,
+// walked in XCD-major order (xcd_major).
 template <typename R, int P, int MODE, bool NARROW>
 __global__ __launch_bounds__((ColShape<R, P, NARROW>::THREADS)) void cols_kernel(ColArgs a) {
-    const uint32_t G = gridDim.x * gridDim.y;
-    const uint32_t b = xcd_major(blockIdx.y * gridDim.x + blockIdx.x, G);
-    cols_body<R, P, MODE, NARROW>(a, b % gridDim.x, b / gridDim.x);
+    const uint32_t nbx = static_cast<uint32_t>(ceil_div(a.W, ColShape<R, P, NARROW>::B));
+    const uint32_t b = xcd_major(blockIdx.x, gridDim.x);
+    cols_body<R, P, MODE, NARROW>(a, b % nbx, b / nbx);
 }
 
 // Row launches with fewer than this many workgroups use the narrow shape.
@@ -94,15 +100,17 @@ constexpr int64_t kRowNarrowBelow = 256;
 // ---------------------------------------------------------------------------
 
 template <typename R, int D>
-hipError_t kfill_launch(const int L[3], const double A[9], double norm, void* lags, hipStream_t s) {
-    int64_t count = 1;
-    for (int k = 0; k < D; ++k) count *= 2 * L[k] + 1;
-    const int64_t blocks = ceil_div(count, 256);
-    KDE_LAUNCH((kfill_kernel<R, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       static_cast<R*>(lags), count, L[0], D > 1 ? L[1] : 0, D > 2 ? L[2] : 0,
-                       static_cast<R>(A[0]), static_cast<R>(A[1]), static_cast<R>(A[2]),
-                       static_cast<R>(A[4]), static_cast<R>(A[5]), static_cast<R>(A[8]),
-                       static_cast<R>(norm));
+hipError_t kfill_launch(const int L[kMaxD], const double A[kMaxD * kMaxD], double norm, void* lags, hipStream_t s) {
+    KfillArgs<R, D> a{};
+    a.lags = static_cast<R*>(lags);
+    a.count = 1;
+    for (int k = 0; k < D; ++k) {
+        a.L[k] = L[k];
+        a.count *= 2 * L[k] + 1;
+    }
+    for (int k = 0; k < kMaxD * kMaxD; ++k) a.A[k] = static_cast<R>(A[k]);
+    a.norm = static_cast<R>(norm);
+    KDE_LAUNCH((kfill_kernel<R, D>), dim3(static_cast<unsigned>(ceil_div(a.count, 256))), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -127,7 +135,8 @@ hipError_t rows_r2c_launch(int kind, int d, const void* args, hipStream_t s) {
     if (kind == kRowCountsU64) return rows_r2c_pick<R, P, kRowCountsU64, false, 1>(a, s);
     if (d == 1) return rows_r2c_pick<R, P, kRowGaussCirc, true, 1>(a, s);
     if (d == 2) return rows_r2c_pick<R, P, kRowGaussCirc, false, 2>(a, s);
-    return rows_r2c_pick<R, P, kRowGaussCirc, false, 3>(a, s);
+    if (d == 3) return rows_r2c_pick<R, P, kRowGaussCirc, false, 3>(a, s);
+    return rows_r2c_pick<R, P, kRowGaussCirc, false, 4>(a, s);
 }
 
 template <typename R, int P, bool NARROW>
@@ -152,7 +161,9 @@ hipError_t rows_c2r_launch(const void* args, hipStream_t s) {
 template <typename R, int P, bool NARROW>
 hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
     constexpr int B = ColShape<R, P, NARROW>::B;
-    const dim3 g(static_cast<unsigned>(ceil_div(a.W, B)), static_cast<unsigned>(a.outer));
+    const int64_t blocks = ceil_div(a.W, B) * a.outer;
+    if (blocks <= 0 || blocks > INT32_MAX) return hipErrorInvalidValue;
+    const dim3 g(static_cast<unsigned>(blocks));
     const dim3 blk(ColShape<R, P, NARROW>::THREADS);
     switch (mode) {
         case kColFwdPrefix: KDE_LAUNCH((cols_kernel<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, a); break;
@@ -207,16 +218,18 @@ hipError_t cols_any(int P, int mode, int narrow, const ColArgs& a, hipStream_t s
 
 }  // namespace
 
-hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], double norm, void* lags,
-                        hipStream_t s) {
+hipError_t launch_kfill(int prec, int d, const int L[kMaxD], const double A[kMaxD * kMaxD], double norm,
+                        void* lags, hipStream_t s) {
     if (prec == 2) {
         if (d == 1) return kfill_launch<double, 1>(L, A, norm, lags, s);
         if (d == 2) return kfill_launch<double, 2>(L, A, norm, lags, s);
-        return kfill_launch<double, 3>(L, A, norm, lags, s);
+        if (d == 3) return kfill_launch<double, 3>(L, A, norm, lags, s);
+        return kfill_launch<double, 4>(L, A, norm, lags, s);
     }
     if (d == 1) return kfill_launch<float, 1>(L, A, norm, lags, s);
     if (d == 2) return kfill_launch<float, 2>(L, A, norm, lags, s);
-    return kfill_launch<float, 3>(L, A, norm, lags, s);
+    if (d == 3) return kfill_launch<float, 3>(L, A, norm, lags, s);
+    return kfill_launch<float, 4>(L, A, norm, lags, s);
 }
 
 hipError_t launch_rows_r2c(int prec, int P, int input_kind, int d, const void* args, hipStream_t s) {

@@ -45,8 +45,10 @@ hipError_t rows_r2c_batch_launch(int kind, int d, const BatchMap& m, hipStream_t
         KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, true, 1>), g, blk, 0, s, m);
     else if (d == 2)
         KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, false, 2>), g, blk, 0, s, m);
-    else
+    else if (d == 3)
         KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, false, 3>), g, blk, 0, s, m);
+    else
+        KDE_LAUNCH((rows_r2c_batch<R, P, kRowGaussCirc, false, 4>), g, blk, 0, s, m);
     return hipGetLastError();
 }
 

@@ -358,18 +358,28 @@ struct RowShape {
     static constexpr int THREADS = T * B;
 };
 
+// q = l'Al accumulated axis by axis, each new axis k adding A_kk l_k^2 + 2 (sum_{a<k} A_ak l_a) l_k.
 template <typename R, int D>
-__device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2) {
+__device__ __forceinline__ R gauss_weight(const RowArgs<R>& g, R l0, R l1, R l2, R l3 = R(0)) {
     R q = g.a00 * l0 * l0;
     if constexpr (D >= 2) q = fmaR(g.a11 * l1, l1, fmaR(R(2) * g.a01 * l0, l1, q));
-    if constexpr (D == 3) q = fmaR(g.a22 * l2, l2, fmaR(R(2) * (fmaR(g.a02, l0, g.a12 * l1)), l2, q));
+    if constexpr (D >= 3) q = fmaR(g.a22 * l2, l2, fmaR(R(2) * (fmaR(g.a02, l0, g.a12 * l1)), l2, q));
+    if constexpr (D == 4)
+        q = fmaR(g.a33 * l3, l3, fmaR(R(2) * (fmaR(g.a03, l0, fmaR(g.a13, l1, g.a23 * l2))), l3, q));
     return g.norm * fexp<R>(R(-0.5) * q);
 }
 
-// Leading lags of lag-box row r: d = 2 -> (r - L0); d = 3 -> (r / n1 - L0, r % n1 - L1).
+// Leading lags of lag-box row r: d = 2 -> (r - L0); d = 3 -> (r / n1 - L0, r % n1 - L1);
+// d = 4 -> (r / (n1 n2) - L0, (r / n2) % n1 - L1, r % n2 - L2).
 template <typename R, int D>
-__device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, R& l1) {
-    if constexpr (D == 3) {
+__device__ __forceinline__ void row_lags(const RowArgs<R>& g, int64_t r, R& l0, R& l1, R& l2) {
+    l2 = 0;
+    if constexpr (D == 4) {
+        const int64_t n1 = 2 * g.L1 + 1, n2 = 2 * g.L2 + 1;
+        l0 = static_cast<R>(r / (n1 * n2) - g.L0);
+        l1 = static_cast<R>((r / n2) % n1 - g.L1);
+        l2 = static_cast<R>(r % n2 - g.L2);
+    } else if constexpr (D == 3) {
         const int64_t n1 = 2 * g.L1 + 1;
         l0 = static_cast<R>(r / n1 - g.L0);
         l1 = static_cast<R>(r % n1 - g.L1);
@@ -409,10 +419,10 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
         }
     } else {
         // weights of two lag-box rows; the last-axis lag l sits at position l mod P
-        R a0 = 0, b0 = 0, a1 = 0, b1 = 0;
+        R a0 = 0, b0 = 0, c0 = 0, a1 = 0, b1 = 0, c1 = 0;
         if (D > 1) {
-            row_lags<R, D>(gw, r0, a0, b0);
-            row_lags<R, D>(gw, r1, a1, b1);
+            row_lags<R, D>(gw, r0, a0, b0, c0);
+            row_lags<R, D>(gw, r1, a1, b1, c1);
         }
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -426,9 +436,12 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
                 } else if constexpr (D == 2) {
                     if (ok0) x = gauss_weight<R, 2>(gw, a0, l, R(0));
                     if (ok1) y = gauss_weight<R, 2>(gw, a1, l, R(0));
-                } else {
+                } else if constexpr (D == 3) {
                     if (ok0) x = gauss_weight<R, 3>(gw, a0, b0, l);
                     if (ok1) y = gauss_weight<R, 3>(gw, a1, b1, l);
+                } else {
+                    if (ok0) x = gauss_weight<R, 4>(gw, a0, b0, c0, l);
+                    if (ok1) y = gauss_weight<R, 4>(gw, a1, b1, c1, l);
                 }
             }
             v[m] = C{x, y};
@@ -537,9 +550,9 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
     __shared__ C lds[B * (P + P / 16)];
     const int b = threadIdx.x & (B - 1), t = threadIdx.x / B;
     const int64_t w = static_cast<int64_t>(bx) * B + b;
-    const int64_t o = by;
+    const int64_t o1 = a.ob ? by / a.ob : 0, o = a.ob ? by % a.ob : by;   // two-level outer index
     const bool act = w < a.W;
-    const C* in = static_cast<const C*>(a.in) + o * a.in_os + w;
+    const C* in = static_cast<const C*>(a.in) + o1 * a.in_os1 + o * a.in_os + w;
     C v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -558,7 +571,7 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
     if constexpr (MODE == kColConvLag) {
         // the spectrum of this line: transform of the lag column, placed circularly
         // (it is real because the lag box is centrally symmetric)
-        const C* kin = static_cast<const C*>(a.kt) + o * a.kt_os + w;
+        const C* kin = static_cast<const C*>(a.kt) + o1 * a.kt_os1 + o * a.kt_os + w;
         C kv[E];
 #pragma unroll
         for (int m = 0; m < E; ++m) {
@@ -578,11 +591,11 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
     }
     if (!act) return;
     if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
-        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
+        C* out = static_cast<C*>(a.out) + o1 * a.out_os1 + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < E; ++m) out[(t + T * m) * a.out_ps] = v[m];
     } else {   // kColConvLag (in place) and kColInvPrefix: keep [0, mout)
-        C* out = static_cast<C*>(a.out) + o * a.out_os + w;
+        C* out = static_cast<C*>(a.out) + o1 * a.out_os1 + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int p = t + T * m;

@@ -46,6 +46,7 @@ __device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t G) {
 constexpr size_t kScratchBytes = size_t(256) << 20;
 hipError_t scratch_address(int dev, void** out);
 
+constexpr int kMaxD = 4;      // largest dimension
 constexpr int kMaxP = 4096;   // largest padded FFT length per axis
 constexpr int kMinP = 16;     // smallest (one radix-16 stage)
 
@@ -53,11 +54,11 @@ constexpr int kMinP = 16;     // smallest (one radix-16 stage)
 struct BinConsts {
     int d;
     int Q;
-    int64_t M[3];
-    int64_t stride[3];      // row-major element strides of the counts array
-    double lo[3];
-    double delta[3];
-    double top[3];          // M_k - 1 as a double
+    int64_t M[kMaxD];
+    int64_t stride[kMaxD];  // row-major element strides of the counts array
+    double lo[kMaxD];
+    double delta[kMaxD];
+    double top[kMaxD];      // M_k - 1 as a double
 };
 
 // Tiled binning: the grid is cut into tiles of T_1 x ... x T_d cells; every
@@ -86,12 +87,12 @@ constexpr int kMaxChunks = 2048;             // chunk-indexed LDS arrays of the 
 constexpr int kSplitRecords = 4096;          // records of one gather segment at most
 
 struct TileGeom {
-    int T[3];               // tile extent (cells, power of two) per axis
-    int logT[3];
-    int nt[3];              // tiles per axis
+    int T[kMaxD];           // tile extent (cells, power of two) per axis
+    int logT[kMaxD];
+    int nt[kMaxD];          // tiles per axis
     int ntiles;
     int tile_cells;         // prod T
-    int jbits[3];           // record bits of (tile-local lower corner + 1) per axis
+    int jbits[kMaxD];       // record bits of (tile-local lower corner + 1) per axis
     int qbits;              // record bits of one fraction q (Q + 1)
     int64_t nchunk;         // ceil(n / kBinChunk)
     int64_t chunk_cap;      // records a chunk's region holds: kBinChunk 2^d
@@ -136,10 +137,10 @@ enum RowInput : int {
 // k_l = norm exp(-0.5 l'Al) on the lag box [-L, L]^d; A_ab = delta_a delta_b (H^-1)_ab.
 // Row r of the row pass is the lag box row with leading lags (l_1, .., l_{d-1}).
 struct GaussLag {
-    double A[9];
+    double A[kMaxD * kMaxD];
     double norm;
     int d;
-    int L[3];
+    int L[kMaxD];
 };
 
 // Arguments of the row (contiguous-axis) r2c pass in the working precision R.
@@ -148,8 +149,8 @@ struct RowArgs {
     const void* in;         // uint64 counts rows (kRowCountsU64); unused for kRowGaussCirc
     int64_t nrows, in_ld;
     int len;                // nonzero prefix of a counts row, or L of the last axis (weights)
-    R a00, a01, a02, a11, a12, a22, norm;   // weights: norm exp(-0.5 l'Al)
-    int L0, L1;             // weights: half widths of the leading axes
+    R a00, a01, a02, a03, a11, a12, a13, a22, a23, a33, norm;   // weights: norm exp(-0.5 l'Al)
+    int L0, L1, L2;         // weights: half widths of the leading axes
     void* out;
     int64_t out_ld;
 };
@@ -176,13 +177,19 @@ enum ColMode : int {
                             // placed lag column (kt, 2 kt_len + 1 entries), computed in place
 };
 
+// The outer index o of a strided pass splits as o1 = o / ob, o2 = o % ob (ob = 0:
+// o2 = o, o1 = 0), the lines of o at o1 os1 + o2 os from the base: two levels,
+// for the middle axes of a 4-D array whose leading and trailing axes change
+// length between input and output.
 struct ColArgs {
     const void* in;
     void* out;
     int64_t W;              // lines per outer index (lines are adjacent in memory)
     int64_t outer;          // number of outer indices (grid.y)
+    int64_t ob;             // inner extent of the outer index (0: one level)
     int64_t in_os, in_ps;   // input: outer stride, element stride (complex elements)
     int64_t out_os, out_ps; // output: outer stride, element stride
+    int64_t in_os1, out_os1, kt_os1;   // strides of o1 (two-level outer index)
     int len;                // nonzero input prefix length, or L for circular inputs
     int mout;               // kept output prefix length
     const void* kt;         // kColConvLag: lag columns transformed along the other axes
@@ -202,15 +209,21 @@ RowArgs<R> make_row_args(const void* in, const GaussLag* gauss, int64_t nrows, i
     a.out = out;
     a.out_ld = out_ld;
     if (gauss) {
-        a.a00 = static_cast<R>(gauss->A[0]);
-        a.a01 = static_cast<R>(gauss->A[1]);
-        a.a02 = static_cast<R>(gauss->A[2]);
-        a.a11 = static_cast<R>(gauss->A[4]);
-        a.a12 = static_cast<R>(gauss->A[5]);
-        a.a22 = static_cast<R>(gauss->A[8]);
+        const double* A = gauss->A;   // row-major kMaxD x kMaxD
+        a.a00 = static_cast<R>(A[0]);
+        a.a01 = static_cast<R>(A[1]);
+        a.a02 = static_cast<R>(A[2]);
+        a.a03 = static_cast<R>(A[3]);
+        a.a11 = static_cast<R>(A[kMaxD + 1]);
+        a.a12 = static_cast<R>(A[kMaxD + 2]);
+        a.a13 = static_cast<R>(A[kMaxD + 3]);
+        a.a22 = static_cast<R>(A[2 * kMaxD + 2]);
+        a.a23 = static_cast<R>(A[2 * kMaxD + 3]);
+        a.a33 = static_cast<R>(A[3 * kMaxD + 3]);
         a.norm = static_cast<R>(gauss->norm);
         a.L0 = gauss->L[0];
         a.L1 = gauss->L[1];
+        a.L2 = gauss->L[2];
     }
     return a;
 }
@@ -253,8 +266,8 @@ hipError_t launch_plan_kcol(int prec, int P, const PlanColArgs& a, hipStream_t s
 hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s);
 hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* counts,
                       uint64_t* n_dropped, hipStream_t s);
-// k_l = norm exp(-0.5 l'Al) on the lag box; A is d x d row-major, in FP64 from the host.
-hipError_t launch_kfill(int prec, int d, const int L[3], const double A[9], double norm,
+// k_l = norm exp(-0.5 l'Al) on the lag box; A is kMaxD x kMaxD row-major, in FP64 from the host.
+hipError_t launch_kfill(int prec, int d, const int L[kMaxD], const double A[kMaxD * kMaxD], double norm,
                         void* lags, hipStream_t s);
 // Row passes: `args` points to RowArgs<R> / C2RArgs<R> of the precision prec
 // (1: float, 2: double); d is the lag-box dimension of kRowGaussCirc inputs.

@@ -45,14 +45,17 @@ class KdeError(RuntimeError):
         self.code = code
 
 
+MAX_D = 4   # KDE_MAX_D
+
+
 class KdeGrid(ctypes.Structure):
-    _fields_ = [("d", ctypes.c_int32), ("reserved", ctypes.c_int32), ("M", ctypes.c_int64 * 3),
-                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+    _fields_ = [("d", ctypes.c_int32), ("reserved", ctypes.c_int32), ("M", ctypes.c_int64 * MAX_D),
+                ("lo", ctypes.c_double * MAX_D), ("hi", ctypes.c_double * MAX_D)]
 
 
 class KdeParams(ctypes.Structure):
-    _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * 3), ("Q", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * 3), ("extent", ctypes.c_int32), ("reuse_spectrum", ctypes.c_int32),
+    _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * MAX_D), ("Q", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * MAX_D), ("extent", ctypes.c_int32), ("reuse_spectrum", ctypes.c_int32),
                 ("trace_capacity", ctypes.c_int32),
                 ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
                 ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
@@ -60,8 +63,8 @@ class KdeParams(ctypes.Structure):
 
 class KdePlan(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("Q", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("L", ctypes.c_int32 * 3), ("P", ctypes.c_int32 * 3), ("reserved", ctypes.c_int32),
-                ("delta", ctypes.c_double * 3), ("lambda_max", ctypes.c_double), ("det_H", ctypes.c_double),
+                ("L", ctypes.c_int32 * MAX_D), ("P", ctypes.c_int32 * MAX_D), ("reserved", ctypes.c_int32),
+                ("delta", ctypes.c_double * MAX_D), ("lambda_max", ctypes.c_double), ("det_H", ctypes.c_double),
                 ("norm", ctypes.c_double), ("lag_count", ctypes.c_int64), ("lag_bytes", ctypes.c_size_t),
                 ("conv_ws_bytes", ctypes.c_size_t), ("eval_ws_bytes", ctypes.c_size_t),
                 ("density_bytes", ctypes.c_size_t), ("bin_ws_bytes", ctypes.c_size_t),
@@ -69,19 +72,19 @@ class KdePlan(ctypes.Structure):
 
 
 class KdeBatchItem(ctypes.Structure):
-    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * 9), ("grid", KdeGrid),
+    _fields_ = [("X", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * (MAX_D * MAX_D)), ("grid", KdeGrid),
                 ("density", ctypes.c_void_p), ("n_dropped", ctypes.c_void_p), ("counts", ctypes.c_void_p),
                 ("dot", ctypes.c_void_p)]
 
 
 class KdeLscvItem(ctypes.Structure):
-    _fields_ = [("counts", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * 9), ("grid", KdeGrid),
+    _fields_ = [("counts", ctypes.c_void_p), ("n", ctypes.c_int64), ("H", ctypes.c_double * (MAX_D * MAX_D)), ("grid", KdeGrid),
                 ("out", ctypes.c_void_p)]
 
 
 class KdeBatchInfo(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("launches", ctypes.c_int32), ("ws_bytes", ctypes.c_size_t),
-                ("tile", ctypes.c_int32 * 3), ("narrow_mask", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * MAX_D), ("narrow_mask", ctypes.c_int32)]
 
 
 class KdeMlpInfo(ctypes.Structure):
@@ -156,8 +159,8 @@ def make_grid(lo, hi, M) -> KdeGrid:
     hi = np.atleast_1d(np.asarray(hi, dtype=np.float64))
     M = np.atleast_1d(np.asarray(M, dtype=np.int64))
     d = int(M.size)
-    if lo.size != d or hi.size != d or not 1 <= d <= 3:
-        raise ValueError("lo, hi and M need one entry per axis, 1 <= d <= 3")
+    if lo.size != d or hi.size != d or not 1 <= d <= MAX_D:
+        raise ValueError(f"lo, hi and M need one entry per axis, 1 <= d <= {MAX_D}")
     g = KdeGrid()
     g.d = d
     for k in range(d):

@@ -57,7 +57,7 @@ def test_plan_matches_oracle(name):
 def test_plan_random_spd_matches_oracle():
     rng = np.random.default_rng(4)
     for trial in range(200):
-        d = int(rng.integers(1, 4))
+        d = int(rng.integers(1, 5))
         H = W.random_spd(rng, d, lam_min=(0.01, 0.5), ratio=(1.0, 50.0))
         M = tuple(int(m) for m in rng.integers(2, 200, size=d))
         lo = rng.uniform(-5, 0, size=d)
@@ -67,6 +67,21 @@ def test_plan_random_spd_matches_oracle():
         op = O.plan(H, lo, hi, M, n)
         assert plan["L"] == op["L"], (trial, plan["L"], op["L"])
         assert plan["lambda_max"] == pytest.approx(O.lambda_max(H), rel=1e-12)
+
+
+def test_plan_4d_matches_oracle():
+    """d = 4: Eq. (15) with lambda_max from the cyclic Jacobi rotations, |H|, k_0, the default
+    8^4 binning tile (record: 4 x 9 fraction bits + 4 x 4 corner bits) and a workspace."""
+    w = W.small_mixture(seed=70, d=4, n=20_000, M=(24, 20, 18, 30))
+    plan = K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M))
+    op = O.plan(w.H, w.lo, w.hi, w.M, w.n)
+    assert plan["d"] == 4 and plan["Q"] == 8 and plan["L"] == op["L"]
+    assert plan["lambda_max"] == pytest.approx(np.linalg.eigvalsh(w.H)[-1], rel=1e-13)
+    assert plan["det_H"] == pytest.approx(np.linalg.det(w.H), rel=1e-12)
+    k0 = O.lag_weights(w.H, op["delta"], (0,) * 4, w.n).ravel()[0]
+    assert plan["norm"] == pytest.approx(k0, rel=1e-13)
+    assert plan["bin_ws_bytes"] > 0 and plan["conv_ws_bytes"] > 0
+    assert plan["lag_count"] == np.prod([2 * l + 1 for l in op["L"]])
 
 
 def test_plan_binning_only():
@@ -114,11 +129,12 @@ def test_plan_errors():
     assert _code(np.zeros((2, 2)), 10, good) == -2
     assert _code(H, 2 ** 33, good) == -3                               # n 2^32 overflows
     assert _code(H, 10, ([-1, -1], [1, 1], [4000, 32])) == -5          # P > 4096
-    g4 = K.make_grid([0.0] * 3, [1.0] * 3, [4] * 3)
-    g4.d = 4                                                           # d outside {1, 2, 3}
+    g5 = K.make_grid([0.0] * 4, [1.0] * 4, [4] * 4)
+    g5.d = 5                                                           # d outside {1, 2, 3, 4}
     out = KB.KdePlan()
-    H4 = np.eye(4).ctypes.data_as(ctypes.c_void_p)
-    assert K.lib().kde_plan_query(H4, 10, ctypes.byref(g4), None, ctypes.byref(out)) == -1
+    H5 = np.eye(5)
+    assert K.lib().kde_plan_query(H5.ctypes.data_as(ctypes.c_void_p), 10, ctypes.byref(g5), None,
+                                  ctypes.byref(out)) == -1
 
 
 def test_device_entry_points_reject_before_enqueue():
@@ -222,7 +238,7 @@ def test_batch_plan_errors():
     assert _batch_info(ok, p)[0] == -1
     p.tile[0], p.tile[1] = 16, 64
     rc, info = _batch_info(ok, p)
-    assert rc == 0 and tuple(info.tile) == (16, 64, 0)
+    assert rc == 0 and tuple(info.tile) == (16, 64, 0, 0)
     assert lib.kde_batch_query(None, ctypes.byref(KB.KdeBatchInfo())) == -1
 
 
@@ -366,7 +382,7 @@ def test_grid_from_data_errors():
     assert call(Xp, 2, 2, Hp, 3.0, 64, ctypes.byref(g)) == 0 and g.d == 2
     assert call(None, 2, 2, Hp, 3.0, 64, ctypes.byref(g)) == -1          # no samples
     assert call(Xp, 0, 2, Hp, 3.0, 64, ctypes.byref(g)) == -1            # n < 1
-    assert call(Xp, 2, 4, Hp, 3.0, 64, ctypes.byref(g)) == -1            # d outside {1, 2, 3}
+    assert call(Xp, 2, 5, Hp, 3.0, 64, ctypes.byref(g)) == -1            # d outside {1, 2, 3, 4}
     assert call(Xp, 2, 2, Hp, 3.0, 1, ctypes.byref(g)) == -1             # M < 2
     assert call(Xp, 2, 2, Hp, -1.0, 64, ctypes.byref(g)) == -1           # negative nsd
     assert call(Xp, 2, 2, Hp, float("nan"), 64, ctypes.byref(g)) == -1

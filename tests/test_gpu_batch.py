@@ -83,6 +83,27 @@ def test_batch_mixed_dimensions_and_atomic_fallback():
         _assert_matches_single(B, items, **opts)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_four_dimensional_items(prec):
+    """d = 4 items (three strided passes per transform direction) beside 2-D and 3-D ones;
+    Q = 12 sends the 4-D items to the atomic binning (4 x 13 fraction bits plus the corner
+    bits exceed a 64-bit record) while the others tile."""
+    wl = [W.small_mixture(90 + i, d, n, M) for i, (d, n, M) in enumerate(
+        [(4, 20000, (12, 10, 9, 14)), (2, 5000, (40, 33)), (4, 3000, 16), (3, 8000, (12, 20, 9)),
+         (4, 40000, (20, 24, 18, 30))])]
+    items = _items(wl)
+    for Q in (None, 12):
+        opts = {"prec": prec} if Q is None else {"prec": prec, "Q": Q}
+        B = K.KdeBatch(items, n_dropped=True, **opts)
+        B.eval()
+        torch.cuda.synchronize()
+        _assert_matches_single(B, items, **opts)
+    for i in (0, 4):    # the last batch ran with Q = 12
+        ref, _ = O.kde_binned(wl[i].X, wl[i].H, wl[i].lo, wl[i].hi, wl[i].M, Q=12, method="fft")
+        got = B.densities[i].double().cpu().numpy()
+        assert float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))) <= TOL[prec], i
+
+
 def test_batch_graph_capture_replays_match_eager():
     wl = W.batch2d(12, seed_offset=13, n_range=(1e3, 3e4), sides=(64, 128, 256))
     items = _items(wl)
@@ -134,7 +155,7 @@ def test_batch_tune_keeps_results():
     torch.cuda.synchronize()
     ref = [d.clone() for d in B.densities]
     info = B.tune(reps=2)
-    assert info["tile"] in [(0, 0, 0), (16, 64, 0), (64, 16, 0), (64, 64, 0), (16, 16, 0)]
+    assert info["tile"] in [(0, 0, 0, 0), (16, 64, 0, 0), (64, 16, 0, 0), (64, 64, 0, 0), (16, 16, 0, 0)]
     B.eval()
     torch.cuda.synchronize()
     for i, d in enumerate(B.densities):

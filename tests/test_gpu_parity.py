@@ -60,7 +60,8 @@ def test_bin_workloads_bit_exact(name):
 
 
 @pytest.mark.parametrize("d,M,Q", [(1, (1000,), None), (1, (7,), 20), (2, (37, 50), None), (2, (2, 2), None),
-                                   (3, (5, 9, 17), None), (3, (40, 33, 2), 8), (2, (300, 3), 24)])
+                                   (3, (5, 9, 17), None), (3, (40, 33, 2), 8), (2, (300, 3), 24),
+                                   (4, (7, 9, 5, 11), None), (4, (24, 24, 24, 24), None), (4, (3, 40, 2, 17), 6)])
 def test_bin_ragged_bit_exact(d, M, Q):
     rng = np.random.default_rng(100 + d)
     n = 50_000
@@ -92,7 +93,7 @@ def test_bin_tile_edges_bit_exact():
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("d,M,Q", [(2, (300, 3), 27), (1, (50,), 60), (3, (9, 10, 11), 20)])
+@pytest.mark.parametrize("d,M,Q", [(2, (300, 3), 27), (1, (50,), 60), (3, (9, 10, 11), 20), (4, (5, 6, 7, 8), 14)])
 def test_bin_atomic_fallback_bit_exact(d, M, Q):
     """Records wider than 64 bits (large Q) take the global-atomic kernel; same results."""
     plan = K.kde_plan_query(None, 10, ([0.0] * d, [1.0] * d, M), Q=Q)
@@ -107,7 +108,7 @@ def test_bin_atomic_fallback_bit_exact(d, M, Q):
 
 
 @pytest.mark.parametrize("d,M,center", [(2, (512, 512), 0.0), (2, (100, 70), 0.97), (3, (40, 50, 37), 0.95),
-                                         (1, (5000,), 0.99)])
+                                         (1, (5000,), 0.99), (4, (24, 24, 24, 24), 0.9)])
 def test_bin_heavy_tile_segments(d, M, center):
     """Most samples in one tile (also a ragged tile at the far edge of the grid): hundreds of
     thousands of records in one tile, cut into segments whose gather workgroups add into
@@ -121,7 +122,7 @@ def test_bin_heavy_tile_segments(d, M, center):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 @pytest.mark.parametrize("n", [1, 2, 511, 2047, 2048, 2049, 16_385])
 def test_bin_chunk_boundaries(d, n):
     """Sample counts around the 2048-sample chunk of the sort pass (a last chunk of one
@@ -129,7 +130,7 @@ def test_bin_chunk_boundaries(d, n):
     rng = np.random.default_rng(700 + 10 * d)
     X = rng.normal(size=(n, d))
     lo, hi = np.full(d, -3.0), np.full(d, 3.0)
-    M = {1: (300,), 2: (61, 70), 3: (20, 17, 33)}[d]
+    M = {1: (300,), 2: (61, 70), 3: (20, 17, 33), 4: (9, 10, 11, 12)}[d]
     ref, rnd = O.bin_fixed(X, lo, hi, M)
     got, gnd = _counts(X, lo, hi, M)
     assert gnd == rnd
@@ -164,6 +165,19 @@ def test_kernel_grid(prec, name):
     assert np.max(np.abs(got - ref)) <= tol * ref.max()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_kernel_grid_4d(prec):
+    w = W.small_mixture(seed=71, d=4, n=20_000, M=(20, 24, 18, 30))
+    p = O.plan(w.H, w.lo, w.hi, w.M, w.n)
+    ref = O.lag_weights(w.H, p["delta"], p["L"], w.n)
+    got = K.kde_kernel_grid(w.H, w.n, (w.lo, w.hi, w.M), prec=prec, device=DEV)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert got.shape == ref.shape
+    tol = 2e-6 if prec == "f32" else 1e-14
+    assert np.max(np.abs(got - ref)) <= tol * ref.max()
+
+
 # --------------------------------------------------------------------------
 # convolution from exact counts (Eq. 7): isolates the FFT path
 # --------------------------------------------------------------------------
@@ -187,6 +201,11 @@ CONV_CASES = [
     (2, (520, 700), 15, None, 1.0),        # P = 1024 on both axes
     (3, (7, 9, 300), 16, None, 1.0),       # P_3 = 512: row passes at 4 / 8 points per thread
     (3, (300, 7, 9), 17, None, 1.0),       # P_1 = 512: product pass at 8 points per thread
+    (4, (24, 24, 24, 24), 18, None, 1.0),  # 4-D: three strided passes each way
+    (4, (20, 24, 18, 30), 19, None, 1.0),  # ragged, P_4 = 64 != P_1..3
+    (4, (6, 5, 4, 7), 20, (5, 4, 3, 6), 1.0),   # full lag box, P = 16
+    (4, (9, 12, 7, 40), 21, None, 2.0),
+    (4, (40, 6, 5, 9), 22, None, 1.0),     # P_1 = 64: the product pass on the longest axis
 ]
 
 
@@ -218,6 +237,24 @@ def test_eval_small_workload(prec):
     torch.cuda.synchronize()
     assert int(nd.cpu().numpy()[0]) == 0
     assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_4d(prec):
+    """The whole estimate in d = 4 on a 24^4 grid: every cell against the oracle's FFT form of
+    Eq. (7), and sampled cells against the direct sum evaluated one by one."""
+    w = W.small_mixture(seed=72, d=4, n=50_000, M=24)
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method="fft")
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert int(nd.cpu().numpy()[0]) == info["n_dropped"] == 0
+    assert _rel(got, f) <= TOL[prec]
+    rng = np.random.default_rng(3)
+    pts = [tuple(int(v) for v in rng.integers(0, 24, size=4)) for _ in range(40)]
+    pts.append(tuple(int(v) for v in np.unravel_index(np.argmax(f), f.shape)))
+    direct = O.conv_direct_at(info["c"], info["k"], info["L"], pts)
+    assert np.max(np.abs(np.array([got[p] for p in pts]) - direct)) <= TOL[prec] * np.max(f)
 
 
 def test_eval_small_diagonal_and_full_differ():

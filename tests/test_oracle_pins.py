@@ -71,7 +71,20 @@ def test_binning_hand_cases_1d_3d():
     assert int(c3.sum()) == 2 ** 30
 
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+def test_binning_hand_case_4d():
+    """d = 4, Q = 8: fractions (1/4, 1/2, 0, 3/4) give the per-axis weight pairs (192, 64),
+    (128, 128), (256, 0), (64, 192); corner b receives their product."""
+    c4, nd4 = O.bin_fixed(np.array([[0.25, 0.5, 0.0, 0.75]]), [0.0] * 4, [1.0] * 4, (2, 2, 2, 2))
+    assert nd4 == 0 and O.default_Q(4) == 8
+    assert int(c4[0, 0, 0, 0]) == 402_653_184        # 192 128 256 64
+    assert int(c4[0, 0, 0, 1]) == 1_207_959_552      # 192 128 256 192
+    assert int(c4[1, 1, 0, 0]) == 134_217_728        # 64 128 256 64
+    assert int(c4[1, 0, 0, 1]) == 402_653_184        # 64 128 256 192
+    assert not c4[:, :, 1, :].any()                  # q = 0 on axis 3: nothing on the upper face
+    assert int(c4.sum()) == 2 ** 32
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_binning_counts_sum_to_n(d):
     """Grid counts sum to n (Section 3 footnote), here n - n_dropped exactly in units 2^-dQ."""
     rng = np.random.default_rng(5 + d)
@@ -82,6 +95,20 @@ def test_binning_counts_sum_to_n(d):
     inside = np.all((X >= -3.0) & (X <= 3.0), axis=1)
     assert nd == n - inside.sum() and nd > 0
     assert int(counts.sum(dtype=np.uint64)) == (n - nd) * 2 ** (d * O.default_Q(d))
+
+
+def test_binning_first_moment_4d():
+    """The same in d = 4 (Q = 8) on every axis: a transposed or shifted corner index fails it."""
+    w = W.small_mixture(seed=61, d=4, n=5000, M=(9, 12, 7, 10))
+    counts, nd = O.bin_fixed(w.X, w.lo, w.hi, w.M)
+    assert nd == 0
+    c = O.counts_to_c(counts, 4)
+    g = O.grid_axes(w.lo, w.hi, w.M)
+    delta = O.bin_width(w.lo, w.hi, w.M)
+    for a in range(4):
+        marg = c.sum(axis=tuple(b for b in range(4) if b != a))
+        tol = w.n * delta[a] * 2.0 ** -(8 + 1) + 1e-9
+        assert abs((marg * g[a]).sum() - w.X[:, a].sum()) <= tol, a
 
 
 def test_binning_first_moment():
@@ -137,11 +164,12 @@ def test_paper_constants_fixture():
     np.array([[0.09, 0.06], [0.06, 0.08]]),
     np.array([[0.5, -0.2, 0.1], [-0.2, 0.3, 0.05], [0.1, 0.05, 0.2]]),
     np.array([[0.04]]),
+    np.array([[0.5, -0.2, 0.1, 0.05], [-0.2, 0.3, 0.05, -0.1], [0.1, 0.05, 0.2, 0.02], [0.05, -0.1, 0.02, 0.25]]),
 ])
 def test_lag_weights_vs_scipy_mvn(H):
     d = H.shape[0]
-    delta = np.array([0.11, 0.07, 0.13][:d])
-    L = tuple([4, 5, 3][:d])
+    delta = np.array([0.11, 0.07, 0.13, 0.09][:d])
+    L = tuple([4, 5, 3, 2][:d])
     n = 37
     k = O.lag_weights(H, delta, L, n)
     mvn = scipy.stats.multivariate_normal(mean=np.zeros(d), cov=H)
@@ -169,7 +197,8 @@ def test_lag_symmetries():
 # Eq. (7): the direct truncated convolution
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape,L", [((13,), (4,)), ((9, 14), (3, 5)), ((6, 7, 5), (2, 3, 1)), ((5, 4), (4, 3))])
+@pytest.mark.parametrize("shape,L", [((13,), (4,)), ((9, 14), (3, 5)), ((6, 7, 5), (2, 3, 1)), ((5, 4), (4, 3)),
+                                     ((5, 4, 6, 3), (2, 1, 2, 1))])
 def test_conv_direct_vs_scipy_convolve(shape, L):
     """Eq. (7) with an arbitrary (asymmetric) weight box equals the 'full'
     linear convolution sliced at offset L (library routine)."""
@@ -268,10 +297,11 @@ def test_translation_by_whole_cells():
 # Section 4: the FFT algorithms
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_corrected_fft_equals_direct(d):
     """The corrected algorithm (Eq. 12-14) gives Eq. (7) for any H (Section 5)."""
-    w = W.small_mixture(seed=d, d=d, n=3000, M=(24, 19, 15)[:d])
+    M = (24, 19, 15)[:d] if d < 4 else (11, 9, 8, 10)
+    w = W.small_mixture(seed=d, d=d, n=3000, M=M)
     f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
     g = O.conv_fft_corrected(info["c"], info["k"], info["L"])
     assert np.max(np.abs(f - g)) <= 1e-13 * np.max(f)
@@ -352,6 +382,31 @@ def test_binned_converges_to_eq1():
     assert errs[0] <= 0.04
     assert 3.0 <= errs[0] / errs[1] <= 5.0
     assert 3.0 <= errs[1] / errs[2] <= 5.0
+
+
+def test_diagonal_H_4d_is_separable():
+    """d = 4 with diagonal H: K_H is the product of four 1-D normal densities, so Eq. (7) is four
+    1-D convolutions in turn, each the textbook np.convolve with a scipy normal density."""
+    w = W.small_mixture(seed=62, d=4, n=4000, M=(12, 9, 10, 8), diagonal_H=True)
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+    L, delta = info["L"], info["delta"]
+    g = info["c"] / w.n
+    for a in range(4):
+        lags = np.arange(-L[a], L[a] + 1) * delta[a]
+        ker = scipy.stats.norm(scale=math.sqrt(w.H[a, a])).pdf(lags)
+        g = np.apply_along_axis(lambda v: np.convolve(v, ker, mode="full")[L[a]:L[a] + v.size], a, g)
+    assert np.max(np.abs(f - g)) <= 1e-13 * np.max(f)
+
+
+def test_total_mass_4d():
+    """sum_j f_j prod delta_k ~ 1 in d = 4, short by at most the normal tail outside the
+    tau = 3.7 ellipsoid (chi^2 with 4 degrees of freedom)."""
+    w = W.small_mixture(seed=63, d=4, n=3000, M=(24, 24, 24, 24))
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method="fft")
+    mass = f.sum() * np.prod(info["delta"])
+    r2 = 3.7 ** 2
+    tail = math.exp(-r2 / 2) * (1 + r2 / 2)          # P(chi^2_4 > r^2)
+    assert 1 - tail - 1e-3 <= mass <= 1 + 1e-3
 
 
 # --------------------------------------------------------------------------
