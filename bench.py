@@ -164,19 +164,18 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
     # the product pass also reads its lag columns and transforms them in place
     lagcols = {2: {"conv_col": nb[0] * H * cs - P[0] * H * rs},
                3: {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs}}.get(d, {})
-    # the sort reads X, writes the records (and its table) and zeroes the counts; the plan
-    # scans the table; the gather reads the records and writes the counts
     binning = {
         "zero_counts": (0, cells * 8), "zero_dropped": (0, 8), "bin": (x_read + counts_write, 0),
-        "bin_sort": (x_read, records + counts_write), "bin_plan": (0, 0), "bin_gather": (counts_write, records),
+        "bin_hist": (x_read, 0), "bin_scan": (0, 0), "bin_scatter": (0, x_read + records),
+        "bin_accum": (counts_write, records),
     }
     if name in binning:
         a, extra = binning[name]
         return {"alg": a, "design": a + extra}
-    if name == "plan_kcol":
+    if name == "hist_kspec":
+        return {"alg": x_read + spec["kspec_r2c"], "design": x_read + spec["kspec_r2c"]}
+    if name == "scan_kcol":
         return {"alg": spec["kspec_col2"], "design": spec["kspec_col2"]}
-    if name == "sort_kspec":
-        return {"alg": x_read + spec["kspec_r2c"], "design": x_read + records + counts_write + spec["kspec_r2c"]}
     if name == "kfill":
         return {"alg": int(np.prod(nb)) * rs, "design": int(np.prod(nb)) * rs}
     if name in spec:
@@ -302,8 +301,8 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     bin_alg = w.n * w.d * 8 + cells * 8
     steps_roof = {"binning": step_roofline(kern, bin_names, bin_alg),
                   "fft_convolution": step_roofline(kern, conv_names, conv_alg)}
-    if steps_roof["binning"] and "sort_kspec" in kern:
-        steps_roof["binning"]["note"] = "sort_kspec also runs the kernel spectrum's row pass beside the sort"
+    if steps_roof["binning"] and "hist_kspec" in kern:
+        steps_roof["binning"]["note"] = "hist_kspec also runs the kernel spectrum's row pass beside the histogram"
     return {
         "workload": name, "prec": prec, "n": w.n, "M": list(w.M), "L": list(plan["L"]), "P": list(plan["P"]),
         "ms_per_step": ms_step, "ms_per_step_traced": (u1 - u0) * 1e3 / steps, "gpu_ms_per_step_traced": gpu_step_ms,

@@ -54,7 +54,7 @@ struct Layout {
 
 struct BinLayout {
     // offsets into the binning workspace (tiled path)
-    size_t tab = 0, pre = 0, drops = 0, items = 0, nitems = 0, records = 0, total = 0;
+    size_t hist = 0, tot = 0, drops = 0, records = 0, seg = 0, total = 0;
 };
 
 struct Plan {
@@ -69,11 +69,11 @@ struct Plan {
     BinLayout blay;
 };
 
-// Tile geometry of the binning passes: 32 x 32 cells in 2-D, 8 x 16 x 32 in
-// 3-D, 8^4 in 4-D, 1024 in 1-D, or the caller's tile (clamped to the grid), widened until
-// the tile count fits the sort's LDS counters. Returns false when the tiled
-// path cannot be used: too many cells per tile, records wider than 64 bits,
-// n 2^d >= 2^32, or more chunks than the gather's LDS tables hold.
+// Tile geometry of the binning pass: 32 x 32 cells in 2-D, 8 x 16 x 32 in
+// 3-D, 8^4 in 4-D, 1024 in 1-D, or the caller's tile (clamped to the grid),
+// widened until the tile count fits the per-workgroup histogram. Returns false
+// when the tiled path cannot be used: too many cells per tile, records wider
+// than 64 bits, or n 2^d >= 2^32.
 bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde::TileGeom* tg, BinLayout* bl) {
     kde::TileGeom g{};
     static const int base[kde::kMaxD][kde::kMaxD] = {{1024}, {32, 32}, {8, 16, 32}, {8, 8, 8, 8}};
@@ -96,12 +96,11 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
         }
         g.T[worst] *= 2;
     }
-    int64_t cells = 1, grid_cells = 1;
+    int64_t cells = 1;
     int bits = 0;
     g.qbits = Q + 1;
     for (int k = 0; k < d; ++k) {
         cells *= g.T[k];
-        grid_cells *= M[k];
         int lg = 0;
         while ((1 << lg) < g.T[k]) ++lg;
         g.logT[k] = lg;
@@ -110,26 +109,22 @@ bool plan_tiles(int d, const int64_t* M, int Q, int64_t n, const int* tile, kde:
     }
     if (cells > kde::kMaxTileCells || bits > 64) return false;
     g.tile_cells = static_cast<int>(cells);
-    g.cells = grid_cells;
-    const int64_t max_records = n << d;
-    if (n <= 0 || max_records >= (int64_t(1) << 32)) return false;
+    g.max_records = n << d;
+    if (n <= 0 || g.max_records >= (int64_t(1) << 32)) return false;
+    g.S = kde::kSegment;
     g.nchunk = (n + kde::kBinChunk - 1) / kde::kBinChunk;
-    if (g.nchunk > kde::kMaxChunks) return false;
-    g.chunk_cap = int64_t(kde::kBinChunk) << d;
-    // the plan cuts a tile of R records into ceil(R / kSplitRecords) segments: at most this many in all
-    g.max_items = g.ntiles + (max_records + kde::kSplitRecords - 1) / kde::kSplitRecords;
+    g.max_segments = g.ntiles + (g.max_records + g.S - 1) / g.S;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
         off = align_up(off + bytes);
         return at;
     };
-    bl->tab = take(static_cast<size_t>(g.nchunk) * g.ntiles * 4);
-    bl->pre = take(static_cast<size_t>(g.nchunk + 1) * g.ntiles * 4);
+    bl->hist = take(static_cast<size_t>(g.nchunk) * g.ntiles * 4);
+    bl->tot = take(static_cast<size_t>(g.ntiles) * 4);
     bl->drops = take(static_cast<size_t>(g.nchunk) * 4);
-    bl->items = take(static_cast<size_t>(g.max_items) * 16);
-    bl->nitems = take(4);
-    bl->records = take(static_cast<size_t>(g.nchunk * g.chunk_cap) * 8);
+    bl->records = take(static_cast<size_t>(g.max_records) * 8);
+    bl->seg = take(static_cast<size_t>(g.max_segments) * 16);
     bl->total = off;
     *tg = g;
     return true;
@@ -428,7 +423,7 @@ struct Tracer {
 // produced; the batched path collects them and launches all passes with the
 // same kernel together.
 enum PassKind : int { kPassZero, kPassBinAtomic, kPassBin, kPassRowR2C, kPassRowC2R, kPassCols, kPassDotPartial,
-                      kPassDotFinal, kPassSortKspec, kPassPlanKcol };
+                      kPassDotFinal, kPassHistKspec, kPassScanKcol };
 
 struct Pass {
     PassKind kind;
@@ -470,9 +465,9 @@ int exec_pass(const Pass& p, hipStream_t s) {
         case kPassCols:
             e = kde::launch_cols(p.prec, p.P, p.sub, p.narrow, *reinterpret_cast<const kde::ColArgs*>(p.args), s);
             break;
-        case kPassSortKspec: e = kde::launch_sort_kspec(p.prec, p.P, p.d, p.args, s); break;
-        case kPassPlanKcol:
-            e = kde::launch_plan_kcol(p.prec, p.P, *reinterpret_cast<const kde::PlanColArgs*>(p.args), s);
+        case kPassHistKspec: e = kde::launch_hist_kspec(p.prec, p.P, p.d, p.args, s); break;
+        case kPassScanKcol:
+            e = kde::launch_scan_kcol(p.prec, p.P, *reinterpret_cast<const kde::ScanColArgs*>(p.args), s);
             break;
         case kPassDotPartial:
         case kPassDotFinal:
@@ -516,12 +511,11 @@ kde::BinArgs bin_args(const Plan& pl, const kde::BinConsts& c, const double* X, 
     a.n = n;
     a.c = c;
     a.g = pl.tg;
-    a.w.tab = reinterpret_cast<uint32_t*>(ws + b.tab);
-    a.w.pre = reinterpret_cast<uint32_t*>(ws + b.pre);
+    a.w.hist = reinterpret_cast<uint32_t*>(ws + b.hist);
+    a.w.tot = reinterpret_cast<uint32_t*>(ws + b.tot);
     a.w.drops = reinterpret_cast<uint32_t*>(ws + b.drops);
-    a.w.items = reinterpret_cast<uint4*>(ws + b.items);
-    a.w.nitems = reinterpret_cast<uint32_t*>(ws + b.nitems);
     a.w.records = reinterpret_cast<uint64_t*>(ws + b.records);
+    a.w.seg = reinterpret_cast<uint4*>(ws + b.seg);
     a.counts = counts;
     a.n_dropped = reinterpret_cast<unsigned long long*>(n_dropped);
     return a;
@@ -546,35 +540,35 @@ kde::BinConsts bin_consts(const Plan& pl, const kde_grid* g) {
     return c;
 }
 
-// Binning (Section 2, first step): the three tiled stages, or zero fill and
+// Binning (Section 2, first step): the four tiled stages, or zero fill and
 // global atomics where the tiled path does not apply. With `spec` (the
-// kernel-spectrum row pass, padded length up to kSortSpecMaxP) the sort stage
-// and that pass share one launch; with `spec_col` (the 3-D spectrum's strided
-// pass, same limit) the plan stage and that pass do.
+// kernel-spectrum row pass) the histogram stage and that pass share one
+// launch; with `spec_col` (the 3-D spectrum's strided pass) the scan stage
+// and that pass do.
 int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint64_t* counts, uint64_t* n_dropped,
             char* ws, Emit& emit, const Pass* spec = nullptr, const Pass* spec_col = nullptr) {
     const kde::BinConsts c = bin_consts(pl, g);
     int64_t cells = 1;
     for (int k = 0; k < pl.pub.d; ++k) cells *= g->M[k];
     if (pl.tiled && n > 0) {
-        static const char* names[3] = {"bin_sort", "bin_plan", "bin_gather"};
+        static const char* names[4] = {"bin_hist", "bin_scan", "bin_scatter", "bin_accum"};
         const kde::BinArgs a = bin_args(pl, c, X, n, counts, n_dropped, ws);
-        for (int st = kde::kBinSort; st <= kde::kBinGather; ++st) {
-            if (st == kde::kBinSort && spec) {
+        for (int st = kde::kBinHist; st <= kde::kBinAccum; ++st) {
+            if (st == kde::kBinHist && spec) {
                 Pass f;
-                f.kind = kPassSortKspec;
+                f.kind = kPassHistKspec;
                 f.prec = spec->prec;
                 f.P = spec->P;
                 f.d = pl.pub.d;
                 f.order = st;
-                f.name = "sort_kspec";
+                f.name = "hist_kspec";
                 if (spec->prec == KDE_F64) {
-                    kde::SortSpecArgs<double> sa{};
+                    kde::HistSpecArgs<double> sa{};
                     sa.bin = a;
                     std::memcpy(&sa.row, spec->args, sizeof(sa.row));
                     f.set_args(sa);
                 } else {
-                    kde::SortSpecArgs<float> sa{};
+                    kde::HistSpecArgs<float> sa{};
                     sa.bin = a;
                     std::memcpy(&sa.row, spec->args, sizeof(sa.row));
                     f.set_args(sa);
@@ -582,15 +576,15 @@ int run_bin(const Plan& pl, const double* X, int64_t n, const kde_grid* g, uint6
                 KDE_CHECK(emit(f));
                 continue;
             }
-            if (st == kde::kBinPlan && spec_col) {
+            if (st == kde::kBinScan && spec_col) {
                 Pass f;
-                f.kind = kPassPlanKcol;
+                f.kind = kPassScanKcol;
                 f.prec = spec_col->prec;
                 f.P = spec_col->P;
                 f.d = pl.pub.d;
                 f.order = st;
-                f.name = "plan_kcol";
-                kde::PlanColArgs sa{};
+                f.name = "scan_kcol";
+                kde::ScanColArgs sa{};
                 sa.bin = a;
                 std::memcpy(&sa.col, spec_col->args, sizeof(sa.col));
                 f.set_args(sa);
@@ -1433,11 +1427,10 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
     char* bin_ws = ws + align_up(pl.counts_bytes);
     char* conv_ws = bin_ws + align_up(pl.pub.bin_ws_bytes);
     const bool reuse = params && params->reuse_spectrum;
-    // with tiled binning the spectrum's row pass rides in the sort's launch and its
-    // strided pass (3-D) in the plan's
+    // with tiled binning the spectrum rides in the binning launches: its row pass
+    // in the histogram's, its strided pass (3-D) in the scan's
     std::vector<Pass> spec;
-    if (pl.tiled && !reuse && pl.pub.d <= 3 && pl.pub.P[pl.pub.d - 1] <= kde::kSortSpecMaxP &&
-        (pl.pub.d < 3 || pl.pub.P[1] <= kde::kSortSpecMaxP)) {
+    if (pl.tiled && !reuse && pl.pub.d <= 3) {
         Collect c(spec);
         KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
         const size_t want = pl.pub.d == 3 ? 2 : 1;

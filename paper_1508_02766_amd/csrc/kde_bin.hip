@@ -11,24 +11,24 @@
 //
 // Two implementations with identical results:
 //
-// * tiled (default): every (sample, tile) pair the sample's 2^d corners touch
-//   becomes one packed record; three launches:
-//     sort    one workgroup per chunk of 2048 samples reads them once, groups
-//             the chunk's records by tile in the chunk's own region (LDS
-//             counts, scan, slots) and writes one table entry per (tile,
-//             chunk): the group's offset and length; it also zeroes its share
-//             of the counts
-//     plan    one workgroup per tile numbers the tile's records across the
-//             chunks (exclusive scan of its group lengths) and cuts them into
-//             segments of at most 4096, appended to a work list
-//     gather  one workgroup per segment sums it in LDS; the only segment of a
-//             tile is stored with plain writes, the segments of a heavier tile
-//             add their sums to the zeroed counts with 64-bit integer atomics
-//             (one per nonzero cell and segment; exact in any order)
+// * tiled (default): a counting sort of packed (sample, tile) records into
+//   per-tile buckets, then one workgroup per segment of a bucket sums its
+//   records in LDS. Four launches:
+//     hist     per-chunk histogram of records per tile (LDS atomics)
+//     scan     per-tile exclusive scan over chunks (one workgroup per tile);
+//              zeroes the counts of tiles with more than one segment
+//     scatter  block scan of the tile totals, packed records into buckets
+//     accum    LDS sum of one segment (<= S records) of one tile; a tile with
+//              one segment is stored with plain writes, the segments of
+//              other tiles are added to the counts with 64-bit integer
+//              atomics (one per nonzero cell and segment; exact in any order)
+//   The scatter's workgroup 0 also writes the accumulation's work list (one
+//   descriptor per segment: tile, record range, shared flag), which each
+//   accumulation workgroup reads with one load.
 //   A sample whose corners straddle a tile edge gets one record per tile it
 //   touches, so every cell belongs to exactly one tile.
 // * atomic (fallback when a record does not fit in 64 bits or the grid needs
-//   more tiles than one workgroup can count): zero fill, then 2^d global
+//   more tiles than one workgroup can histogram): zero fill, then 2^d global
 //   64-bit atomic adds per sample.
 
 #include "kde_bin_dev.h"
@@ -36,38 +36,55 @@
 namespace kde {
 namespace {
 
-// Single-instance and batched entry points of the three stages (see BatchMap
-// for how a batched launch assigns workgroups to instances). The sort takes
-// its chunks in XCD-major order: consecutive chunks write neighbouring words
-// of the tile-major table, which then share one L2.
+// Single-instance and batched entry points of the four stages (see BatchMap
+// for how a batched launch assigns workgroups to instances).
+
+#define KDE_BATCH_PROLOGUE                                              \
+    const auto* tab = static_cast<const BinArgs*>(m.tab);               \
+    const int inst = static_cast<int>(m.owner[blockIdx.x]);             \
+    const BinArgs& a = tab[inst];                                       \
+    const uint32_t blk = blockIdx.x - m.start[inst];
+
+// The batched histogram takes the chunks in XCD-major order: consecutive
+// chunks write neighbouring words of the tile-major histogram, so they share
+// one L2 (the batched scatter measured faster in launch order).
+#define KDE_BATCH_PROLOGUE_XCD                                          \
+    const auto* tab = static_cast<const BinArgs*>(m.tab);               \
+    const uint32_t bid = xcd_major(blockIdx.x, gridDim.x);              \
+    const int inst = static_cast<int>(m.owner[bid]);                    \
+    const BinArgs& a = tab[inst];                                       \
+    const uint32_t blk = bid - m.start[inst];
 
 template <int D>
-__global__ __launch_bounds__(kSortThreads) void bin_sort_kernel(BinArgs a) {
-    bin_sort_body<D>(a, xcd_major(blockIdx.x, gridDim.x));
+__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(BinArgs a) { bin_hist_body<D>(a, xcd_major(blockIdx.x, gridDim.x)); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_hist_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE_XCD
+    bin_hist_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kSortThreads) void bin_sort_batch(BatchMap m) {
-    const auto* tab = static_cast<const BinArgs*>(m.tab);
-    const uint32_t bid = xcd_major(blockIdx.x, gridDim.x);
-    const int inst = static_cast<int>(m.owner[bid]);
-    bin_sort_body<D>(tab[inst], bid - m.start[inst]);
-}
-__global__ __launch_bounds__(kPlanThreads) void bin_plan_kernel(BinArgs a) { bin_plan_body(a, blockIdx.x); }
-__global__ __launch_bounds__(kPlanThreads) void bin_plan_batch(BatchMap m) {
-    const auto* tab = static_cast<const BinArgs*>(m.tab);
-    const int inst = static_cast<int>(m.owner[blockIdx.x]);
-    bin_plan_body(tab[inst], blockIdx.x - m.start[inst]);
+__global__ __launch_bounds__(kBinThreads) void bin_scan_kernel(BinArgs a) { bin_scan_body<D>(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void bin_scan_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_scan_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kGatherThreads) void bin_gather_kernel(BinArgs a) {
-    bin_gather_body<D>(a, blockIdx.x);
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_kernel(BinArgs a) { bin_scatter_body<D>(a, xcd_major(blockIdx.x, gridDim.x)); }
+template <int D>
+__global__ __launch_bounds__(kScatterThreads) void bin_scatter_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_scatter_body<D>(a, blk);
 }
 template <int D>
-__global__ __launch_bounds__(kGatherThreads) void bin_gather_batch(BatchMap m) {
-    const auto* tab = static_cast<const BinArgs*>(m.tab);
-    const int inst = static_cast<int>(m.owner[blockIdx.x]);
-    bin_gather_body<D>(tab[inst], blockIdx.x - m.start[inst]);
+__global__ __launch_bounds__(kAccumThreads) void bin_accum_kernel(BinArgs a) { bin_accum_body<D>(a, blockIdx.x); }
+template <int D>
+__global__ __launch_bounds__(kAccumBatchThreads) void bin_accum_batch(BatchMap m) {
+    KDE_BATCH_PROLOGUE
+    bin_accum_body<D, kAccumBatchThreads>(a, blk);
 }
+#undef KDE_BATCH_PROLOGUE
+#undef KDE_BATCH_PROLOGUE_XCD
 
 // ---------------------------------------------------------------------------
 // atomic path
@@ -140,44 +157,52 @@ hipError_t launch_bin(const BinConsts& c, const double* X, int64_t n, uint64_t* 
 namespace {
 
 int64_t bin_stage_extent(int stage, const TileGeom& g) {
-    return stage == kBinSort ? g.nchunk : (stage == kBinPlan ? g.ntiles : g.max_items);
+    switch (stage) {
+        case kBinHist:
+        case kBinScatter: return g.nchunk;
+        case kBinScan: return g.ntiles;
+        default: return g.max_segments;
+    }
 }
 
 template <int D>
 hipError_t bin_stage_d(int stage, const BinArgs& a, hipStream_t s) {
+    const dim3 blk(stage == kBinAccum ? kAccumThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
     const dim3 grid(static_cast<unsigned>(bin_stage_extent(stage, a.g)));
     const size_t lds = bin_stage_lds(stage, a.g);
-    if (stage == kBinSort)
-        KDE_LAUNCH((bin_sort_kernel<D>), grid, dim3(kSortThreads), lds, s, a);
-    else if (stage == kBinPlan)
-        KDE_LAUNCH(bin_plan_kernel, grid, dim3(kPlanThreads), 0, s, a);
-    else if (stage == kBinGather)
-        KDE_LAUNCH((bin_gather_kernel<D>), grid, dim3(kGatherThreads), lds, s, a);
-    else
-        return hipErrorInvalidValue;
+    switch (stage) {
+        case kBinHist: KDE_LAUNCH((bin_hist_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinScan: KDE_LAUNCH((bin_scan_kernel<D>), grid, blk, 0, s, a); break;
+        case kBinScatter: KDE_LAUNCH((bin_scatter_kernel<D>), grid, blk, lds, s, a); break;
+        case kBinAccum: KDE_LAUNCH((bin_accum_kernel<D>), grid, blk, lds, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t bin_stage_batch_d(int stage, const BatchMap& m, size_t lds, hipStream_t s) {
+    const dim3 blk(stage == kBinAccum ? kAccumBatchThreads : (stage == kBinScatter ? kScatterThreads : kBinThreads));
     const dim3 grid(m.blocks);
-    if (stage == kBinSort)
-        KDE_LAUNCH((bin_sort_batch<D>), grid, dim3(kSortThreads), lds, s, m);
-    else if (stage == kBinPlan)
-        KDE_LAUNCH(bin_plan_batch, grid, dim3(kPlanThreads), 0, s, m);
-    else if (stage == kBinGather)
-        KDE_LAUNCH((bin_gather_batch<D>), grid, dim3(kGatherThreads), lds, s, m);
-    else
-        return hipErrorInvalidValue;
+    switch (stage) {
+        case kBinHist: KDE_LAUNCH((bin_hist_batch<D>), grid, blk, lds, s, m); break;
+        case kBinScan: KDE_LAUNCH((bin_scan_batch<D>), grid, blk, 0, s, m); break;
+        case kBinScatter: KDE_LAUNCH((bin_scatter_batch<D>), grid, blk, lds, s, m); break;
+        case kBinAccum: KDE_LAUNCH((bin_accum_batch<D>), grid, blk, lds, s, m); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
 size_t bin_stage_lds(int stage, const TileGeom& g) {
-    if (stage == kBinSort) return static_cast<size_t>(g.ntiles) * 8;
-    if (stage == kBinPlan) return 0;
-    return static_cast<size_t>(g.tile_cells) * 8 + (2 * static_cast<size_t>(g.nchunk) + 1) * 4 + kSplitRecords * 4;
+    switch (stage) {
+        case kBinHist: return static_cast<size_t>(g.ntiles) * 4;
+        case kBinScatter: return static_cast<size_t>(g.ntiles) * 8;
+        case kBinAccum: return static_cast<size_t>(g.tile_cells) * 8;
+        default: return 0;
+    }
 }
 
 // A batched launch gives every instance its single-instance extent.

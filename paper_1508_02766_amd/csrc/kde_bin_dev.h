@@ -1,6 +1,6 @@
-// Device code of the binning step (the two passes of the tiled binning and
-// their helpers), shared by the binning launches (kde_bin.hip) and the fused
-// sort + spectrum launch (kde_fused.hip). Sources including it are
+// Device code of the binning step (the four passes of the tiled counting
+// sort and their helpers), shared by the binning launches (kde_bin.hip) and
+// the fused scan + spectrum launch (kde_fused.hip). Sources including it are
 // built without floating-point contraction or fast-math, so that the FP64
 // coordinate arithmetic is one subtraction and one correctly rounded division.
 #pragma once
@@ -70,8 +70,7 @@ __device__ __forceinline__ void load_chunk(const double* __restrict__ X, int64_t
     }
 }
 
-// Calls f(tile, record, b) for every tile the corners j..j+1 touch (b: the
-// corner of the lower node's tile offset, 0 <= b < 2^d).
+// Calls f(tile, record) for every tile the corners j..j+1 touch.
 template <int D, typename F>
 __device__ __forceinline__ void for_each_tile(const TileGeom& g, const int (&j)[D], const uint64_t (&q)[D], F&& f) {
     int tlo[D];
@@ -100,7 +99,7 @@ __device__ __forceinline__ void for_each_tile(const TileGeom& g, const int (&j)[
             rec |= static_cast<uint64_t>(jl) << shift;
             shift += g.jbits[k];
         }
-        if (use) f(tile, rec, b);
+        if (use) f(tile, rec);
     }
 }
 
@@ -137,41 +136,46 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t* a, int n, uin
     return total;
 }
 
-// Inclusive prefix maximum of a[0..n) in LDS by a block of NT threads (each a
-// contiguous run, then a wave scan and the maxima of the earlier waves).
-template <int NT>
-__device__ __forceinline__ void block_inclusive_max_scan(uint32_t* a, int n, uint32_t* wave_max) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per = (n + NT - 1) / NT;
-    const int b0 = tid * per < n ? tid * per : n;
-    const int b1 = b0 + per < n ? b0 + per : n;
-    uint32_t s = 0;
-    for (int i = b0; i < b1; ++i) s = a[i] > s ? a[i] : s;
-    uint32_t x = s;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x = y > x ? y : x;
-    }
-    if (lane == 63) wave_max[wave] = x;
-    __syncthreads();
-    uint32_t before = 0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w)
-        if (w < wave) before = wave_max[w] > before ? wave_max[w] : before;
-    const uint32_t up = __shfl_up(x, 1, 64);             // every lane takes part in the shuffle
-    uint32_t run = lane > 0 ? up : 0;                    // maximum of the earlier lanes of this wave
-    run = before > run ? before : run;
-    for (int i = b0; i < b1; ++i) {
-        run = a[i] > run ? a[i] : run;
-        a[i] = run;
-    }
-    __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // tiled path
 // ---------------------------------------------------------------------------
+
+template <int D>
+__device__ __forceinline__ void bin_hist_body(const BinArgs& a, uint32_t blk) {
+    const double* __restrict__ X = a.X;
+    const int64_t n = a.n;
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    uint32_t* __restrict__ hist = a.w.hist;
+    uint32_t* __restrict__ drops = a.w.drops;
+    extern __shared__ uint32_t h[];     // [ntiles]
+    __shared__ uint32_t nd;
+    const int tid = threadIdx.x;
+    constexpr int kPer = per_thread<kBinThreads>();
+    double x[kPer][D];
+    bool valid[kPer];
+    load_chunk<D, kBinThreads>(X, n, blk, x, valid);   // in flight while the histogram is cleared
+    for (int t = tid; t < g.ntiles; t += kBinThreads) h[t] = 0;
+    if (tid == 0) nd = 0;
+    __syncthreads();
+    uint32_t dropped = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        if (!valid[k]) continue;
+        int j[D];
+        uint64_t q[D];
+        if (!classify_x<D>(x[k], c, j, q)) {
+            ++dropped;
+            continue;
+        }
+        for_each_tile<D>(g, j, q, [&](uint32_t tile, uint64_t) { atomicAdd(&h[tile], 1u); });
+    }
+    if (dropped) atomicAdd(&nd, dropped);
+    __syncthreads();
+    // tile-major: the scan reads each tile's chunk counts contiguously
+    for (int t = tid; t < g.ntiles; t += kBinThreads) hist[static_cast<int64_t>(t) * g.nchunk + blk] = h[t];
+    if (tid == 0) drops[blk] = nd;
+}
 
 template <int D>
 __device__ __forceinline__ void tile_frame(const BinConsts& c, const TileGeom& g, uint32_t tile, int64_t (&org)[D],
@@ -204,210 +208,211 @@ __device__ __forceinline__ int64_t tile_cell_index(const BinConsts& c, const Til
     return inside ? idx : -1;
 }
 
-// Pass 1, one workgroup per chunk `blk` of kBinChunk samples: the samples are
-// loaded once (into registers) and classified once, their records counted per
-// tile (LDS atomics),
-// the counts scanned into the offsets of the tile groups in the chunk's region,
-// the table column of the chunk written, and the records written to their
-// groups (a second LDS atomic per record gives its slot). The workgroup also
-// zeroes its share of the counts, which the gather of heavy tiles adds into,
-// and workgroup 0 the work-list counter of the plan.
-template <int D, int NT = kSortThreads>
-__device__ __forceinline__ void bin_sort_body(const BinArgs& a, uint32_t blk) {
+// One workgroup per tile: exclusive scan of hist[tile][.] over the chunks
+// (each thread a contiguous run of chunks, then a workgroup scan of the run
+// sums), tot[tile] = the tile's record count; the counts of a tile with more
+// than one segment are zeroed for the accumulation. Workgroup 0 also totals
+// the dropped samples.
+template <int D>
+__device__ __forceinline__ void bin_scan_body(const BinArgs& a, uint32_t blk) {
+    const BinConsts& c = a.c;
+    const TileGeom& g = a.g;
+    const uint32_t* __restrict__ drops = a.w.drops;
+    unsigned long long* __restrict__ n_dropped = a.n_dropped;
+    __shared__ uint32_t wave_sums[kBinThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tile = static_cast<int>(blk);
+    const int64_t nch = g.nchunk;
+    const int64_t per = (nch + kBinThreads - 1) / kBinThreads;
+    const int64_t c0 = tid * per < nch ? tid * per : nch;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    uint32_t* __restrict__ row = a.w.hist + static_cast<int64_t>(tile) * nch;
+    uint32_t s = 0;
+    for (int64_t ch = c0; ch < c1; ++ch) s += row[ch];
+    uint32_t x = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_sums[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kBinThreads / 64; ++w) {
+        if (w < wave) before += wave_sums[w];
+        total += wave_sums[w];
+    }
+    uint32_t run = before + x - s;
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const uint32_t v = row[ch];
+        row[ch] = run;
+        run += v;
+    }
+    if (tid == 0) a.w.tot[tile] = total;
+    // a tile with several segments is summed into the counts with atomics: zero it here
+    if (total > static_cast<uint32_t>(g.S)) {
+        int64_t org[D];
+        int ext[D];
+        tile_frame<D>(c, g, static_cast<uint32_t>(tile), org, ext);
+        for (int i = tid; i < g.tile_cells; i += kBinThreads) {
+            const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
+            if (idx >= 0) a.counts[idx] = 0;
+        }
+    }
+    if (blk == 0 && n_dropped) {
+        __shared__ unsigned long long acc;
+        if (tid == 0) acc = 0;
+        __syncthreads();
+        unsigned long long d = 0;
+        for (int64_t ch = tid; ch < nch; ch += kBinThreads) d += drops[ch];
+        if (d) atomicAdd(&acc, d);
+        __syncthreads();
+        if (tid == 0) n_dropped[0] = acc;
+    }
+}
+
+template <int D, int NT = kScatterThreads>
+__device__ __forceinline__ void bin_scatter_body(const BinArgs& a, uint32_t blk) {
     const double* __restrict__ X = a.X;
     const int64_t n = a.n;
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
-    extern __shared__ uint32_t sort_lds[];   // [ntiles] records per tile, [ntiles] cursors
-    uint32_t* h = sort_lds;
-    uint32_t* cur = sort_lds + g.ntiles;
+    extern __shared__ uint32_t cur[];   // [ntiles] cursors, [ntiles] this chunk's offsets
     __shared__ uint32_t wave_sums[NT / 64];
-    __shared__ uint32_t nd;
+    uint32_t* aux = cur + g.ntiles;
     const int tid = threadIdx.x;
+    const bool lead = blk == 0;
+    // The tile totals and this chunk's offsets are loaded before the samples: vector
+    // memory loads return in order, so the prologue below waits for them alone while
+    // the samples are still in flight (up to kPre * NT tiles in registers).
+    constexpr int kPre = 4;
+    uint32_t pt[kPre], ph[kPre];
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+        const int t = tid + m * NT;
+        pt[m] = t < g.ntiles ? w.tot[t] : 0u;
+        ph[m] = t < g.ntiles && !lead ? w.hist[static_cast<int64_t>(t) * g.nchunk + blk] : 0u;
+    }
     constexpr int kPer = per_thread<NT>();
     double x[kPer][D];
     bool valid[kPer];
-    load_chunk<D, NT>(X, n, blk, x, valid);   // in flight while the counts share is cleared
-    {
-        const int64_t share = (g.cells + g.nchunk - 1) / g.nchunk;
-        const int64_t z0 = static_cast<int64_t>(blk) * share;
-        const int64_t z1 = z0 + share < g.cells ? z0 + share : g.cells;
-        for (int64_t i = z0 + tid; i < z1; i += NT) a.counts[i] = 0;
+    load_chunk<D, NT>(X, n, blk, x, valid);
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+        const int t = tid + m * NT;
+        if (t < g.ntiles) {
+            cur[t] = pt[m];
+            aux[t] = ph[m];
+        }
     }
-    for (int t = tid; t < g.ntiles; t += NT) h[t] = 0;
-    if (tid == 0) nd = 0;
-    if (tid == 0 && blk == 0) w.nitems[0] = 0;   // the plan appends its segments from zero
+    for (int t = tid + kPre * NT; t < g.ntiles; t += NT) {
+        cur[t] = w.tot[t];
+        if (!lead) aux[t] = w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
+    }
     __syncthreads();
-    // each sample is classified once; its lower corner and fractions stay in registers
-    // for the second round
-    uint32_t dropped = 0;
-    int jj[kPer][D];
-    uint64_t qq[kPer][D];
-    bool in[kPer];
+    block_exclusive_scan<NT>(cur, g.ntiles, wave_sums);   // cur = tile starts
+    if (lead) {
+        // the accumulation's work list: tile t owns max(1, ceil(tot / S)) consecutive segments
+        // of at most S records; aux first holds the segment counts, then their offsets
+        for (int t = tid; t < g.ntiles; t += NT) {
+            const uint32_t cnt = w.tot[t];
+            aux[t] = cnt == 0 ? 1u : (cnt + g.S - 1) / g.S;
+        }
+        __syncthreads();
+        const uint32_t nsegs = block_exclusive_scan<NT>(aux, g.ntiles, wave_sums);
+        const uint32_t S = static_cast<uint32_t>(g.S);
+        for (int t = tid; t < g.ntiles; t += NT) {
+            const uint32_t cnt = w.tot[t];
+            const uint32_t end = cur[t] + cnt;
+            const uint32_t e = t + 1 < g.ntiles ? aux[t + 1] : nsegs;
+            uint32_t r = cur[t];
+            for (uint32_t q = aux[t]; q < e; ++q, r += S)
+                w.seg[q] = make_uint4(static_cast<uint32_t>(t), r, end - r > S ? r + S : end, cnt > S ? 1u : 0u);
+            cur[t] += w.hist[static_cast<int64_t>(t) * g.nchunk + blk];
+        }
+        for (int64_t q = nsegs + tid; q < g.max_segments; q += NT)
+            w.seg[q] = make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
+    } else {
+        for (int t = tid; t < g.ntiles; t += NT) cur[t] += aux[t];
+    }
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        in[k] = valid[k] && classify_x<D>(x[k], c, jj[k], qq[k]);
-        if (valid[k] && !in[k]) ++dropped;
-        if (in[k]) for_each_tile<D>(g, jj[k], qq[k], [&](uint32_t tile, uint64_t, int) { atomicAdd(&h[tile], 1u); });
-    }
-    if (dropped) atomicAdd(&nd, dropped);
-    __syncthreads();
-    for (int t = tid; t < g.ntiles; t += NT) cur[t] = h[t];
-    __syncthreads();
-    block_exclusive_scan<NT>(cur, g.ntiles, wave_sums);   // cur = group offsets (ends with a barrier)
-    // table column of this chunk, tile-major so that the gather reads a tile's row contiguously
-    for (int t = tid; t < g.ntiles; t += NT) w.tab[static_cast<int64_t>(t) * g.nchunk + blk] = (cur[t] << 16) | h[t];
-    if (tid == 0) w.drops[blk] = nd;
-    __syncthreads();
-    uint64_t* __restrict__ region = w.records + static_cast<int64_t>(blk) * g.chunk_cap;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        if (!in[k]) continue;
-        for_each_tile<D>(g, jj[k], qq[k], [&](uint32_t tile, uint64_t rec, int) {
+        if (!valid[k]) continue;
+        int j[D];
+        uint64_t q[D];
+        if (!classify_x<D>(x[k], c, j, q)) continue;
+        for_each_tile<D>(g, j, q, [&](uint32_t tile, uint64_t rec) {
             const uint32_t pos = atomicAdd(&cur[tile], 1u);
-            region[pos] = rec;
+            w.records[pos] = rec;
         });
     }
 }
 
-// Adds the 2^d corner weights of one record to the tile's LDS sums.
-template <int D>
-__device__ __forceinline__ void accumulate_record(unsigned long long* grid, const TileGeom& g, const int (&ext)[D],
-                                                  uint64_t rec, uint64_t one) {
-    const uint64_t qmask = (1ull << g.qbits) - 1;
-    uint64_t q[D];
-    int jl[D];
-    int shift = D * g.qbits;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        q[a] = (rec >> (a * g.qbits)) & qmask;
-        jl[a] = static_cast<int>((rec >> shift) & ((1ull << g.jbits[a]) - 1)) - 1;
-        shift += g.jbits[a];
-    }
-#pragma unroll
-    for (int b = 0; b < (1 << D); ++b) {
-        bool inside = true;
-        int cell = 0;
-        uint64_t wgt = 1;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int bit = (b >> (D - 1 - a)) & 1;
-            const int ca = jl[a] + bit;
-            inside = inside && ca >= 0 && ca < ext[a];
-            cell = (cell << g.logT[a]) + ca;
-            wgt *= bit ? q[a] : one - q[a];
-        }
-        if (inside && wgt) atomicAdd(&grid[cell], static_cast<unsigned long long>(wgt));
-    }
-}
-
-// Pass 2, one workgroup per tile: the exclusive scan of the tile's group
-// lengths over the chunks (the index of the tile's first record in each chunk)
-// goes to the tile's prefix row; the tile's R records are cut into
-// m = ceil(R / kSplitRecords) segments of equal size, appended to the work
-// list with one atomic add. Workgroup 0 also totals the dropped samples.
-template <int NT = kPlanThreads>
-__device__ __forceinline__ void bin_plan_body(const BinArgs& a, uint32_t tile) {
-    const TileGeom& g = a.g;
-    const BinWork& w = a.w;
-    const int nch = static_cast<int>(g.nchunk);
-    __shared__ uint32_t cnt[kMaxChunks];
-    __shared__ uint32_t wave_sums[NT / 64];
-    __shared__ uint32_t base;
-    const int tid = threadIdx.x;
-    if (tile == 0 && a.n_dropped) {
-        __shared__ unsigned long long acc;
-        if (tid == 0) acc = 0;
-        __syncthreads();
-        unsigned long long dsum = 0;
-        for (int ch = tid; ch < nch; ch += NT) dsum += w.drops[ch];
-        if (dsum) atomicAdd(&acc, dsum);
-        __syncthreads();
-        if (tid == 0) a.n_dropped[0] = acc;
-    }
-    const uint32_t* __restrict__ row = w.tab + static_cast<int64_t>(tile) * g.nchunk;
-    for (int ch = tid; ch < nch; ch += NT) cnt[ch] = row[ch] & 0xFFFFu;
-    __syncthreads();
-    const uint32_t total = block_exclusive_scan<NT>(cnt, nch, wave_sums);   // ends with a barrier
-    uint32_t* __restrict__ prow = w.pre + static_cast<int64_t>(tile) * (g.nchunk + 1);
-    for (int ch = tid; ch < nch; ch += NT) prow[ch] = cnt[ch];
-    if (tid == 0) prow[nch] = total;
-    if (total == 0) return;                                                  // the sort zeroed the tile
-    const uint32_t m = (total + kSplitRecords - 1) / kSplitRecords;
-    if (tid == 0) base = atomicAdd(w.nitems, m);
-    __syncthreads();
-    for (uint32_t k = tid; k < m; k += NT) w.items[base + k] = make_uint4(tile, k, m, total);
-}
-
-// Pass 3, one workgroup per work-list item: segment k of the m of its tile,
-// records [k R / m, (k + 1) R / m) of the tile's R (at most kSplitRecords).
-// The chunk of each of them is mapped in LDS from the tile's prefix row, then
-// thread i takes records i, i + NT, ... (a wave's loads run along the tile's
-// groups) and adds their corner weights to the tile's LDS sums. m = 1:
-// the sums are stored; m > 1: added to the counts the sort zeroed. Workgroups
-// beyond the list leave at once.
-template <int D, int NT = kGatherThreads>
-__device__ __forceinline__ void bin_gather_body(const BinArgs& a, uint32_t blk) {
+// One workgroup per segment (<= S records of one tile): sum the records'
+// corner weights in LDS, then store the tile (sole segment) or add the
+// segment's sums to the zeroed counts with 64-bit integer atomics (exact, in
+// any order).
+template <int D, int NT = kAccumThreads>
+__device__ __forceinline__ void bin_accum_body(const BinArgs& a, uint32_t blk) {
     const BinConsts& c = a.c;
     const TileGeom& g = a.g;
     const BinWork& w = a.w;
     uint64_t* __restrict__ counts = a.counts;
-    if (blk >= w.nitems[0]) return;
-    const uint4 item = w.items[blk];
-    const uint32_t tile = item.x, k = item.y, m = item.z, total = item.w;
-    const int nch = static_cast<int>(g.nchunk);
-    extern __shared__ unsigned long long gather_lds[];
-    unsigned long long* grid = gather_lds;                                     // [tile_cells]
-    uint32_t* pre = reinterpret_cast<uint32_t*>(gather_lds + g.tile_cells);   // [nchunk + 1]
-    uint32_t* ent = pre + nch + 1;                                             // [nchunk]
-    uint32_t* wmap = ent + nch;                                                // [kSplitRecords]
-    __shared__ uint32_t wave_max[NT / 64];
+    extern __shared__ unsigned long long grid[];   // [tile_cells]
     const int tid = threadIdx.x;
-    const uint32_t* __restrict__ row = w.tab + static_cast<int64_t>(tile) * g.nchunk;
-    const uint32_t* __restrict__ prow = w.pre + static_cast<int64_t>(tile) * (g.nchunk + 1);
-    for (int ch = tid; ch < nch; ch += NT) {
-        ent[ch] = row[ch];
-        pre[ch] = prow[ch];
+    const uint4 sd = w.seg[blk];                    // work list written by the scatter pass
+    if (sd.x == 0xFFFFFFFFu) return;
+    const uint32_t tile = sd.x, r0 = sd.y, r1 = sd.z;
+    const bool shared_tile = sd.w != 0;
+    // this thread's records, loaded together
+    constexpr int kRec = kSegment / NT;
+    uint64_t recs[kRec];
+#pragma unroll
+    for (int m = 0; m < kRec; ++m) {
+        const uint32_t r = r0 + tid + m * NT;
+        recs[m] = r < r1 ? w.records[r] : 0;
     }
-    if (tid == 0) pre[nch] = total;
-    for (int i = tid; i < g.tile_cells; i += NT) grid[i] = 0;
     int64_t org[D];
     int ext[D];
     tile_frame<D>(c, g, tile, org, ext);
-    const uint32_t r0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * k / m);
-    const uint32_t r1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (k + 1) / m);   // r1 - r0 <= kSplitRecords
+    for (int i = tid; i < g.tile_cells; i += NT) grid[i] = 0;
     __syncthreads();
-    // the chunk of every record of the segment, in LDS: each chunk with records in [r0, r1)
-    // marks the position of its first one (the largest index wins where empty chunks share
-    // it), and a prefix maximum carries the marks forward; then thread i takes records
-    // i, i + NT, ... (a wave's loads run along the tile's groups)
-    for (int i = tid; i < kSplitRecords; i += NT) wmap[i] = 0;
-    __syncthreads();
-    for (int ch = tid; ch < nch; ch += NT) {
-        const uint32_t p0 = pre[ch], p1 = pre[ch + 1];
-        if (p1 > r0 && p0 < r1) atomicMax(&wmap[(p0 > r0 ? p0 : r0) - r0], static_cast<uint32_t>(ch));
-    }
-    __syncthreads();
-    block_inclusive_max_scan<NT>(wmap, static_cast<int>(r1 - r0), wave_max);
     const uint64_t one = 1ull << c.Q;
-    constexpr int kPer = (kSplitRecords + NT - 1) / NT;
-    uint64_t rec[kPer];
+    const uint64_t qmask = (1ull << g.qbits) - 1;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const uint32_t rr = r0 + static_cast<uint32_t>(tid + u * NT);
-        rec[u] = 0;
-        if (rr < r1) {
-            const int ch = static_cast<int>(wmap[rr - r0]);
-            const int64_t at = static_cast<int64_t>(ch) * g.chunk_cap + (ent[ch] >> 16) + (rr - pre[ch]);
-            rec[u] = w.records[at];
+    for (int m = 0; m < kRec; ++m) {
+        if (r0 + tid + m * NT >= r1) break;
+        const uint64_t rec = recs[m];
+        uint64_t q[D];
+        int jl[D];
+        int shift = D * g.qbits;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            q[a] = (rec >> (a * g.qbits)) & qmask;
+            jl[a] = static_cast<int>((rec >> shift) & ((1ull << g.jbits[a]) - 1)) - 1;
+            shift += g.jbits[a];
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << D); ++b) {
+            bool inside = true;
+            int cell = 0;
+            uint64_t wgt = 1;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const int bit = (b >> (D - 1 - a)) & 1;
+                const int ca = jl[a] + bit;
+                inside = inside && ca >= 0 && ca < ext[a];
+                cell = (cell << g.logT[a]) + ca;
+                wgt *= bit ? q[a] : one - q[a];
+            }
+            if (inside && wgt) atomicAdd(&grid[cell], static_cast<unsigned long long>(wgt));
         }
     }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u)
-        if (r0 + static_cast<uint32_t>(tid + u * NT) < r1) accumulate_record<D>(grid, g, ext, rec[u], one);
     __syncthreads();
-    if (m == 1) {
+    if (!shared_tile) {
         for (int i = tid; i < g.tile_cells; i += NT) {
             const int64_t idx = tile_cell_index<D>(c, g, org, ext, i);
             if (idx >= 0) counts[idx] = grid[i];

@@ -63,28 +63,18 @@ struct BinConsts {
 
 // Tiled binning: the grid is cut into tiles of T_1 x ... x T_d cells; every
 // (sample, tile) pair the sample's 2^d corners touch becomes one packed 64-bit
-// record (tile-local lower corner + 1 and the d fixed-point fractions q). Three
-// passes:
-//   sort    one workgroup per chunk of kBinChunk samples reads them once,
-//           writes the chunk's records grouped by tile into the chunk's own
-//           region, and a table entry per (tile, chunk): the group's offset in
-//           the region (high 16 bits) and its length (low 16 bits); it also
-//           zeroes its share of the counts (and workgroup 0 the item counter);
-//   plan    one workgroup per tile: the exclusive scan of the tile's group
-//           lengths over the chunks (numbering its records), and its records
-//           cut into m = ceil(R / kSplitRecords) equal segments, appended to a
-//           work list (one atomic add per tile);
-//   gather  one workgroup per work-list item sums its segment in LDS: stored
-//           when the tile has one segment, else added to the zeroed counts
-//           with 64-bit integer atomics (exact in any order).
-constexpr int kBinChunk = 2048;              // samples per sort workgroup
-constexpr int kSortThreads = 512;            // threads of a sort workgroup (divides kBinChunk)
-constexpr int kPlanThreads = 256;            // threads of a plan workgroup
-constexpr int kGatherThreads = 1024;         // threads of a gather workgroup
-constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays of the sort: at most 64 KiB
+// record (tile-local lower corner + 1 and the d fixed-point fractions q), the
+// records are bucketed by tile with a counting sort, and each segment of a
+// tile is summed in LDS, then stored (a tile's only segment) or added to the
+// counts with integer atomics (tiles with several segments).
+constexpr int kBinThreads = 256;
+constexpr int kBinChunk = 2048;              // samples per histogram / scatter workgroup
+constexpr int kMaxTiles = 8192;              // tile-indexed LDS arrays: at most 96 KiB
 constexpr int kMaxTileCells = 4096;
-constexpr int kMaxChunks = 2048;             // chunk-indexed LDS arrays of the plan and gather: 16 KiB
-constexpr int kSplitRecords = 4096;          // records of one gather segment at most
+constexpr int kSegment = 4096;                // records per accumulation segment
+constexpr int kAccumThreads = 1024;           // threads of an accumulation workgroup
+constexpr int kAccumBatchThreads = 256;       // the same in batched launches (many small tiles)
+constexpr int kScatterThreads = 512;          // threads of a scatter workgroup (divides kBinChunk)
 
 struct TileGeom {
     int T[kMaxD];           // tile extent (cells, power of two) per axis
@@ -94,19 +84,19 @@ struct TileGeom {
     int tile_cells;         // prod T
     int jbits[kMaxD];       // record bits of (tile-local lower corner + 1) per axis
     int qbits;              // record bits of one fraction q (Q + 1)
+    int S;                  // records per accumulation segment
     int64_t nchunk;         // ceil(n / kBinChunk)
-    int64_t chunk_cap;      // records a chunk's region holds: kBinChunk 2^d
-    int64_t cells;          // prod M
-    int64_t max_items;      // gather workgroups: ntiles + ceil(n 2^d / kSplitRecords) bounds the segments
+    int64_t max_records;    // n 2^d
+    int64_t max_segments;   // ntiles + ceil(max_records / S): accumulation workgroups
 };
 
 struct BinWork {
-    uint32_t* tab;          // [ntiles][nchunk]: (offset << 16) | length of the tile's group in the chunk
-    uint32_t* pre;          // [ntiles][nchunk + 1]: records of the tile before chunk c; entry nchunk: all
+    uint32_t* hist;         // [ntiles][nchunk] counts, then exclusive offsets over chunks
+    uint32_t* tot;          // [ntiles] records per tile
     uint32_t* drops;        // [nchunk] dropped samples per chunk
-    uint4* items;           // [max_items] segments: {tile, k, m, records of the tile}
-    uint32_t* nitems;       // [1] segments appended by the plan
-    uint64_t* records;      // [nchunk][chunk_cap]
+    uint64_t* records;      // [max_records]
+    uint4* seg;             // [max_segments] accumulation work list: {tile, first record, end
+                            // record, tile has several segments}; tile all ones: no work
 };
 
 // Everything one instance of the tiled binning reads and writes.
@@ -120,7 +110,7 @@ struct BinArgs {
     unsigned long long* n_dropped;   // may be null
 };
 
-enum BinStage : int { kBinSort = 0, kBinPlan = 1, kBinGather = 2 };
+enum BinStage : int { kBinHist = 0, kBinScan = 1, kBinScatter = 2, kBinAccum = 3 };
 
 // One stage of the tiled binning for one instance; bin_stage_lds is the
 // dynamic LDS a stage needs for the geometry g.
@@ -243,24 +233,23 @@ C2RArgs<R> make_c2r_args(const void* in, int64_t nrows, int64_t in_ld, const voi
     return a;
 }
 
-// The binning sort and the kernel-spectrum row pass in one launch (padded
-// lengths up to kSortSpecMaxP): the first workgroups transform lag-box rows,
-// the rest sort chunks.
-constexpr int kSortSpecMaxP = 1024;
+// The binning histogram and the kernel-spectrum row pass in one launch
+// (d <= 2): the first workgroups transform lag-box rows, the rest histogram.
 template <typename R>
-struct SortSpecArgs {
+struct HistSpecArgs {
     BinArgs bin;
     RowArgs<R> row;
 };
-hipError_t launch_sort_kspec(int prec, int P, int d, const void* args, hipStream_t s);
+hipError_t launch_hist_kspec(int prec, int P, int d, const void* args, hipStream_t s);
+int64_t hist_kspec_blocks(int P, int64_t nchunk, int64_t spec_rows);
 
-// The binning plan and the 3-D spectrum's strided pass (kColFwdCirc) in one
-// launch: the first workgroups transform lag-box columns, the rest plan tiles.
-struct PlanColArgs {
+// The binning scan and the spectrum's strided pass (kColFwdCirc) in one launch
+// (d = 3): the first workgroups transform lag-box columns, the rest scan.
+struct ScanColArgs {
     BinArgs bin;
     ColArgs col;
 };
-hipError_t launch_plan_kcol(int prec, int P, const PlanColArgs& a, hipStream_t s);
+hipError_t launch_scan_kcol(int prec, int P, const ScanColArgs& a, hipStream_t s);
 
 // All launchers return hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t* p, int64_t count, hipStream_t s);

@@ -205,15 +205,15 @@ def test_batch_plan_sizes_and_launch_count():
     assert rc == 0 and info.count == 3
     need = sum(K.kde_plan_query(H, n, g)["eval_ws_bytes"] for n, H, g in probs)
     assert info.ws_bytes >= need
-    assert info.launches == 3 + 4 * 2                 # two padded lengths (128, 256)
+    assert info.launches == 4 + 4 * 2                 # two padded lengths (128, 256)
     # d = 1, 2, 3 together: one launch per (pass, template) group
     probs = [(5000, [[0.2]], ((-3,), (3,), (300,))), (5000, H2, ((-3, -3), (3, 3), (64, 64))),
              (5000, np.eye(3) * 0.3, ((-3,) * 3, (3,) * 3, (20, 20, 20)))]
     rc, info = _batch_info(_batch_items(probs))
     assert rc == 0
-    # binning 3 per d; d=1: kspec, counts, product; d=2: kspec, counts, conv, c2r;
+    # binning 4 per d; d=1: kspec, counts, product; d=2: kspec, counts, conv, c2r;
     # d=3: kspec_r2c, kspec_col2, counts_r2c, counts_col2, conv_col1, inv_col2, c2r
-    assert info.launches == 9 + 3 + 4 + 7
+    assert info.launches == 12 + 3 + 4 + 7
 
 
 def test_batch_plan_errors():
@@ -343,9 +343,9 @@ def test_bench_counter_record_names_the_sources():
         assert 1.5 < cal["fetch_factor"] < 2.5 and 0.5 < cal["write_factor"] < 1.5
         assert all(k["FETCH_SIZE"] > 0 for k in c["workloads"][wl].values())
     if c["source_sha256"] == bench.kernel_source_hash():
-        assert bench.measured_traffic("mix2d_512", "bin_gather") > 0
+        assert bench.measured_traffic("mix2d_512", "bin_scatter") > 0
     else:
-        assert bench.measured_traffic("mix2d_512", "bin_gather") is None
+        assert bench.measured_traffic("mix2d_512", "bin_scatter") is None
 
 
 # --------------------------------------------------------------------------

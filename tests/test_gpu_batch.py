@@ -50,9 +50,9 @@ def test_batch_matches_single_bit_identical(prec):
     _assert_matches_single(B, items, prec=prec)
     info = B.info()
     sides = {w.M[0] for w in wl}
-    # three binning stages, then one launch per padded length for each of the
+    # four binning stages, then one launch per padded length for each of the
     # four FFT passes
-    assert info["launches"] == 3 + 4 * len(sides)
+    assert info["launches"] == 4 + 4 * len(sides)
 
 
 def test_batch_matches_oracle():
@@ -183,7 +183,8 @@ def test_batch_trace_names_groups():
     B.eval()
     torch.cuda.synchronize()
     t = B.trace()
-    assert t["names"] == ["bin_sort", "bin_plan", "bin_gather", "counts_r2c", "kspec_r2c", "conv_col", "c2r"]
+    assert t["names"] == ["bin_hist", "bin_scan", "bin_scatter", "bin_accum", "counts_r2c",
+                          "kspec_r2c", "conv_col", "c2r"]
     for i in range(t["count"]):
         ms = ctypes.c_float()
         assert hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(evs[2 * i]),
