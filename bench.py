@@ -5,12 +5,12 @@ samples, lag-box fill, kernel spectrum, forward FFTs of the counts, product,
 inverse FFTs, window) over inputs already resident in HBM. Default workload:
 d = 2, n = 1,000,000 samples of a 5-component normal mixture, 512 x 512 grid,
 full H with correlation 0.8, FP32 convolution. The JSON line also carries the
-3-D 128^3 and FP64 variants, the batched form (256 independent 2-D problems
+3-D 128^3, 4-D 48^4 and FP64 variants, the batched form (256 independent 2-D problems
 of uneven size through kde_batch_*, autotuned, eager and graph-replayed), the
 per-kernel roofline of the dominant kernel and the FP64 CPU oracle timed on
 the host.
 
-    python bench.py [--steps K] [--warmup W] [--workload mix2d_512|mix3d_128] [--prec f32|f64]
+    python bench.py [--steps K] [--warmup W] [--workload mix2d_512|mix3d_128|mix4d_48] [--prec f32|f64]
 """
 from __future__ import annotations
 
@@ -68,10 +68,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="mix2d_512", choices=["mix2d_512", "mix3d_128"])
+    ap.add_argument("--workload", default="mix2d_512", choices=["mix2d_512", "mix3d_128", "mix4d_48"])
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / FP64 / batched side measurements")
-    ap.add_argument("--variants", default="mix2d_512_f64,mix3d_128_f32,mix3d_128_f64,batch",
+    ap.add_argument("--no-variants", action="store_true", help="skip the 3-D / 4-D / FP64 / batched side measurements")
+    ap.add_argument("--variants", default="mix2d_512_f64,mix3d_128_f32,mix3d_128_f64,mix4d_48_f32,batch",
                     help="comma-separated side measurements to run")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched measurement (0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -120,7 +120,8 @@ class Hip:
 def conv_method_bytes(d, M, P, prec):
     """Method bytes of the FFT convolution (counts -> density), per pass, r2c form:
     2-D: 8 M^2 + 4 M H w_c + P H w_r + M^2 w_r; 3-D: 8 M^3 + 4 M^2 H w_c + 4 M P H w_c
-    + P^2 H w_r + M^3 w_r, with H = P_d / 2 + 1 (1-D: 8 M + 2 H w_c + H w_r + M w_r)."""
+    + P^2 H w_r + M^3 w_r, with H = P_d / 2 + 1 (1-D: 8 M + 2 H w_c + H w_r + M w_r; 4-D: each
+    strided pass reads and writes its arrays once, and the product reads the real spectrum)."""
     rs = 4 if prec == "f32" else 8
     cs = 2 * rs
     H = P[-1] // 2 + 1
@@ -130,6 +131,13 @@ def conv_method_bytes(d, M, P, prec):
     if d == 2:
         rows = M[0] * H * cs
         return {"counts_r2c": cells * 8 + rows, "conv_col": 2 * rows + P[0] * H * rs, "c2r": rows + cells * rs}
+    if d == 4:
+        z1 = M[0] * M[1] * M[2] * H * cs          # [M0][M1][M2] half spectra
+        z2 = M[0] * M[1] * P[2] * H * cs          # [M0][M1][P2]
+        z3 = M[0] * P[1] * P[2] * H * cs          # [M0][P1][P2]
+        return {"counts_r2c": cells * 8 + z1, "counts_col3": z1 + z2, "counts_col2": z2 + z3,
+                "conv_col1": 2 * z3 + P[0] * P[1] * P[2] * H * rs, "inv_col2": z3 + z2, "inv_col3": z2 + z1,
+                "c2r": z1 + cells * rs}
     plane = M[0] * M[1] * H * cs
     mid = M[0] * P[1] * H * cs
     return {"counts_r2c": cells * 8 + plane, "counts_col2": plane + mid, "conv_col1": 2 * mid + P[0] * P[1] * H * rs,
@@ -146,6 +154,11 @@ def spectrum_bytes(d, L, P, prec):
         return {"kspec_r2c": H * cs // 2}
     if d == 2:
         return {"kspec_r2c": nb[0] * H * cs}
+    if d == 4:
+        k1 = nb[0] * nb[1] * nb[2] * H * cs
+        k2 = nb[0] * nb[1] * P[2] * H * cs
+        k3 = nb[0] * P[1] * P[2] * H * cs
+        return {"kspec_r2c": k1, "kspec_col3": k1 + k2, "kspec_col2": k2 + k3}
     return {"kspec_r2c": nb[0] * nb[1] * H * cs, "kspec_col2": nb[0] * nb[1] * H * cs + nb[0] * P[1] * H * cs}
 
 
@@ -163,7 +176,8 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
     nb = [2 * l + 1 for l in L]
     # the product pass also reads its lag columns and transforms them in place
     lagcols = {2: {"conv_col": nb[0] * H * cs - P[0] * H * rs},
-               3: {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs}}.get(d, {})
+               3: {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs},
+               4: {"conv_col1": nb[0] * P[1] * P[2] * H * cs - P[0] * P[1] * P[2] * H * rs}}.get(d, {})
     binning = {
         "zero_counts": (0, cells * 8), "zero_dropped": (0, 8), "bin": (x_read + counts_write, 0),
         "bin_hist": (x_read, 0), "bin_scan": (0, 0), "bin_scatter": (0, x_read + records),
@@ -184,8 +198,9 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
     return {"alg": a, "design": a + lagcols.get(name, 0)}
 
 
-CONV_KERNELS = {"counts_r2c", "counts_col2", "conv_col", "conv_col1", "inv_col2", "c2r", "product_c2r"}
-SPEC_KERNELS = {"kspec_r2c", "kspec_col2"}
+CONV_KERNELS = {"counts_r2c", "counts_col2", "counts_col3", "conv_col", "conv_col1", "inv_col2", "inv_col3", "c2r",
+                "product_c2r"}
+SPEC_KERNELS = {"kspec_r2c", "kspec_col2", "kspec_col3"}
 
 
 def step_roofline(kern: dict, names, alg_bytes: int) -> dict:
@@ -484,7 +499,7 @@ def main():
     variants = {}
     if not a.no_variants:
         chosen = set(a.variants.split(","))
-        for name, prec in (("mix2d_512", "f64"), ("mix3d_128", "f32"), ("mix3d_128", "f64")):
+        for name, prec in (("mix2d_512", "f64"), ("mix3d_128", "f32"), ("mix3d_128", "f64"), ("mix4d_48", "f32")):
             if (name, prec) == (a.workload, a.prec) or f"{name}_{prec}" not in chosen:
                 continue
             v = measure(K, W, hip, name, prec, max(20, a.steps // 4), 5)

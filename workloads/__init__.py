@@ -146,6 +146,17 @@ def mix3d_128(n: int = 1_000_000, M: int = 128, seed_offset: int = 0) -> Workloa
     return Workload("mix3d_128", X, H, lo, hi, (M, M, M))
 
 
+def mix4d_48(n: int = 1_000_000, M: int = 48, seed_offset: int = 0) -> Workload:
+    rng = np.random.default_rng(SEED_BASE + 5 + seed_offset)
+    k = 4
+    means = rng.uniform(-4.0, 4.0, size=(k, 4))
+    covs = [random_spd(rng, 4, ratio=(1.0, 20.0)) for _ in range(k)]
+    X = sample_mixture(rng, n, means, covs)
+    H = normal_scale_H(X)
+    lo, hi = grid_box(X, H)
+    return Workload("mix4d_48", X, H, lo, hi, (M, M, M, M))
+
+
 def batch2d(count: int = 256, seed_offset: int = 0, n_range=(1e3, 1e6), sides=(64, 128, 256, 512),
             ratio_max: float = 20.0) -> list:
     rng = np.random.default_rng(SEED_BASE + 4 + seed_offset)
@@ -172,6 +183,7 @@ WORKLOADS = {
     "mix2d_small": mix2d_small,
     "mix2d_512": mix2d_512,
     "mix3d_128": mix3d_128,
+    "mix4d_48": mix4d_48,
 }
 
 
