@@ -175,9 +175,13 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
     spec = spectrum_bytes(d, L, P, prec)
     nb = [2 * l + 1 for l in L]
     # the product pass also reads its lag columns and transforms them in place
-    lagcols = {2: {"conv_col": nb[0] * H * cs - P[0] * H * rs},
-               3: {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs},
-               4: {"conv_col1": nb[0] * P[1] * P[2] * H * cs - P[0] * P[1] * P[2] * H * rs}}.get(d, {})
+    lagcols = {}
+    if d == 2:
+        lagcols = {"conv_col": nb[0] * H * cs - P[0] * H * rs}
+    elif d == 3:
+        lagcols = {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs}
+    elif d == 4:
+        lagcols = {"conv_col1": nb[0] * P[1] * P[2] * H * cs - P[0] * P[1] * P[2] * H * rs}
     binning = {
         "zero_counts": (0, cells * 8), "zero_dropped": (0, 8), "bin": (x_read + counts_write, 0),
         "bin_hist": (x_read, 0), "bin_scan": (0, 0), "bin_scatter": (0, x_read + records),
