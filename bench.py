@@ -182,16 +182,19 @@ def kernel_bytes(name: str, w, plan: dict, prec: str) -> dict:
         lagcols = {"conv_col1": nb[0] * P[1] * H * cs - P[0] * P[1] * H * rs}
     elif d == 4:
         lagcols = {"conv_col1": nb[0] * P[1] * P[2] * H * cs - P[0] * P[1] * P[2] * H * rs}
+    # The method reads X once and writes the counts once. This design reads X twice (the
+    # histogram counts records, the scatter places them); the method's read is credited to the
+    # scatter, whose records the accumulation sums, and the histogram's read is design bytes.
     binning = {
         "zero_counts": (0, cells * 8), "zero_dropped": (0, 8), "bin": (x_read + counts_write, 0),
-        "bin_hist": (x_read, 0), "bin_scan": (0, 0), "bin_scatter": (0, x_read + records),
+        "bin_hist": (0, x_read), "bin_scan": (0, 0), "bin_scatter": (x_read, records),
         "bin_accum": (counts_write, records),
     }
     if name in binning:
         a, extra = binning[name]
         return {"alg": a, "design": a + extra}
     if name == "hist_kspec":
-        return {"alg": x_read + spec["kspec_r2c"], "design": x_read + spec["kspec_r2c"]}
+        return {"alg": spec["kspec_r2c"], "design": x_read + spec["kspec_r2c"]}
     if name == "scan_kcol":
         return {"alg": spec["kspec_col2"], "design": spec["kspec_col2"]}
     if name == "kfill":
