@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 TOL = {"f32": 2e-5, "f64": 1e-12}
-CASES = [(2, 2000, 64, 0.7), (2, 500, 40, 1.6), (1, 3000, 200, 1.0), (3, 1500, 20, 1.2), (2, 20000, 128, 0.5)]
+CASES = [(2, 2000, 64, 0.7), (2, 500, 40, 1.6), (1, 3000, 200, 1.0), (3, 1500, 20, 1.2), (2, 20000, 128, 0.5),
+         (4, 2000, 12, 1.0)]
 
 
 def _dev(x):
