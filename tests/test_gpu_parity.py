@@ -49,7 +49,7 @@ def test_bin_hand_cases_bit_exact():
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("name", ["mix2d_small", "mix2d_512", "mix3d_128"])
+@pytest.mark.parametrize("name", ["mix2d_small", "mix2d_512", "mix3d_128", "mix4d_48"])
 def test_bin_workloads_bit_exact(name):
     w = W.WORKLOADS[name]()
     ref, rnd = O.bin_fixed(w.X, w.lo, w.hi, w.M)
@@ -386,6 +386,34 @@ def test_eval_3d_128_full_grid(ref3d128, full3d128, prec):
     pts = [(64, 64, 64), (0, 0, 0), (127, 3, 90), (17, 127, 0)]
     ref = O.conv_direct_at(c, k, p["L"], pts)
     assert np.max(np.abs(np.array([full3d128[q] for q in pts]) - ref)) <= 1e-14 * full3d128.max()
+
+
+@pytest.fixture(scope="module")
+def ref4d48():
+    """The 4-D bench workload (n = 1e6, 48^4) through the oracle: counts, weights and the
+    FFT form of Eq. (7) (Eq. 12-14 at P_k >= M_k + L_k, pinned on the CPU to the direct sum)."""
+    import os
+    w = W.mix4d_48()
+    f, info = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method="fft", workers=min(16, os.cpu_count() or 1))
+    return w, info, f
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_eval_4d_48_full_grid(ref4d48, prec):
+    """Every one of the 5.3M cells of the 4-D estimate against the oracle, and sampled cells
+    against the direct sum evaluated one by one."""
+    w, info, f = ref4d48
+    got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    assert int(nd.cpu().numpy()[0]) == info["n_dropped"]
+    assert got.shape == f.shape
+    assert _rel(got, f) <= TOL[prec], _rel(got, f)
+    rng = np.random.default_rng(9)
+    pts = [tuple(int(v) for v in rng.integers(0, 48, size=4)) for _ in range(200)]
+    pts.append(tuple(int(v) for v in np.unravel_index(np.argmax(f), f.shape)))
+    ref = O.conv_direct_at(info["c"], info["k"], info["L"], pts)
+    assert np.max(np.abs(np.array([got[q] for q in pts]) - ref)) <= TOL[prec] * f.max()
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
