@@ -370,6 +370,13 @@ def test_grid_from_data_hand_values():
     assert M == (40, 40)
     lo, hi, _ = K.grid_tuple(K.kde_grid_from_data(X[:3, :1], [[0.04]], 8, 0.0))
     assert lo[0] == 0.0 and hi[0] == 2.0
+    # d = 4: sqrt(H_kk) = 0.5, 1, 2, 0.25 (off-diagonal entries do not enter), times 3
+    X4 = np.array([[0.0, 1.0, -2.0, 3.0], [1.0, -1.0, 2.0, 3.5], [0.5, 0.0, 0.0, 2.0]])
+    H4 = np.diag([0.25, 1.0, 4.0, 0.0625])
+    H4[0, 1] = H4[1, 0] = 0.1
+    lo, hi, M = K.grid_tuple(K.kde_grid_from_data(X4, H4, 24, 3.0))
+    assert np.array_equal(lo, [-1.5, -4.0, -8.0, 1.25]) and np.array_equal(hi, [2.5, 4.0, 8.0, 4.25])
+    assert M == (24, 24, 24, 24)
 
 
 def test_grid_from_data_errors():
