@@ -203,6 +203,116 @@ __device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
     }
 }
 
+// First-stage DFTs of a line whose zero padding the launch knows: all inputs
+// (kPruneNone); only the lower half a[0 .. RAD/2) (kPruneHalf: a zero-padded
+// prefix of at most P/2 elements, Eq. 13); only a[0] and a[RAD - 1]
+// (kPruneEnds: a circularly placed lag axis whose half width L is below the
+// line's T threads, Eq. 12). The terms left out are additions of zero, so the
+// outputs are the full DFT's (up to the sign of a zero).
+enum Prune : int { kPruneNone = 0, kPruneHalf = 1, kPruneEnds = 2 };
+
+// Pruned first stages add a second copy of a transform to a kernel. They pay
+// where the passes are VALU-bound (FP32, P <= 256: the 3-D product pass 27.9 ->
+// 26.9 us at 128^3); in FP64 the extra registers cost occupancy (the same pass
+// 42.7 -> 62.7 us), and the latency-bound P = 1024 passes got slower by 0.4 us.
+template <typename R, int P>
+constexpr bool kPruneFirst = sizeof(R) == 4 && P <= 256;
+
+template <typename R>
+__device__ __forceinline__ void dft4_half(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {   // a2 = a3 = 0
+    const cpx<R> x0 = a0, x1 = a1, t3 = mul_minus_i(x1);
+    a0 = x0 + x1;
+    a2 = x0 - x1;
+    a1 = x0 + t3;
+    a3 = x0 - t3;
+}
+
+template <typename R>
+__device__ __forceinline__ void dft4_ends(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {   // a1 = a2 = 0
+    const cpx<R> x0 = a0, x3 = a3, t3 = mul_minus_i(cpx<R>{-x3.re, -x3.im});
+    a0 = x0 + x3;
+    a2 = x0 - x3;
+    a1 = x0 + t3;
+    a3 = x0 - t3;
+}
+
+template <typename R>
+__device__ __forceinline__ void dft4_last(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {   // a0 = a1 = a2 = 0
+    const cpx<R> x3 = a3, t3 = mul_minus_i(cpx<R>{-x3.re, -x3.im});
+    a0 = x3;
+    a2 = cpx<R>{-x3.re, -x3.im};
+    a1 = t3;
+    a3 = cpx<R>{-t3.re, -t3.im};
+}
+
+template <int RAD, int PR, typename R>
+__device__ __forceinline__ void dft_first(cpx<R> (&a)[RAD]) {
+    if constexpr (PR == kPruneNone || RAD == 2) {
+        dft<RAD>(a);
+    } else if constexpr (RAD == 4) {
+        if constexpr (PR == kPruneHalf) dft4_half(a[0], a[1], a[2], a[3]);
+        else dft4_ends(a[0], a[1], a[2], a[3]);
+    } else if constexpr (RAD == 8) {
+        if constexpr (PR == kPruneHalf) {
+            dft4_half(a[0], a[2], a[4], a[6]);
+            dft4_half(a[1], a[3], a[5], a[7]);
+        } else {
+            a[2] = a[0];
+            a[4] = a[0];
+            a[6] = a[0];
+            dft4_last(a[1], a[3], a[5], a[7]);
+        }
+        const cpx<R> o1 = rot16<2>(a[3]), o2 = rot16<4>(a[5]), o3 = rot16<6>(a[7]);
+        const cpx<R> y0 = a[0] + a[1], y4 = a[0] - a[1];
+        const cpx<R> y1 = a[2] + o1, y5 = a[2] - o1;
+        const cpx<R> y2 = a[4] + o2, y6 = a[4] - o2;
+        const cpx<R> y3 = a[6] + o3, y7 = a[6] - o3;
+        a[0] = y0; a[1] = y1; a[2] = y2; a[3] = y3;
+        a[4] = y4; a[5] = y5; a[6] = y6; a[7] = y7;
+    } else {
+        static_assert(RAD == 16, "first-stage radix 4, 8 or 16");
+        if constexpr (PR == kPruneHalf) {
+            dft4_half(a[0], a[4], a[8], a[12]);
+            dft4_half(a[1], a[5], a[9], a[13]);
+            dft4_half(a[2], a[6], a[10], a[14]);
+            dft4_half(a[3], a[7], a[11], a[15]);
+            a[5] = rot16<1>(a[5]);
+            a[6] = rot16<2>(a[6]);
+            a[9] = rot16<2>(a[9]);
+            a[10] = rot16<4>(a[10]);
+            a[13] = rot16<3>(a[13]);
+            a[14] = rot16<6>(a[14]);
+        } else {
+            // rows n2 = 1, 2 of the 4 x 4 input block are zero and stay zero
+            a[4] = a[0];
+            a[8] = a[0];
+            a[12] = a[0];
+            dft4_last(a[3], a[7], a[11], a[15]);
+        }
+        a[7] = rot16<3>(a[7]);
+        a[11] = rot16<6>(a[11]);
+        a[15] = rot16<9>(a[15]);
+        if constexpr (PR == kPruneHalf) {
+            dft4(a[0], a[1], a[2], a[3]);
+            dft4(a[4], a[5], a[6], a[7]);
+            dft4(a[8], a[9], a[10], a[11]);
+            dft4(a[12], a[13], a[14], a[15]);
+        } else {
+            dft4_ends(a[0], a[1], a[2], a[3]);
+            dft4_ends(a[4], a[5], a[6], a[7]);
+            dft4_ends(a[8], a[9], a[10], a[11]);
+            dft4_ends(a[12], a[13], a[14], a[15]);
+        }
+        cpx<R> y[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) y[k1 + 4 * k2] = a[4 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = y[i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // in-workgroup Stockham FFT of one line of length P
 // ---------------------------------------------------------------------------
@@ -264,7 +374,7 @@ __device__ __forceinline__ void load_twiddles(StageTwiddles<R, P, E, NS>& tw, in
 // j + r P/RAD and writes (j / NS) NS RAD + j % NS + r NS. Element
 // t + T m always lives in register slot m. `w` holds this thread's twiddles
 // exp(-2 pi i r (j mod NS) / (NS RAD)) for u, r >= 1.
-template <typename R, int P, int E, int LS, int RAD, int NS, int NW>
+template <typename R, int P, int E, int LS, int RAD, int NS, int NW, int PR = kPruneNone>
 __device__ __forceinline__ void fft_stage(cpx<R> (&v)[E], cpx<R>* lds, int t, const cpx<R> (&w)[NW]) {
     constexpr int T = P / E;
     constexpr int NB = E / RAD;
@@ -284,7 +394,8 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[E], cpx<R>* lds, int t, co
 #pragma unroll
             for (int r = 1; r < RAD; ++r) a[r] = a[r] * w[u * (RAD - 1) + r - 1];
         }
-        dft<RAD>(a);
+        if constexpr (kFirst) dft_first<RAD, PR>(a);
+        else dft<RAD>(a);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) v[u + r * NB] = a[r];
     }
@@ -311,15 +422,16 @@ __device__ __forceinline__ void fft_stages(cpx<R> (&v)[E], cpx<R>* lds, int t, c
 
 // Forward DFT (sign -1) of the line whose element t + T m is in v[m]; on
 // return v[m] holds output t + T m. Every thread of the workgroup must call
-// it (it contains barriers). LS is the LDS distance between padded elements.
-template <typename R, int P, int E, int LS>
+// it (it contains barriers). LS is the LDS distance between padded elements;
+// PR: the zero padding of the input the first stage may skip (dft_first).
+template <typename R, int P, int E, int LS, int PR = kPruneNone>
 __device__ __forceinline__ void fft_line(cpx<R> (&v)[E], cpx<R>* lds, int t) {
     static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
     static_assert((E == 4 || E == 8 || E == 16) && E <= P, "4, 8 or 16 points per thread");
     StageTwiddles<R, P, E, E> tw;
     load_twiddles<R, P, E, E>(tw, t);
     constexpr cpx<R> none[1] = {};
-    fft_stage<R, P, E, LS, E, 1>(v, lds, t, none);
+    fft_stage<R, P, E, LS, E, 1, 1, PR>(v, lds, t, none);
     fft_stages<R, P, E, LS, E>(v, lds, t, tw);
 }
 
@@ -448,7 +560,11 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
         }
     }
     C* line = lds + b * LINE;
-    fft_line<R, P, E, 1>(v, line, t);
+    // zero padding the first stage skips: counts past len (len <= P/2), or lags past L < T
+    if (kPruneFirst<R, P> && (IN_KIND == kRowCountsU64 ? 2 * len <= P : len < T))
+        fft_line<R, P, E, 1, IN_KIND == kRowCountsU64 ? kPruneHalf : kPruneEnds>(v, line, t);
+    else
+        fft_line<R, P, E, 1>(v, line, t);
     // split Z = X + iY of two real rows: X_k = (Z_k + conj Z_-k)/2, Y_k = (Z_k - conj Z_-k)/(2i)
     __syncthreads();
 #pragma unroll
@@ -579,15 +695,29 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
             const int idx = p <= a.kt_len ? p + a.kt_len : (p >= P - a.kt_len ? p - P + a.kt_len : -1);
             kv[m] = (act && idx >= 0) ? kin[idx * a.kt_ps] : C{0, 0};
         }
-        fft_line<R, P, E, B>(kv, lds + b, t);
-        fft_line<R, P, E, B>(v, lds + b, t);
+        if (kPruneFirst<R, P> && a.kt_len < T)
+            fft_line<R, P, E, B, kPruneEnds>(kv, lds + b, t);
+        else
+            fft_line<R, P, E, B>(kv, lds + b, t);
+        if (kPruneFirst<R, P> && 2 * a.len <= P)
+            fft_line<R, P, E, B, kPruneHalf>(v, lds + b, t);
+        else
+            fft_line<R, P, E, B>(v, lds + b, t);
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = scal(v[m], kv[m].re);
         ifft_line<R, P, E, B>(v, lds + b, t);
     } else if constexpr (MODE == kColInvPrefix) {
         ifft_line<R, P, E, B>(v, lds + b, t);
-    } else {
-        fft_line<R, P, E, B>(v, lds + b, t);
+    } else if constexpr (MODE == kColFwdPrefix) {
+        if (kPruneFirst<R, P> && 2 * a.len <= P)
+            fft_line<R, P, E, B, kPruneHalf>(v, lds + b, t);
+        else
+            fft_line<R, P, E, B>(v, lds + b, t);
+    } else {   // kColFwdCirc
+        if (kPruneFirst<R, P> && a.len < T)
+            fft_line<R, P, E, B, kPruneEnds>(v, lds + b, t);
+        else
+            fft_line<R, P, E, B>(v, lds + b, t);
     }
     if (!act) return;
     if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
