@@ -95,6 +95,17 @@ typedef struct kde_params {
                                  point with the same H, n, grid and options; it is not
                                  recomputed. The caller guarantees the match; the result is
                                  then identical to a full call */
+    int32_t store_spectrum;   /* 0 or 1; d >= 2, kde_conv / kde_eval / kde_lscv (batches
+                                 return KDE_ERR_ARG; d = 1 always stores it). 0 (default): the
+                                 product pass transforms each line's lag column itself (three
+                                 line transforms per line of the slowest axis, Eq. 10). 1: one
+                                 more spectrum pass stores the real spectrum of Eq. (10) on the
+                                 whole padded grid (P_1 ... P_(d-1) x pitch(P_d) reals of the
+                                 precision more workspace, pitch(P) = P/2 + 1 rounded up to a
+                                 multiple of 16) and the product pass reads it (two line
+                                 transforms). The same transforms either way, so the same
+                                 results; 1 pays off with reuse_spectrum (serving one H on new
+                                 samples), where the spectrum pass is skipped */
     int32_t trace_capacity;   /* optional per-kernel timing: number of events in
                                  trace_events, used in pairs */
     hipEvent_t* trace_events; /* if non-NULL: the i-th pass of the call (one kernel; the two

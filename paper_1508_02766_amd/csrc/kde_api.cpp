@@ -65,6 +65,7 @@ struct Plan {
     Layout lay;
     size_t counts_bytes;
     bool tiled;       // tiled binning (else global atomics)
+    bool store;       // d >= 2: the real spectrum is stored on the whole padded grid
     kde::TileGeom tg;
     BinLayout blay;
 };
@@ -216,6 +217,8 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         if (tcells > kde::kMaxTileCells) return KDE_ERR_ARG;
         if (prm->extent != 0 && prm->extent != 1) return KDE_ERR_ARG;
         if (prm->reuse_spectrum != 0 && prm->reuse_spectrum != 1) return KDE_ERR_ARG;
+        if (prm->store_spectrum != 0 && prm->store_spectrum != 1) return KDE_ERR_ARG;
+        out->store = prm->store_spectrum == 1 && d >= 2;
         extent = prm->extent;
         if (prm->trace_events && prm->trace_capacity < 0) return KDE_ERR_ARG;
     }
@@ -358,6 +361,12 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         L.z1 = take(static_cast<size_t>(M0 * M1 * M2 * Hl) * cs);
         L.z2 = take(static_cast<size_t>(M0 * M1 * P2 * Hl) * cs);
         L.z3 = take(static_cast<size_t>(M0 * P1 * P2 * Hl) * cs);
+    }
+    if (out->store) {
+        // the real spectrum [P0][P1 .. P(d-2)][Hl]
+        int64_t lines = Hl;
+        for (int k = 0; k < d - 1; ++k) lines *= p.P[k];
+        L.khat = take(static_cast<size_t>(lines) * rs);
     }
     L.total = off;
     p.conv_ws_bytes = L.total;
@@ -698,9 +707,9 @@ Pass cols_pass(const Plan& pl, int P, int mode, const kde::ColArgs& a, int nmask
 
 // Kernel spectrum: lag-box weights computed in place (Eq. 6 over the signed
 // box of Eq. 12), transformed along every axis but the slowest (whose
-// transform the product pass computes per line); real because the box is
-// centrally symmetric and placed circularly.
-int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
+// transform the product pass computes per line unless the plan stores the
+// spectrum); real because the box is centrally symmetric and placed circularly.
+int run_kspec_lags(const Plan& pl, char* ws, int nmask, Emit& emit) {
     const kde_plan& p = pl.pub;
     const int d = p.d;
     const ConvBufs b = conv_bufs(pl, ws);
@@ -769,6 +778,35 @@ int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
     k1.out_ps = Hp;
     k1.len = p.L[1];
     return emit(cols_pass(pl, P1, kde::kColFwdCirc, k1, nmask, 1, "kspec_col2"));
+}
+
+// The slowest axis of the spectrum (d >= 2, stored plans): the lag columns
+// transformed along the other axes, [2 L0 + 1][lines], to the real spectrum
+// [P0][lines]. Its transform prunes as the product pass's own lag-column
+// transform does, so both spectra are the same numbers.
+int run_kspec_store(const Plan& pl, char* ws, int nmask, Emit& emit) {
+    const kde_plan& p = pl.pub;
+    const int d = p.d;
+    const ConvBufs b = conv_bufs(pl, ws);
+    const int64_t Pl = p.P[d - 1], Hp = half_pitch(static_cast<int>(Pl));
+    int64_t mid = 1;   // P1 .. P(d-2)
+    for (int k = 1; k < d - 1; ++k) mid *= p.P[k];
+    kde::ColArgs ks{};
+    ks.in = d == 2 ? b.kt1 : (d == 3 ? b.kt2 : b.kt3);
+    ks.out = b.khat;
+    ks.W = Pl / 2 + 1;
+    ks.outer = mid;
+    ks.in_os = Hp;
+    ks.out_os = Hp;
+    ks.in_ps = mid * Hp;
+    ks.out_ps = mid * Hp;
+    ks.len = p.L[0];
+    return emit(cols_pass(pl, p.P[0], kde::kColFwdCircRe, ks, nmask, 3, "kspec_col1"));
+}
+
+int run_kspec(const Plan& pl, char* ws, int nmask, Emit& emit) {
+    KDE_CHECK(run_kspec_lags(pl, ws, nmask, emit));
+    return pl.store ? run_kspec_store(pl, ws, nmask, emit) : KDE_OK;
 }
 
 // Forward transforms of the zero-padded counts that do not need the spectrum.
@@ -840,6 +878,8 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     const ConvBufs b = conv_bufs(pl, ws);
     double scale = std::ldexp(1.0, -d * p.Q);
     for (int k = 0; k < d; ++k) scale /= static_cast<double>(p.P[k]);
+    // a stored spectrum has the real-spectrum layout of the data, [P0][..][Hp] (kt strides)
+    const int conv_mode = pl.store ? kde::kColConvSpec : kde::kColConvLag;
     if (d == 1) {
         const int P0 = p.P[0];
         const int64_t H0 = P0 / 2 + 1, M0 = g->M[0];
@@ -852,7 +892,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         kde::ColArgs ca{};
         ca.in = b.z1;
         ca.out = b.z1;
-        ca.kt = b.kt1;
+        ca.kt = pl.store ? b.khat : b.kt1;
         ca.kt_ps = Hp;
         ca.kt_len = p.L[0];
         ca.W = H1;
@@ -861,7 +901,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         ca.out_ps = Hp;
         ca.len = static_cast<int>(M0);
         ca.mout = static_cast<int>(M0);
-        KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, ca, nmask, 20, "conv_col")));
+        KDE_CHECK(emit(cols_pass(pl, P0, conv_mode, ca, nmask, 20, "conv_col")));
         return emit(row_c2r_pass(pl, P1, b.z1, M0, Hp, nullptr, density, M1, static_cast<int>(M1), scale, 21, "c2r"));
     }
     if (d == 4) {
@@ -872,7 +912,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         kde::ColArgs cv{};
         cv.in = b.z3;
         cv.out = b.z3;
-        cv.kt = b.kt3;
+        cv.kt = pl.store ? b.khat : b.kt3;
         cv.W = H3;
         cv.outer = static_cast<int64_t>(P1) * P2;
         cv.in_os = Hp;
@@ -884,7 +924,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
         cv.kt_len = p.L[0];
         cv.len = static_cast<int>(M0);
         cv.mout = static_cast<int>(M0);
-        KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, cv, nmask, 20, "conv_col1")));
+        KDE_CHECK(emit(cols_pass(pl, P0, conv_mode, cv, nmask, 20, "conv_col1")));
         // axis 1: [M0][P1][P2 Hp] -> [M0][M1][P2 Hp]; outer index (i0, w2)
         kde::ColArgs i1{};
         i1.in = b.z3;
@@ -920,7 +960,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     kde::ColArgs cv{};
     cv.in = b.z2;
     cv.out = b.z2;
-    cv.kt = b.kt2;
+    cv.kt = pl.store ? b.khat : b.kt2;
     cv.W = H2;                                  // lines (w2, w3): outer index w2, inner w3
     cv.outer = P1;
     cv.in_os = Hp;
@@ -932,7 +972,7 @@ int run_product_inv(const Plan& pl, const kde_grid* g, void* density, char* ws, 
     cv.kt_len = p.L[0];
     cv.len = static_cast<int>(M0);
     cv.mout = static_cast<int>(M0);
-    KDE_CHECK(emit(cols_pass(pl, P0, kde::kColConvLag, cv, nmask, 20, "conv_col1")));
+    KDE_CHECK(emit(cols_pass(pl, P0, conv_mode, cv, nmask, 20, "conv_col1")));
     kde::ColArgs i1{};
     i1.in = b.z2;
     i1.out = b.z1;
@@ -1354,6 +1394,8 @@ int rebind(kde_batch& b, hipStream_t s) {
 // LSCV job table) at the head of the workspace.
 int batch_create(std::vector<kde_batch_item>&& items, std::vector<char>&& internal, std::vector<kde::LscvJob>&& jobs,
                  const kde_params* params, kde_batch** out) {
+    // the batched column kernels transform the lag columns in the product pass
+    if (params && params->store_spectrum) return KDE_ERR_ARG;
     auto* b = new (std::nothrow) kde_batch;
     if (!b) return KDE_ERR_ARG;
     const int count = static_cast<int>(items.size());
@@ -1432,7 +1474,7 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
     std::vector<Pass> spec;
     if (pl.tiled && !reuse && pl.pub.d <= 3) {
         Collect c(spec);
-        KDE_CHECK(run_kspec(pl, conv_ws, -1, c));
+        KDE_CHECK(run_kspec_lags(pl, conv_ws, -1, c));
         const size_t want = pl.pub.d == 3 ? 2 : 1;
         if (spec.size() != want || spec[0].kind != kPassRowR2C || (want == 2 && spec[1].kind != kPassCols))
             spec.clear();
@@ -1440,7 +1482,7 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
     Tracer tr(params, stream);
     KDE_CHECK(tr.start());
     const int r = run_phases(
-        stream, tr, overlap && pl.pub.d >= 3 && spec.empty(),
+        stream, tr, overlap && pl.pub.d >= 3 && spec.empty() && !reuse,
         [&](hipStream_t s) {
             Direct e(s, tr);
             return reuse || !spec.empty() ? KDE_OK : run_kspec(pl, conv_ws, -1, e);
@@ -1449,6 +1491,8 @@ int eval_planned(const Plan& pl, const double* X, int64_t n, const kde_grid* gri
             Direct e(s, tr);
             KDE_CHECK(run_bin(pl, X, n, grid, counts, n_dropped, bin_ws, e, spec.empty() ? nullptr : &spec[0],
                               spec.size() == 2 ? &spec[1] : nullptr));
+            // a stored spectrum's slowest axis follows the passes fused into the binning
+            if (!spec.empty() && pl.store) KDE_CHECK(run_kspec_store(pl, conv_ws, -1, e));
             return run_counts_fwd(pl, counts, grid, conv_ws, -1, e);
         },
         [&](hipStream_t s) {
@@ -1561,7 +1605,7 @@ int kde_conv(const uint64_t* counts, int64_t n, const double* H, const kde_grid*
     Tracer tr(params, stream);
     KDE_CHECK(tr.start());
     const int r = run_phases(
-        stream, tr, pl.pub.d >= 3,
+        stream, tr, pl.pub.d >= 3 && !reuse,
         [&](hipStream_t s) {
             Direct e(s, tr);
             return reuse ? KDE_OK : run_kspec(pl, conv_ws, -1, e);

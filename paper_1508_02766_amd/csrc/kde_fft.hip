@@ -168,6 +168,8 @@ hipError_t cols_launch_b(int mode, const ColArgs& a, hipStream_t s) {
     switch (mode) {
         case kColFwdPrefix: KDE_LAUNCH((cols_kernel<R, P, kColFwdPrefix, NARROW>), g, blk, 0, s, a); break;
         case kColFwdCirc: KDE_LAUNCH((cols_kernel<R, P, kColFwdCirc, NARROW>), g, blk, 0, s, a); break;
+        case kColFwdCircRe: KDE_LAUNCH((cols_kernel<R, P, kColFwdCircRe, NARROW>), g, blk, 0, s, a); break;
+        case kColConvSpec: KDE_LAUNCH((cols_kernel<R, P, kColConvSpec, NARROW>), g, blk, 0, s, a); break;
         case kColInvPrefix: KDE_LAUNCH((cols_kernel<R, P, kColInvPrefix, NARROW>), g, blk, 0, s, a); break;
         case kColConvLag: KDE_LAUNCH((cols_kernel<R, P, kColConvLag, NARROW>), g, blk, 0, s, a); break;
         default: return hipErrorInvalidValue;

@@ -674,9 +674,9 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
     for (int m = 0; m < E; ++m) {
         const int p = t + T * m;
         C x{0, 0};
-        if constexpr (MODE == kColFwdPrefix || MODE == kColConvLag) {
+        if constexpr (MODE == kColFwdPrefix || MODE == kColConvLag || MODE == kColConvSpec) {
             if (act && p < a.len) x = in[p * a.in_ps];
-        } else if constexpr (MODE == kColFwdCirc) {
+        } else if constexpr (MODE == kColFwdCirc || MODE == kColFwdCircRe) {
             const int idx = p <= a.len ? p + a.len : (p >= P - a.len ? p - P + a.len : -1);
             if (act && idx >= 0) x = in[idx * a.in_ps];
         } else {   // kColInvPrefix
@@ -706,6 +706,19 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = scal(v[m], kv[m].re);
         ifft_line<R, P, E, B>(v, lds + b, t);
+    } else if constexpr (MODE == kColConvSpec) {
+        // the stored spectrum of this line, loaded while the data line is transformed
+        const R* kin = static_cast<const R*>(a.kt) + o1 * a.kt_os1 + o * a.kt_os + w;
+        R kv[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) kv[m] = act ? kin[(t + T * m) * a.kt_ps] : R(0);
+        if (kPruneFirst<R, P> && 2 * a.len <= P)
+            fft_line<R, P, E, B, kPruneHalf>(v, lds + b, t);
+        else
+            fft_line<R, P, E, B>(v, lds + b, t);
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = scal(v[m], kv[m]);
+        ifft_line<R, P, E, B>(v, lds + b, t);
     } else if constexpr (MODE == kColInvPrefix) {
         ifft_line<R, P, E, B>(v, lds + b, t);
     } else if constexpr (MODE == kColFwdPrefix) {
@@ -713,18 +726,22 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
             fft_line<R, P, E, B, kPruneHalf>(v, lds + b, t);
         else
             fft_line<R, P, E, B>(v, lds + b, t);
-    } else {   // kColFwdCirc
+    } else {   // kColFwdCirc, kColFwdCircRe: the same pruning as the lag column of kColConvLag
         if (kPruneFirst<R, P> && a.len < T)
             fft_line<R, P, E, B, kPruneEnds>(v, lds + b, t);
         else
             fft_line<R, P, E, B>(v, lds + b, t);
     }
     if (!act) return;
-    if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
+    if constexpr (MODE == kColFwdCircRe) {
+        R* out = static_cast<R*>(a.out) + o1 * a.out_os1 + o * a.out_os + w;
+#pragma unroll
+        for (int m = 0; m < E; ++m) out[(t + T * m) * a.out_ps] = v[m].re;
+    } else if constexpr (MODE == kColFwdPrefix || MODE == kColFwdCirc) {
         C* out = static_cast<C*>(a.out) + o1 * a.out_os1 + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < E; ++m) out[(t + T * m) * a.out_ps] = v[m];
-    } else {   // kColConvLag (in place) and kColInvPrefix: keep [0, mout)
+    } else {   // kColConvLag, kColConvSpec (in place) and kColInvPrefix: keep [0, mout)
         C* out = static_cast<C*>(a.out) + o1 * a.out_os1 + o * a.out_os + w;
 #pragma unroll
         for (int m = 0; m < E; ++m) {

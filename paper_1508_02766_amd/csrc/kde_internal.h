@@ -161,6 +161,9 @@ struct C2RArgs {
 enum ColMode : int {
     kColFwdPrefix = 0,      // forward FFT of rows [0, len), zero padded; store all P
     kColFwdCirc = 1,        // forward FFT of a circularly placed lag axis (L = len); store all P
+    kColFwdCircRe = 2,      // as kColFwdCirc, storing the real parts only (out holds reals)
+    kColConvSpec = 3,       // forward FFT of [0, len), times the stored real spectrum line
+                            // (kt holds reals), inverse, keep [0, mout)
     kColInvPrefix = 4,      // inverse FFT of all P; keep [0, mout)
     kColConvLag = 5,        // forward FFT of [0, len), times the real spectrum line, inverse,
                             // keep [0, mout); the spectrum line is the FFT of the circularly
@@ -182,7 +185,8 @@ struct ColArgs {
     int64_t in_os1, out_os1, kt_os1;   // strides of o1 (two-level outer index)
     int len;                // nonzero input prefix length, or L for circular inputs
     int mout;               // kept output prefix length
-    const void* kt;         // kColConvLag: lag columns transformed along the other axes
+    const void* kt;         // kColConvLag: lag columns transformed along the other axes;
+                            // kColConvSpec: the real spectrum
     int64_t kt_os, kt_ps;   // their outer and element strides (line stride is 1)
     int kt_len;             // their half width L (2 L + 1 entries per column)
 };

@@ -56,6 +56,7 @@ class KdeGrid(ctypes.Structure):
 class KdeParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * MAX_D), ("Q", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * MAX_D), ("extent", ctypes.c_int32), ("reuse_spectrum", ctypes.c_int32),
+                ("store_spectrum", ctypes.c_int32),
                 ("trace_capacity", ctypes.c_int32),
                 ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
                 ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
@@ -176,11 +177,14 @@ def _grid_shape(g: KdeGrid):
     return tuple(int(g.M[k]) for k in range(g.d))
 
 
-def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, reuse_spectrum=None, trace_events=None,
+def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, reuse_spectrum=None, store_spectrum=None,
+            trace_events=None,
             trace=None):
     p = KdeParams()
     if reuse_spectrum:
         p.reuse_spectrum = 1
+    if store_spectrum:
+        p.store_spectrum = 1
     if extent is not None:
         p.extent = {"eigen": 0, "marginal": 1}.get(extent, extent)
     if tile is not None:
@@ -281,7 +285,7 @@ def kde_plan_query(H, n: int, grid, **opts) -> dict:
     }
 
 
-_PLAN_OPTS = ("prec", "tau", "L", "Q", "tile", "extent")
+_PLAN_OPTS = ("prec", "tau", "L", "Q", "tile", "extent", "store_spectrum")
 
 
 def _workspace(nbytes: int, device, ws=None) -> torch.Tensor:

@@ -104,6 +104,40 @@ def test_plan_overrides_and_precision():
     assert p["L"] == O.truncation_L(w.H, O.bin_width(w.lo, w.hi, w.M), w.M, 2.0)
 
 
+@pytest.mark.parametrize("d,M", [(2, (80, 60)), (3, (20, 24, 18)), (4, (10, 12, 8, 9))])
+def test_plan_stored_spectrum_workspace(d, M):
+    """A stored spectrum adds P_1 .. P_(d-1) x pitch(P_d) reals (pitch: P/2 + 1 rounded up to 16)
+    of the precision to the convolution workspace and changes nothing else of the plan."""
+    w = W.small_mixture(400 + d, d, 5_000, M)
+    g = (w.lo, w.hi, w.M)
+    for prec, rs in (("f32", 4), ("f64", 8)):
+        a = K.kde_plan_query(w.H, w.n, g, prec=prec)
+        b = K.kde_plan_query(w.H, w.n, g, prec=prec, store_spectrum=True)
+        pitch = (a["P"][-1] // 2 + 1 + 15) // 16 * 16
+        extra = int(np.prod(a["P"][:-1])) * pitch * rs
+        assert b["conv_ws_bytes"] - a["conv_ws_bytes"] == (extra + 255) // 256 * 256
+        assert b["eval_ws_bytes"] - a["eval_ws_bytes"] == b["conv_ws_bytes"] - a["conv_ws_bytes"]
+        assert a["L"] == b["L"] and a["P"] == b["P"] and a["bin_ws_bytes"] == b["bin_ws_bytes"]
+    one = W.small_mixture(410, 1, 5_000, (300,))
+    g1 = (one.lo, one.hi, one.M)
+    assert K.kde_plan_query(one.H, one.n, g1, store_spectrum=True) == K.kde_plan_query(one.H, one.n, g1)
+
+
+def test_stored_spectrum_rejections():
+    """store_spectrum takes 0 or 1, and batches refuse it."""
+    H = np.array([[0.09, 0.06], [0.06, 0.08]])
+    good = ([-1.0, -1.0], [1.0, 1.0], [32, 32])
+    p = KB.KdeParams()
+    p.store_spectrum = 2
+    out = KB.KdePlan()
+    Hc = (ctypes.c_double * 4)(*H.ravel())
+    assert K.lib().kde_plan_query(Hc, 10, ctypes.byref(K.make_grid(*good)), ctypes.byref(p), ctypes.byref(out)) == -1
+    ok = _batch_items([(1000, H.tolist(), ((-3, -3), (3, 3), (64, 64)))])
+    q = KB.KdeParams()
+    q.store_spectrum = 1
+    assert _batch_info(ok, q)[0] == -1
+
+
 def _code(H, n, grid, **opts):
     try:
         K.kde_plan_query(H, n, grid, **opts)

@@ -302,6 +302,39 @@ def test_reused_spectrum_matches_full_call(name, M):
     assert torch.equal(reused, full)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("d,M", [(2, (300, 200)), (2, (512, 512)), (3, (48, 40, 36)), (3, (128, 128, 128)),
+                                 (4, (16, 20, 12, 18))])
+def test_stored_spectrum_matches_default(prec, d, M):
+    """Storing the real spectrum on the padded grid (one more spectrum pass; the product pass
+    reads it instead of transforming the lag columns) gives the default path's bits: for a full
+    estimate, for a stored spectrum reused on new samples, and for kde_conv."""
+    w = W.small_mixture(500 + d, d, 60_000, M, ratio=(1.0, 20.0))
+    w2 = W.small_mixture(520 + d, d, 60_000, M, ratio=(1.0, 20.0))
+    g = (w.lo, w.hi, w.M)
+    X, X2 = _dev(w.X), _dev(w2.X)
+    plan = K.kde_plan_query(w.H, w.n, g, prec=prec, store_spectrum=True)
+    ws = torch.empty(plan["eval_ws_bytes"], dtype=torch.uint8, device=DEV)
+    ref = K.kde_eval(X, w.H, g, prec=prec)[0]
+    got = K.kde_eval(X, w.H, g, prec=prec, ws=ws, store_spectrum=True)[0]
+    reused = K.kde_eval(X2, w.H, g, prec=prec, ws=ws, store_spectrum=True, reuse_spectrum=True)[0]
+    full2 = K.kde_eval(X2, w.H, g, prec=prec)[0]
+    counts, _ = K.kde_bin(X, g)
+    conv = K.kde_conv(counts, w.n, w.H, g, prec=prec, store_spectrum=True)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(reused, full2)
+    assert torch.equal(conv, ref)
+    if d <= 3 and max(M) <= 300:
+        lscv_s = K.kde_lscv(counts, w.n, w.H, g, prec=prec, store_spectrum=True)
+        lscv_d = K.kde_lscv(counts, w.n, w.H, g, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(lscv_s, lscv_d)
+    if int(np.prod(M)) <= 200_000:
+        f, _ = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+        assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
 @pytest.fixture(scope="module")
 def ref2d512():
     w = W.mix2d_512()
