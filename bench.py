@@ -269,6 +269,35 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     g1 = time.perf_counter()
     del graph
+
+    def traced(ws_, nsteps=steps, flush=None, **o):
+        """nsteps steps with every kernel stamping an event pair with its own dispatch start and
+        end (hipExtLaunchKernel); tracing keeps all kernels in order on one stream. With `flush`,
+        a 512 MiB write before each step evicts the last-level cache (cold kernels)."""
+        events = [[hip.event() for _ in range(cap)] for _ in range(nsteps)]
+        calls = [K.prepare_eval(X, w.H, grid, out, ws_, nd, prec=prec, trace_events=events[s], **o)
+                 for s in range(nsteps)]
+        torch.cuda.synchronize()
+        u0 = time.perf_counter()
+        for c in calls:
+            if flush is not None:
+                flush.fill_(1)
+            c()
+        torch.cuda.synchronize()
+        u1 = time.perf_counter()
+        per = {}
+        names = None
+        for s in range(nsteps):
+            tr = calls[s].trace()
+            names = tr["names"]
+            for i, nm in enumerate(names):
+                per.setdefault(nm, []).append(hip.elapsed_ms(events[s][2 * i], events[s][2 * i + 1]))
+        gpu_ms = float(np.mean([hip.elapsed_ms(events[s][0], events[s][2 * len(names) - 1]) for s in range(nsteps)]))
+        for row in events:
+            for e in row:
+                hip.destroy(e)
+        return names, {nm: float(np.mean(per[nm])) * 1e3 for nm in names}, gpu_ms, (u1 - u0) * 1e3 / nsteps
+
     # cold steps: a 512 MiB write before each step evicts the last-level cache, so the
     # step reads its inputs from HBM; each step is bracketed by events on the stream
     flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
@@ -281,32 +310,18 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         e1.record()
         e1.synchronize()
         cold.append(e0.elapsed_time(e1))
+    _, cold_us, _, _ = traced(ws, nsteps=10, flush=flush)
     del flush
-    def traced(ws_, **o):
-        """K steps with every kernel stamping an event pair with its own dispatch start and
-        end (hipExtLaunchKernel); tracing keeps all kernels in order on one stream."""
-        events = [[hip.event() for _ in range(cap)] for _ in range(steps)]
-        calls = [K.prepare_eval(X, w.H, grid, out, ws_, nd, prec=prec, trace_events=events[s], **o)
-                 for s in range(steps)]
-        torch.cuda.synchronize()
-        u0 = time.perf_counter()
-        for c in calls:
-            c()
-        torch.cuda.synchronize()
-        u1 = time.perf_counter()
-        per = {}
-        names = None
-        for s in range(steps):
-            tr = calls[s].trace()
-            names = tr["names"]
-            for i, nm in enumerate(names):
-                per.setdefault(nm, []).append(hip.elapsed_ms(events[s][2 * i], events[s][2 * i + 1]))
-        gpu_ms = float(np.mean([hip.elapsed_ms(events[s][0], events[s][2 * len(names) - 1]) for s in range(steps)]))
-        for row in events:
-            for e in row:
-                hip.destroy(e)
-        return names, {nm: float(np.mean(per[nm])) * 1e3 for nm in names}, gpu_ms, (u1 - u0) * 1e3 / steps
-
+    # warm steps one by one, each bracketed by events on the stream (median of 50)
+    ev = []
+    for _ in range(50):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plain()
+        e1.record()
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    ev_ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
     names, per_us, gpu_step_ms, ms_traced = traced(ws)
     # serving with the spectrum stored on the padded grid: after one full call, the product
     # pass reads the stored real spectrum instead of transforming each line's lag column
@@ -327,11 +342,16 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     for nm in names:
         us = per_us[nm]
         b = kernel_bytes(nm, w, plan, prec)
+        uc = cold_us.get(nm)
         kern[nm] = {"us": round(us, 3), "alg_bytes": int(b["alg"]), "alg_GBs": round(b["alg"] / (us * 1e-6) / 1e9, 1),
+                    "alg_frac": round(b["alg"] / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                    "us_cold": round(uc, 3) if uc else None,
+                    "alg_frac_cold": round(b["alg"] / (uc * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if uc else None,
                     "design_bytes": int(b["design"])}
         hbm = measured_traffic(name, nm) if prec == "f32" else None
         if hbm is not None:
             kern[nm]["hbm_bytes"] = hbm
+            kern[nm]["hbm_frac"] = round(hbm / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     conv_names = [k for k in names if k in CONV_KERNELS]
     bin_names = [k for k in names if k not in CONV_KERNELS and k not in SPEC_KERNELS]
     conv_us = sum(kern[k]["us"] for k in conv_names)
@@ -341,6 +361,12 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     bin_alg = w.n * w.d * 8 + cells * 8
     steps_roof = {"binning": step_roofline(kern, bin_names, bin_alg),
                   "fft_convolution": step_roofline(kern, conv_names, conv_alg)}
+    cold_kern = {k: {"us": v["us_cold"]} for k, v in kern.items() if v["us_cold"]}
+    for key, nm_, alg in (("binning", bin_names, bin_alg), ("fft_convolution", conv_names, conv_alg)):
+        c = step_roofline(cold_kern, nm_, alg)
+        if steps_roof[key] and c:
+            steps_roof[key]["us_cold"] = c["us"]
+            steps_roof[key]["frac_cold"] = c["frac"]
     if w.d >= 2:
         # the same chain reading the stored spectrum (serving a fixed H): the method's bytes as
         # above; the stored spectrum read, prod P_k / P_d x pitch reals, is design traffic
@@ -359,6 +385,7 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
         "workload": name, "prec": prec, "n": w.n, "M": list(w.M), "L": list(plan["L"]), "P": list(plan["P"]),
         "ms_per_step": ms_step, "ms_per_step_traced": ms_traced, "gpu_ms_per_step_traced": gpu_step_ms,
         "ms_per_step_cold": float(np.median(cold)), "ms_per_step_graph": (g1 - g0) * 1e3 / steps,
+        "ms_per_step_event_median": ev_ms,
         "ms_per_step_reused_spectrum": (r1 - r0) * 1e3 / steps,
         "ms_per_step_stored_spectrum": (s1 - s0) * 1e3 / steps,
         "samples_per_s": w.n / (ms_step * 1e-3), "grid_pts_per_s": cells / (ms_step * 1e-3),
@@ -481,25 +508,32 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(W, name: str, reps: int):
+def cpu_baseline(W, name: str, reps: int, gpu_density=None):
     """The FP64 oracle on the host, over the same workload, in three legs: (i) the direct
     Eq. (7) sum (the oracle's primary result; `value`), single thread; (ii) the oracle's
     FFT form with NumPy's single-threaded FFT; (iii) the same FFT form through
     scipy.fft with one worker per host core. Each leg includes the oracle's binning and
-    lag weights."""
+    lag weights. `gpu_density` ({precision: host array}) is compared with leg (i)'s result:
+    max |gpu - oracle| / max |oracle| per precision."""
     import oracle as O
     w = W.WORKLOADS[name]()
     ncpu = os.cpu_count() or 1
+    last = {}
 
     def leg(method, workers, r):
         ts = []
         for _ in range(r):
             t0 = time.perf_counter()
-            O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method=method, workers=workers)
+            last[method] = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method=method, workers=workers)[0]
             ts.append(time.perf_counter() - t0)
         return float(np.median(ts))
 
     t_direct = leg("direct", None, reps)
+    acc = None
+    if gpu_density:
+        ref = last["direct"]
+        acc = {p: float(np.max(np.abs(np.asarray(f, dtype=np.float64) - ref)) / float(np.max(np.abs(ref))))
+               for p, f in gpu_density.items()}
     fft_reps = max(1, reps // 3)
     t_fft = leg("fft", None, fft_reps)
     t_fft_mt = leg("fft", ncpu, fft_reps)
@@ -513,6 +547,7 @@ def cpu_baseline(W, name: str, reps: int):
     }
     return {"value": round(w.n / t_direct, 1), "unit": "samples/s", "cores": 1, "kind": "oracle",
             "host_cpu": _cpu_model(), "host_cpu_count": ncpu, "legs": legs,
+            "max_err_rel_vs_oracle": acc,
             "sample": f"{reps} full FP64 oracle passes over the {name} workload (n={w.n}, grid "
                       f"{'x'.join(map(str, w.M))}): fixed-point binning, lag weights, direct Eq. (7); median "
                       f"{t_direct:.2f} s per pass on one thread (value); beside it the oracle's FFT form "
@@ -542,7 +577,8 @@ def main():
                 continue
             v = measure(K, W, hip, name, prec, max(20, a.steps // 4), 5)
             variants[f"{name}_{prec}"] = {k: v[k] for k in ("ms_per_step", "ms_per_step_traced", "ms_per_step_cold",
-                                                            "ms_per_step_graph", "ms_per_step_reused_spectrum",
+                                                            "ms_per_step_graph", "ms_per_step_event_median",
+                                                            "ms_per_step_reused_spectrum",
                                                             "ms_per_step_stored_spectrum", "samples_per_s",
                                                             "grid_pts_per_s", "conv_us", "conv_grid_pts_per_s",
                                                             "bin_us", "bin_samples_per_s", "kernels", "steps")}
@@ -572,7 +608,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cpu = None if a.no_cpu else cpu_baseline(W, a.workload, a.cpu_reps)
+    cpu = None
+    if not a.no_cpu:
+        # the workload's density in both precisions, for the oracle comparison
+        w = W.WORKLOADS[a.workload]()
+        Xd = torch.as_tensor(w.X, device="cuda:0")
+        dens = {p: K.kde_eval(Xd, w.H, (w.lo, w.hi, w.M), prec=p)[0].cpu().numpy() for p in ("f32", "f64")}
+        del Xd
+        cpu = cpu_baseline(W, a.workload, a.cpu_reps, dens)
     line = {
         "metric": "samples/s and grid pts/s for 2-D 512^2 / 3-D 128^3 KDE, FP32 vs FP64, % HBM peak",
         "value": round(main_run["samples_per_s"], 1), "unit": "samples/s", "n_gpus": 1, "steps": a.steps,
@@ -586,11 +629,15 @@ def main():
         "ms_per_step_traced": round(main_run["ms_per_step_traced"], 5),
         "ms_per_step_cold": round(main_run["ms_per_step_cold"], 5),
         "ms_per_step_graph": round(main_run["ms_per_step_graph"], 5),
+        "ms_per_step_event_median": round(main_run["ms_per_step_event_median"], 5),
         "ms_per_step_reused_spectrum": round(main_run["ms_per_step_reused_spectrum"], 5),
         "ms_per_step_stored_spectrum": round(main_run["ms_per_step_stored_spectrum"], 5),
         "gpu_ms_per_step_traced": round(main_run["gpu_ms_per_step_traced"], 5),
         "kernels": kern, "roofline": roof, "cpu_baseline": cpu, "variants": variants,
     }
+    if cpu and cpu.get("max_err_rel_vs_oracle"):
+        # max |density - oracle's direct Eq. (7)| / max |oracle| over the whole grid, both precisions
+        line["max_err_rel_vs_oracle"] = cpu["max_err_rel_vs_oracle"]
     # the same workload with FP64 transforms (the precision the paper computes in), beside the headline
     f64 = variants.get(f"{a.workload}_f64")
     if a.prec == "f32" and f64:
