@@ -61,3 +61,22 @@ def test_noalloc_matches_eval_on_shrinking_calls(prec):
         torch.cuda.synchronize()
         assert torch.equal(out, ref), (w.d, w.M)
         assert int(nd.cpu()[0]) == int(rnd.cpu()[0])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_noalloc_stored_spectrum(prec):
+    """With the real spectrum stored in the scratch (store_spectrum), the density is
+    kde_eval's default one, bit for bit."""
+    dt = torch.float32 if prec == "f32" else torch.float64
+    for w in (W.mix3d_128(n=100_000, M=48), W.mix2d_512(n=100_000, M=256)):
+        g = (w.lo, w.hi, w.M)
+        X = torch.as_tensor(w.X, device=DEV)
+        out = torch.full(w.M, -1.0, dtype=dt, device=DEV)
+        nd = torch.full((1,), 7, dtype=torch.uint64, device=DEV)
+        print(f"kde_eval_noalloc store_spectrum d={w.d} M={w.M} {prec}", flush=True)
+        K.kde_eval_noalloc(X, w.H, g, out, nd, prec=prec, store_spectrum=True)
+        ref, rnd = K.kde_eval(X, w.H, g, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (w.d, w.M)
+        assert int(nd.cpu()[0]) == int(rnd.cpu()[0])
