@@ -361,6 +361,15 @@ def measure(K, W, hip, name: str, prec: str, steps: int, warmup: int):
     bin_alg = w.n * w.d * 8 + cells * 8
     steps_roof = {"binning": step_roofline(kern, bin_names, bin_alg),
                   "fft_convolution": step_roofline(kern, conv_names, conv_alg)}
+    # 3-D and 4-D plans pad to 3 x 2^j where shorter: beside the method bytes at the plan's
+    # lengths, the same formula at the power-of-two lengths (the layout before that choice)
+    pow2 = [max(16, 1 << (int(m) + int(l) - 1).bit_length()) for m, l in zip(w.M, plan["L"])]
+    if steps_roof["fft_convolution"] and list(plan["P"]) != pow2:
+        b2 = sum(conv_method_bytes(w.d, w.M, pow2, prec).values())
+        c = steps_roof["fft_convolution"]
+        c["pow2_P"] = pow2
+        c["pow2_alg_bytes"] = int(b2)
+        c["frac_on_pow2_alg_bytes"] = round(b2 / (c["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
     cold_kern = {k: {"us": v["us_cold"]} for k, v in kern.items() if v["us_cold"]}
     for key, nm_, alg in (("binning", bin_names, bin_alg), ("fft_convolution", conv_names, conv_alg)):
         c = step_roofline(cold_kern, nm_, alg)

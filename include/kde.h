@@ -128,8 +128,9 @@ typedef struct kde_plan {
     int32_t prec;
     int32_t L[KDE_MAX_D];     /* truncation per axis: Eq. (15), the marginal extent, or the
                                  override */
-    int32_t P[KDE_MAX_D];     /* padded FFT length per axis: smallest power of two
-                                 >= max(16, M_k + L_k) */
+    int32_t P[KDE_MAX_D];     /* padded FFT length per axis (highly composite, Section
+                                 4.1): the smallest 2^j >= max(16, M_k + L_k); for d >= 3
+                                 the smallest 3 x 2^j >= 48 instead when that is shorter */
     int32_t reserved;
     double delta[KDE_MAX_D];  /* bin width, Eq. (4) */
     double lambda_max;        /* largest eigenvalue of H */

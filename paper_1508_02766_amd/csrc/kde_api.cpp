@@ -7,7 +7,8 @@
 //   lambda_max(H): closed form for d <= 2, cyclic Jacobi for d >= 3
 //   L_k = min(M_k - 1, ceil(tau sqrt(lambda_max) / delta_k))  Eq. (15)
 //         (or tau sqrt(H_kk) with kde_params.extent = 1)
-//   P_k = smallest power of two >= max(16, M_k + L_k)          zero padding, Section 4.1
+//   P_k = smallest 2^j >= max(16, M_k + L_k), or for d >= 3 the  zero padding, Section 4.1
+//         smallest 3 x 2^j >= 48 when that is shorter            (highly composite lengths)
 //   k_0 = n^-1 (2 pi)^-d/2 |H|^-1/2                            Eq. (6) with Eq. (1)
 //
 // The lag box is placed circularly (lag l at l mod P_k, the true negative
@@ -317,9 +318,15 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
             L = static_cast<int>(x < cap ? x : cap);
         }
         p.L[k] = L;
+        // the shortest highly composite length (Section 4.1) that holds the window and the
+        // lags of the circular layout: 2^k, or in 3-D and 4-D 3 x 2^k when that is shorter.
+        // There every pass has thousands of lines and is bound by its bytes and arithmetic;
+        // in 1-D and 2-D the few long lines are latency-bound, and the 12 points per thread
+        // of a 3 x 2^k line would leave most of the GPU idle (512^2: 45 -> 52 us per step)
         int64_t P = kde::kMinP;
         while (P < g->M[k] + L) P *= 2;
         if (P > kde::kMaxP) return KDE_ERR_SIZE;
+        if (d >= 3 && P >= 64 && 3 * (P / 4) >= g->M[k] + L) P = 3 * (P / 4);
         p.P[k] = static_cast<int32_t>(P);
         lag_count *= 2 * L + 1;
     }

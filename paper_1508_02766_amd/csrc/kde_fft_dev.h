@@ -1,6 +1,6 @@
 // Device building blocks of the FFT convolution kernels: complex arithmetic,
-// the compile-time twiddle table, the radix-16/8/4/2 Stockham line transform
-// in LDS, and the bodies of the row (contiguous axis) and column (strided
+// the compile-time twiddle tables, the Stockham line transform in LDS (lengths
+// 2^k with radix-16/8/4/2 stages, 3 x 2^k with a radix-12 stage first), and the bodies of the row (contiguous axis) and column (strided
 // axis) passes. Included by the single-instance launchers (kde_fft.hip) and
 // the batched ones (kde_fft_batch.hip), so both run the same device code.
 #pragma once
@@ -121,6 +121,53 @@ __device__ __forceinline__ cpx<float> twiddle<float>(int k) { return g_tw32.w[k]
 template <>
 __device__ __forceinline__ cpx<double> twiddle<double>(int k) { return g_tw64.w[k]; }
 
+// exp(-2 pi i k / 3072), k = 0..3071: the twiddles of the lengths 3 x 2^k
+template <typename R>
+struct TwiddleTable3 {
+    cpx<R> w[kMaxP3];
+};
+
+template <typename R>
+constexpr TwiddleTable3<R> make_twiddles3() {
+    TwiddleTable3<R> t{};
+    for (int k = 0; k < kMaxP3; ++k) {
+        const SinCos v = sincos_turn(k, kMaxP3);
+        t.w[k] = cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
+    }
+    return t;
+}
+
+__device__ constexpr TwiddleTable3<float> g_tw32_3 = make_twiddles3<float>();
+__device__ constexpr TwiddleTable3<double> g_tw64_3 = make_twiddles3<double>();
+
+template <typename R>
+__device__ __forceinline__ cpx<R> twiddle3(int k);
+template <>
+__device__ __forceinline__ cpx<float> twiddle3<float>(int k) { return g_tw32_3.w[k]; }
+template <>
+__device__ __forceinline__ cpx<double> twiddle3<double>(int k) { return g_tw64_3.w[k]; }
+
+// Line lengths 3 x 2^k (a radix-12 first stage, then radix 4 and 2).
+__host__ __device__ constexpr bool is_tri(int P) { return P % 3 == 0; }
+
+// multiply by the compile-time constant exp(-2 pi i m / 12)
+template <int m, typename R>
+__device__ __forceinline__ cpx<R> rot12(cpx<R> a) {
+    constexpr int mm = ((m % 12) + 12) % 12;
+    if constexpr (mm == 0) {
+        return a;
+    } else if constexpr (mm == 3) {
+        return mul_minus_i(a);
+    } else if constexpr (mm == 6) {
+        return cpx<R>{-a.re, -a.im};
+    } else if constexpr (mm == 9) {
+        return cpx<R>{-a.im, a.re};
+    } else {
+        constexpr SinCos v = sincos_turn(2 * mm, 24);
+        return a * cpx<R>{static_cast<R>(v.c), static_cast<R>(-v.s)};
+    }
+}
+
 // multiply by the compile-time constant exp(-2 pi i m / 16)
 template <int m, typename R>
 __device__ __forceinline__ cpx<R> rot16(cpx<R> a) {
@@ -150,6 +197,18 @@ __device__ __forceinline__ void dft4(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>&
     a2 = t0 - t2;
     a1 = t1 + t3;
     a3 = t1 - t3;
+}
+
+// length-3 DFT: X_1,2 = a0 - (a1 + a2)/2 -/+ i sin(2 pi/3) (a1 - a2)
+template <typename R>
+__device__ __forceinline__ void dft3(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2) {
+    constexpr R h = static_cast<R>(sincos_turn(8, 24).s);   // sin(2 pi / 3)
+    const cpx<R> s = a1 + a2, d = a1 - a2;
+    const cpx<R> m{fmaR(R(-0.5), s.re, a0.re), fmaR(R(-0.5), s.im, a0.im)};
+    const cpx<R> r{d.im * h, -(d.re * h)};   // -i sin(2 pi/3) (a1 - a2)
+    a0 = a0 + s;
+    a1 = m + r;
+    a2 = m - r;
 }
 
 template <int RAD, typename R>
@@ -200,6 +259,31 @@ __device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
             for (int k2 = 0; k2 < 4; ++k2) y[k1 + 4 * k2] = a[4 * k1 + k2];
 #pragma unroll
         for (int i = 0; i < 16; ++i) a[i] = y[i];
+    } else if constexpr (RAD == 12) {
+        // 12 = 4 x 3: length-4 DFTs over n1 (input n = 3 n1 + n2), twiddle
+        // exp(-2 pi i n2 k1 / 12), length-3 DFTs over n2; output k = k1 + 4 k2.
+        dft4(a[0], a[3], a[6], a[9]);
+        dft4(a[1], a[4], a[7], a[10]);
+        dft4(a[2], a[5], a[8], a[11]);
+        // a[n2 + 3 k1] now holds the inner result for (n2, k1)
+        a[4] = rot12<1>(a[4]);
+        a[5] = rot12<2>(a[5]);
+        a[7] = rot12<2>(a[7]);
+        a[8] = rot12<4>(a[8]);
+        a[10] = rot12<3>(a[10]);
+        a[11] = rot12<6>(a[11]);
+        dft3(a[0], a[1], a[2]);
+        dft3(a[3], a[4], a[5]);
+        dft3(a[6], a[7], a[8]);
+        dft3(a[9], a[10], a[11]);
+        // a[3 k1 + k2] holds output k1 + 4 k2
+        cpx<R> y[12];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) y[k1 + 4 * k2] = a[3 * k1 + k2];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a[i] = y[i];
     }
 }
 
@@ -216,7 +300,7 @@ enum Prune : int { kPruneNone = 0, kPruneHalf = 1, kPruneEnds = 2 };
 // 26.9 us at 128^3); in FP64 the extra registers cost occupancy (the same pass
 // 42.7 -> 62.7 us), and the latency-bound P = 1024 passes got slower by 0.4 us.
 template <typename R, int P>
-constexpr bool kPruneFirst = sizeof(R) == 4 && P <= 256;
+constexpr bool kPruneFirst = sizeof(R) == 4 && P <= 256 && !is_tri(P);
 
 template <typename R>
 __device__ __forceinline__ void dft4_half(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cpx<R>& a3) {   // a2 = a3 = 0
@@ -247,7 +331,7 @@ __device__ __forceinline__ void dft4_last(cpx<R>& a0, cpx<R>& a1, cpx<R>& a2, cp
 
 template <int RAD, int PR, typename R>
 __device__ __forceinline__ void dft_first(cpx<R> (&a)[RAD]) {
-    if constexpr (PR == kPruneNone || RAD == 2) {
+    if constexpr (PR == kPruneNone || RAD == 2 || RAD == 12) {
         dft<RAD>(a);
     } else if constexpr (RAD == 4) {
         if constexpr (PR == kPruneHalf) dft4_half(a[0], a[1], a[2], a[3]);
@@ -327,20 +411,34 @@ __device__ __forceinline__ int padi(int p) { return p + (p >> 4); }
 // per axis of a grid), so they spread over more threads: at P = 512 and 1024
 // the forward row pass of the counts (the first pass after binning, alone on
 // the GPU) uses 4 points per thread, the other row passes and the column
-// passes 8; beyond, the fewest that keep a line within 256 threads. A function
-// of P and the pass alone: every launch shape of a pass rounds identically.
+// passes 8; beyond, the fewest that keep a line within 256 threads. Lengths
+// 3 x 2^k take 12 (a radix-12 stage, then radix 4 and 2). A function of P and
+// the pass alone: every launch shape of a pass rounds identically.
 enum RowPass : int { kRowPassCounts = 0, kRowPassSpec = 1, kRowPassInv = 2 };
 __host__ __device__ constexpr int row_points(int P, int pass) {
-    return P <= 256 ? 16 : (P <= 1024 ? (pass == kRowPassCounts ? 4 : 8) : P / 256);
+    return is_tri(P) ? 12 : (P <= 256 ? 16 : (P <= 1024 ? (pass == kRowPassCounts ? 4 : 8) : P / 256));
 }
 __host__ __device__ constexpr int row_pass_of(int in_kind) {
     return in_kind == kRowCountsU64 ? kRowPassCounts : kRowPassSpec;
 }
-__host__ __device__ constexpr int col_points(int P) { return P <= 256 ? 16 : (P <= 1024 ? 8 : P / 256); }
+__host__ __device__ constexpr int col_points(int P) {
+    return is_tri(P) ? 12 : (P <= 256 ? 16 : (P <= 1024 ? 8 : P / 256));
+}
 
-// Radix of the stage that follows the stages with product NS.
+// Radix of the stage that follows the stages with product NS (3 x 2^k: 12
+// first, then 4 while at least 4 remain, then 2).
 template <int P, int E, int NS>
-constexpr int stage_radix() { return (P / NS) < E ? P / NS : E; }
+constexpr int stage_radix() {
+    if constexpr (is_tri(P)) return NS == 1 ? 12 : ((P / NS) >= 4 ? 4 : 2);
+    else return (P / NS) < E ? P / NS : E;
+}
+
+// j mod NS (NS a power of two, or 3 x 2^k past the first stage)
+template <int NS>
+__device__ __forceinline__ int mod_ns(int j) {
+    if constexpr ((NS & (NS - 1)) == 0) return j & (NS - 1);
+    else return j % NS;
+}
 
 // The twiddles one thread uses in the stages with product NS and after,
 // loaded together at the start of the transform so their latency overlaps the
@@ -361,9 +459,14 @@ __device__ __forceinline__ void load_twiddles(StageTwiddles<R, P, E, NS>& tw, in
         constexpr int T = P / E, RAD = stage_radix<P, E, NS>(), NB = E / RAD;
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            const int jm = (t + T * u) & (NS - 1);
+            const int jm = mod_ns<NS>(t + T * u);
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) tw.w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+            for (int r = 1; r < RAD; ++r) {
+                if constexpr (is_tri(P))
+                    tw.w[u * (RAD - 1) + r - 1] = twiddle3<R>(r * jm * (kMaxP3 / (NS * RAD)));
+                else
+                    tw.w[u * (RAD - 1) + r - 1] = twiddle<R>(r * jm * (kMaxP / (NS * RAD)));
+            }
         }
         load_twiddles<R, P, E, NS * RAD>(tw.next, t);
     }
@@ -404,7 +507,7 @@ __device__ __forceinline__ void fft_stage(cpx<R> (&v)[E], cpx<R>* lds, int t, co
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int j = t + T * u;
-            const int base = (j / NS) * (NS * RAD) + (j & (NS - 1));
+            const int base = (j / NS) * (NS * RAD) + mod_ns<NS>(j);
 #pragma unroll
             for (int r = 0; r < RAD; ++r) lds[padi(base + r * NS) * LS] = v[u + r * NB];
         }
@@ -426,8 +529,11 @@ __device__ __forceinline__ void fft_stages(cpx<R> (&v)[E], cpx<R>* lds, int t, c
 // PR: the zero padding of the input the first stage may skip (dft_first).
 template <typename R, int P, int E, int LS, int PR = kPruneNone>
 __device__ __forceinline__ void fft_line(cpx<R> (&v)[E], cpx<R>* lds, int t) {
-    static_assert(P >= 16 && P <= kMaxP && (P & (P - 1)) == 0, "P must be a power of two in [16, 4096]");
-    static_assert((E == 4 || E == 8 || E == 16) && E <= P, "4, 8 or 16 points per thread");
+    static_assert((P >= 16 && P <= kMaxP && (P & (P - 1)) == 0) ||
+                      (is_tri(P) && P >= 48 && P <= kMaxP3 && ((P / 3) & (P / 3 - 1)) == 0),
+                  "P must be 2^k in [16, 4096] or 3 x 2^k in [48, 3072]");
+    static_assert((E == 4 || E == 8 || E == 16 || (E == 12 && is_tri(P))) && E <= P,
+                  "4, 8 or 16 points per thread (12 for 3 x 2^k)");
     StageTwiddles<R, P, E, E> tw;
     load_twiddles<R, P, E, E>(tw, t);
     constexpr cpx<R> none[1] = {};
@@ -572,7 +678,7 @@ __device__ __forceinline__ void rows_r2c_body(const RowArgs<R>& gw, uint32_t blk
     __syncthreads();
     const R h = R(0.5);
     for (int k = t; k <= P / 2; k += T) {
-        const C zk = line[padi(k)], zn = line[padi((P - k) & (P - 1))];
+        const C zk = line[padi(k)], zn = line[padi(k == 0 ? 0 : P - k)];
         const C X{(zk.re + zn.re) * h, (zk.im - zn.im) * h};
         const C Y{(zk.im + zn.im) * h, (zn.re - zk.re) * h};
         if constexpr (OUT_REAL) {
@@ -753,7 +859,8 @@ __device__ __forceinline__ void cols_body(const ColArgs& a, uint32_t bx, uint32_
 
 __host__ __device__ constexpr int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-#define KDE_FOR_EACH_P(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+#define KDE_FOR_EACH_P(X) \
+    X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096) X(48) X(96) X(192) X(384) X(768) X(1536) X(3072)
 
 }  // namespace
 }  // namespace kde

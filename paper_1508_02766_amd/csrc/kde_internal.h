@@ -47,7 +47,8 @@ constexpr size_t kScratchBytes = size_t(256) << 20;
 hipError_t scratch_address(int dev, void** out);
 
 constexpr int kMaxD = 4;      // largest dimension
-constexpr int kMaxP = 4096;   // largest padded FFT length per axis
+constexpr int kMaxP = 4096;   // largest padded FFT length per axis (2^k)
+constexpr int kMaxP3 = 3072;  // largest padded length 3 x 2^k
 constexpr int kMinP = 16;     // smallest (one radix-16 stage)
 
 // Constants of the fixed-point binning step, prepared on the host.

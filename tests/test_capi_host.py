@@ -50,8 +50,16 @@ def test_plan_matches_oracle(name):
     k0 = O.lag_weights(w.H, op["delta"], (0,) * w.d, w.n).ravel()[0]
     assert plan["norm"] == pytest.approx(k0, rel=1e-13)
     for k in range(w.d):
-        P = plan["P"][k]
-        assert P >= w.M[k] + plan["L"][k] and P >= 16 and P & (P - 1) == 0 and P // 2 < max(16, w.M[k] + plan["L"][k])
+        assert plan["P"][k] == _padded_length(w.M[k] + plan["L"][k], w.d)
+
+
+# Padded lengths (highly composite, Section 4.1): 2^k in [16, 4096], and in 3-D and 4-D
+# also 3 x 2^k in [48, 3072].
+def _padded_length(need: int, d: int) -> int:
+    """The shortest admissible length that holds M_k + L_k (the window and the lags of
+    the circular layout)."""
+    lengths = [2 ** k for k in range(4, 13)] + ([3 * 2 ** k for k in range(4, 11)] if d >= 3 else [])
+    return min(P for P in lengths if P >= need)
 
 
 def test_plan_random_spd_matches_oracle():
@@ -66,6 +74,7 @@ def test_plan_random_spd_matches_oracle():
         plan = K.kde_plan_query(H, n, (lo, hi, M))
         op = O.plan(H, lo, hi, M, n)
         assert plan["L"] == op["L"], (trial, plan["L"], op["L"])
+        assert plan["P"] == tuple(_padded_length(m + l, d) for m, l in zip(M, plan["L"]))
         assert plan["lambda_max"] == pytest.approx(O.lambda_max(H), rel=1e-12)
 
 

@@ -49,10 +49,11 @@ def test_batch_matches_single_bit_identical(prec):
     torch.cuda.synchronize()
     _assert_matches_single(B, items, prec=prec)
     info = B.info()
-    sides = {w.M[0] for w in wl}
-    # four binning stages, then one launch per padded length for each of the
-    # four FFT passes
-    assert info["launches"] == 4 + 4 * len(sides)
+    plans = [K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M), prec=prec) for w in wl]
+    p0, p1 = {p["P"][0] for p in plans}, {p["P"][1] for p in plans}
+    # four binning stages, then one launch per padded length for each of the four FFT
+    # passes: spectrum rows, count rows and the inverse rows over P_2, the product over P_1
+    assert info["launches"] == 4 + 3 * len(p1) + len(p0)
 
 
 def test_batch_matches_oracle():

@@ -182,29 +182,42 @@ def test_kernel_grid_4d(prec):
 # --------------------------------------------------------------------------
 
 CONV_CASES = [
-    # (d, M, seed, L override, H scale)
-    (1, (200,), 1, None, 1.0),
-    (1, (2000,), 2, None, 1.0),            # P = 4096 (largest length)
-    (1, (9,), 3, None, 1.0),               # P = 16 (smallest length)
-    (2, (64, 64), 4, None, 1.0),
-    (2, (37, 50), 5, None, 1.0),           # ragged, odd row count
-    (2, (129, 300), 6, None, 3.0),
-    (2, (2050, 12), 7, None, 0.5),         # P_1 = 4096
-    (2, (1000, 40), 12, None, 0.3),        # P_1 = 2048
-    (2, (24, 19), 8, (23, 18), 1.0),       # full lag box, L = M - 1
-    (3, (20, 17, 23), 9, None, 1.0),
-    (3, (33, 40, 31), 10, None, 2.0),
-    (3, (6, 5, 4), 11, (5, 4, 3), 1.0),    # P = 16: separate row / column passes
-    (3, (24, 40, 10), 13, None, 1.0),      # P = (32, 64, 16): P_2 != P_3, separate passes
-    (2, (300, 257), 14, None, 1.0),        # P = 512 on both axes (4 / 8 points per thread)
-    (2, (520, 700), 15, None, 1.0),        # P = 1024 on both axes
-    (3, (7, 9, 300), 16, None, 1.0),       # P_3 = 512: row passes at 4 / 8 points per thread
-    (3, (300, 7, 9), 17, None, 1.0),       # P_1 = 512: product pass at 8 points per thread
-    (4, (24, 24, 24, 24), 18, None, 1.0),  # 4-D: three strided passes each way
-    (4, (20, 24, 18, 30), 19, None, 1.0),  # ragged, P_4 = 64 != P_1..3
-    (4, (6, 5, 4, 7), 20, (5, 4, 3, 6), 1.0),   # full lag box, P = 16
-    (4, (9, 12, 7, 40), 21, None, 2.0),
-    (4, (40, 6, 5, 9), 22, None, 1.0),     # P_1 = 64: the product pass on the longest axis
+    # (d, M, seed, L override, H scale); the padded lengths P in the comments: 2^k, and in
+    # 3-D and 4-D also 3 x 2^k where shorter
+    (1, (200,), 1, None, 1.0),             # 256
+    (1, (2000,), 2, None, 1.0),            # 4096 (largest length)
+    (1, (1700,), 24, None, 1.0),           # 2048
+    (1, (9,), 3, None, 1.0),               # 16 (smallest length)
+    (2, (64, 64), 4, None, 1.0),           # (128, 128)
+    (2, (37, 50), 5, None, 1.0),           # (64, 64): ragged, odd row count
+    (2, (129, 300), 6, None, 3.0),         # (256, 512)
+    (2, (2050, 12), 7, None, 0.5),         # (4096, 16)
+    (2, (1000, 40), 12, None, 0.3),        # (2048, 64)
+    (2, (40, 1700), 27, None, 0.5),        # (64, 2048): long rows
+    (2, (24, 19), 8, (23, 18), 1.0),       # (64, 64): full lag box, L = M - 1
+    (2, (230, 200), 30, None, 1.0),        # (256, 256): pruned first stages on both axes
+    (2, (300, 257), 14, None, 1.0),        # (512, 512): 4 / 8 points per thread
+    (2, (520, 700), 15, None, 1.0),        # (1024, 1024)
+    (3, (20, 17, 23), 9, None, 1.0),       # (32, 32, 32)
+    (3, (33, 40, 31), 10, None, 2.0),      # (48, 64, 48)
+    (3, (6, 5, 4), 11, (5, 4, 3), 1.0),    # 16: separate row / column passes
+    (3, (24, 40, 10), 13, None, 1.0),      # (32, 48, 16): P_2 != P_3, separate passes
+    (3, (100, 9, 7), 28, None, 1.0),       # (128, 16, 16): the product pass on the longest axis
+    (3, (70, 6, 5), 32, None, 1.0),        # (96, 16, 16)
+    (3, (210, 12, 230), 31, None, 1.0),    # (256, 16, 384): both families in one problem
+    (3, (7, 9, 300), 16, None, 1.0),       # P_3 = 384: row passes at 12 points per thread
+    (3, (300, 7, 9), 17, None, 1.0),       # P_1 = 384: product pass at 12 points per thread
+    (3, (680, 5, 4), 33, (60, 2, 2), 1.0),       # (768, 16, 16)
+    (3, (1400, 5, 4), 34, (100, 2, 2), 1.0),     # (1536, 16, 16)
+    (3, (2900, 5, 4), 35, (150, 2, 2), 1.0),     # (3072, 16, 16): largest 3 x 2^k
+    (3, (4, 5, 700), 36, (2, 2, 50), 1.0),       # (16, 16, 768): long rows
+    (3, (5, 4, 2900), 37, (2, 2, 150), 1.0),     # (16, 16, 3072)
+    (4, (24, 24, 24, 24), 18, None, 1.0),  # 32: three strided passes each way
+    (4, (20, 24, 18, 30), 19, None, 1.0),  # (32, 32, 32, 48): ragged, P_4 != P_1..3
+    (4, (6, 5, 4, 7), 20, (5, 4, 3, 6), 1.0),   # 16: full lag box
+    (4, (9, 12, 7, 40), 21, None, 2.0),    # (16, 16, 16, 64)
+    (4, (40, 6, 5, 9), 22, None, 1.0),     # (64, 16, 16, 16): the product pass on the longest axis
+    (4, (100, 6, 5, 9), 29, None, 1.0),    # (192, 16, 16, 16)
 ]
 
 
@@ -407,7 +420,7 @@ def full3d128(ref3d128):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_eval_3d_128_full_grid(ref3d128, full3d128, prec):
-    """Every one of the 2.1M cells of the 3-D estimate (P = 256 on all three axes)
+    """Every one of the 2.1M cells of the 3-D estimate (P = 192 on all three axes)
     element by element against the oracle."""
     w, p, counts, c, k = ref3d128
     got, nd = K.kde_eval(_dev(w.X), w.H, (w.lo, w.hi, w.M), prec=prec)
