@@ -296,9 +296,10 @@ __device__ __forceinline__ void dft(cpx<R> (&a)[RAD]) {
 enum Prune : int { kPruneNone = 0, kPruneHalf = 1, kPruneEnds = 2 };
 
 // Pruned first stages add a second copy of a transform to a kernel. They pay
-// where the passes are VALU-bound (FP32, P <= 256: the 3-D product pass 27.9 ->
-// 26.9 us at 128^3); in FP64 the extra registers cost occupancy (the same pass
-// 42.7 -> 62.7 us), and the latency-bound P = 1024 passes got slower by 0.4 us.
+// where the passes are VALU-bound (FP32, P <= 256: the 3-D product pass at
+// P = 256, 128^3, 27.9 -> 26.9 us); in FP64 the extra registers cost occupancy
+// (the same pass 42.7 -> 62.7 us), and the latency-bound P = 1024 passes got
+// slower by 0.4 us. Lengths 3 x 2^k run the full first stage.
 template <typename R, int P>
 constexpr bool kPruneFirst = sizeof(R) == 4 && P <= 256 && !is_tri(P);
 
