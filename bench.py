@@ -440,6 +440,18 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
         graph.replay()
     torch.cuda.synchronize()
     graph_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # the same batch with 3 x 2^k padded lengths in 2-D as well (kde_params.lengths)
+    Bc = K.KdeBatch(items, prec="f32", lengths="composite")
+    Bc.tune(reps=3)
+    for _ in range(warmup):
+        Bc.eval()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Bc.eval()
+    torch.cuda.synchronize()
+    composite_ms = (time.perf_counter() - t0) * 1e3 / steps
+    Bc.close()
     # the same problems as one kde_eval call each
     plans = [K.kde_plan_query(w.H, w.n, (w.lo, w.hi, w.M)) for w in wl]
     wss = [torch.empty(p["eval_ws_bytes"], dtype=torch.uint8, device=dev) for p in plans]
@@ -495,6 +507,7 @@ def measure_batch(K, W, hip, count: int, steps: int, warmup: int):
         "problems": count, "n_total": n_tot, "grid_pts_total": cells, "launches": info["launches"],
         "tuned_tile": list(info["tile"]), "tuned_narrow_mask": info["narrow_mask"], "tune_s": round(tune_s, 3),
         "ms_per_batch": round(eager_ms, 4), "ms_per_batch_graph": round(graph_ms, 4),
+        "ms_per_batch_composite_lengths": round(composite_ms, 4),
         "samples_per_s": round(n_tot / (best * 1e-3), 1), "grid_pts_per_s": round(cells / (best * 1e-3), 1),
         "problems_per_s": round(count / (best * 1e-3), 1),
         "ms_per_item_calls": round(loop_ms, 4), "speedup_vs_item_calls": round(loop_ms / best, 2),

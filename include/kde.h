@@ -106,6 +106,11 @@ typedef struct kde_params {
                                  transforms). The same transforms either way, so the same
                                  results; 1 pays off with reuse_spectrum (serving one H on new
                                  samples), where the spectrum pass is skipped */
+    int32_t lengths;          /* padded FFT lengths P_k (kde_plan.P): 0 (default) 2^j, or in 3-D
+                                 and 4-D 3 x 2^j when shorter; 1: 3 x 2^j also in 2-D (pays in
+                                 batches of 2-D problems, whose launches hold many lines; single
+                                 2-D problems are faster with 0); 2: 2^j only. Any value gives
+                                 the estimate of Eq. (7) up to rounding */
     int32_t trace_capacity;   /* optional per-kernel timing: number of events in
                                  trace_events, used in pairs */
     hipEvent_t* trace_events; /* if non-NULL: the i-th pass of the call (one kernel; the two
@@ -130,7 +135,8 @@ typedef struct kde_plan {
                                  override */
     int32_t P[KDE_MAX_D];     /* padded FFT length per axis (highly composite, Section
                                  4.1): the smallest 2^j >= max(16, M_k + L_k); for d >= 3
-                                 the smallest 3 x 2^j >= 48 instead when that is shorter */
+                                 the smallest 3 x 2^j >= 48 instead when that is shorter
+                                 (kde_params.lengths changes the rule) */
     int32_t reserved;
     double delta[KDE_MAX_D];  /* bin width, Eq. (4) */
     double lambda_max;        /* largest eigenvalue of H */

@@ -8,7 +8,8 @@
 //   L_k = min(M_k - 1, ceil(tau sqrt(lambda_max) / delta_k))  Eq. (15)
 //         (or tau sqrt(H_kk) with kde_params.extent = 1)
 //   P_k = smallest 2^j >= max(16, M_k + L_k), or for d >= 3 the  zero padding, Section 4.1
-//         smallest 3 x 2^j >= 48 when that is shorter            (highly composite lengths)
+//         smallest 3 x 2^j >= 48 when that is shorter            (highly composite lengths;
+//         (kde_params.lengths: 3 x 2^j also in 2-D, or 2^j only)  kde_params.lengths)
 //   k_0 = n^-1 (2 pi)^-d/2 |H|^-1/2                            Eq. (6) with Eq. (1)
 //
 // The lag box is placed circularly (lag l at l mod P_k, the true negative
@@ -192,7 +193,7 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
     double tau = kTauDefault;
     int prec = KDE_F32, Q = 32 / d;
     int Lovr[kde::kMaxD] = {}, tile[kde::kMaxD] = {};
-    int extent = 0;
+    int extent = 0, lengths = 0;
     if (prm) {
         if (std::isnan(prm->tau) || std::isinf(prm->tau)) return KDE_ERR_ARG;
         if (prm->tau > 0.0) tau = prm->tau;
@@ -219,6 +220,8 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         if (prm->extent != 0 && prm->extent != 1) return KDE_ERR_ARG;
         if (prm->reuse_spectrum != 0 && prm->reuse_spectrum != 1) return KDE_ERR_ARG;
         if (prm->store_spectrum != 0 && prm->store_spectrum != 1) return KDE_ERR_ARG;
+        if (prm->lengths < 0 || prm->lengths > 2) return KDE_ERR_ARG;
+        lengths = prm->lengths;
         out->store = prm->store_spectrum == 1 && d >= 2;
         extent = prm->extent;
         if (prm->trace_events && prm->trace_capacity < 0) return KDE_ERR_ARG;
@@ -322,11 +325,13 @@ int make_plan(const double* H, int64_t n, int64_t n_min, bool need_H, const kde_
         // lags of the circular layout: 2^k, or in 3-D and 4-D 3 x 2^k when that is shorter.
         // There every pass has thousands of lines and is bound by its bytes and arithmetic;
         // in 1-D and 2-D the few long lines are latency-bound, and the 12 points per thread
-        // of a 3 x 2^k line would leave most of the GPU idle (512^2: 45 -> 52 us per step)
+        // of a 3 x 2^k line would leave most of the GPU idle (512^2: 45 -> 52 us per step).
+        // kde_params.lengths takes 3 x 2^k in 2-D too (batches), or 2^k only.
         int64_t P = kde::kMinP;
         while (P < g->M[k] + L) P *= 2;
         if (P > kde::kMaxP) return KDE_ERR_SIZE;
-        if (d >= 3 && P >= 64 && 3 * (P / 4) >= g->M[k] + L) P = 3 * (P / 4);
+        const bool tri = lengths == 0 ? d >= 3 : lengths == 1 && d >= 2;
+        if (tri && P >= 64 && 3 * (P / 4) >= g->M[k] + L) P = 3 * (P / 4);
         p.P[k] = static_cast<int32_t>(P);
         lag_count *= 2 * L + 1;
     }

@@ -19,7 +19,9 @@ The names and semantics follow include/kde.h:
 ``prec`` ("f32" default, or "f64"), ``tau``, ``L`` (per-axis override),
 ``Q`` (fixed-point bits), ``tile`` (binning tile per axis), ``extent`` ("eigen" = Eq. 15,
 "marginal" = tau sqrt(H_kk) per axis), ``reuse_spectrum`` (the workspace holds the kernel spectrum
-of an earlier call with the same H, n, grid and options), ``trace_events`` (list of raw hipEvent_t handles
+of an earlier call with the same H, n, grid and options), ``store_spectrum`` (keep the whole real
+spectrum for the product pass), ``lengths`` ("auto", "composite": 3 x 2^k also in 2-D, "pow2"),
+``trace_events`` (list of raw hipEvent_t handles
 as ints, used in pairs: pass i stamps events 2i and 2i + 1 with its kernel's start and end) with
 ``trace`` (a dict that receives ``count``, the number of passes stamped, and their ``names``).
 """
@@ -56,7 +58,7 @@ class KdeGrid(ctypes.Structure):
 class KdeParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("L", ctypes.c_int32 * MAX_D), ("Q", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("tile", ctypes.c_int32 * MAX_D), ("extent", ctypes.c_int32), ("reuse_spectrum", ctypes.c_int32),
-                ("store_spectrum", ctypes.c_int32),
+                ("store_spectrum", ctypes.c_int32), ("lengths", ctypes.c_int32),
                 ("trace_capacity", ctypes.c_int32),
                 ("trace_events", ctypes.POINTER(ctypes.c_void_p)), ("trace_count", ctypes.POINTER(ctypes.c_int32)),
                 ("trace_names", ctypes.POINTER(ctypes.c_char_p))]
@@ -178,13 +180,15 @@ def _grid_shape(g: KdeGrid):
 
 
 def _params(prec=None, tau=None, L=None, Q=None, tile=None, extent=None, reuse_spectrum=None, store_spectrum=None,
-            trace_events=None,
+            lengths=None, trace_events=None,
             trace=None):
     p = KdeParams()
     if reuse_spectrum:
         p.reuse_spectrum = 1
     if store_spectrum:
         p.store_spectrum = 1
+    if lengths is not None:
+        p.lengths = {"auto": 0, "composite": 1, "pow2": 2}.get(lengths, lengths)
     if extent is not None:
         p.extent = {"eigen": 0, "marginal": 1}.get(extent, extent)
     if tile is not None:
@@ -285,7 +289,7 @@ def kde_plan_query(H, n: int, grid, **opts) -> dict:
     }
 
 
-_PLAN_OPTS = ("prec", "tau", "L", "Q", "tile", "extent", "store_spectrum")
+_PLAN_OPTS = ("prec", "tau", "L", "Q", "tile", "extent", "store_spectrum", "lengths")
 
 
 def _workspace(nbytes: int, device, ws=None) -> torch.Tensor:

@@ -132,6 +132,21 @@ def test_plan_stored_spectrum_workspace(d, M):
     assert K.kde_plan_query(one.H, one.n, g1, store_spectrum=True) == K.kde_plan_query(one.H, one.n, g1)
 
 
+def test_plan_length_options():
+    """kde_params.lengths: 0 = 2^k (3 x 2^k in 3-D and 4-D where shorter), 1 = 3 x 2^k also
+    in 2-D, 2 = 2^k only; other values are rejected."""
+    w2, w3 = W.mix2d_512(n=10_000), W.mix3d_128(n=10_000)
+    for w, auto, comp, pow2 in ((w2, (1024, 1024), (768, 768), (1024, 1024)),
+                                (w3, (192, 192, 192), (192, 192, 192), (256, 256, 256))):
+        g = (w.lo, w.hi, w.M)
+        assert K.kde_plan_query(w.H, w.n, g)["P"] == auto
+        assert K.kde_plan_query(w.H, w.n, g, lengths="composite")["P"] == comp
+        assert K.kde_plan_query(w.H, w.n, g, lengths="pow2")["P"] == pow2
+    one = W.small_mixture(411, 1, 5_000, (300,))
+    assert K.kde_plan_query(one.H, one.n, (one.lo, one.hi, one.M), lengths="composite")["P"] == (512,)
+    assert _code(w2.H, w2.n, (w2.lo, w2.hi, w2.M), lengths=3) == -1
+
+
 def test_stored_spectrum_rejections():
     """store_spectrum takes 0 or 1, and batches refuse it."""
     H = np.array([[0.09, 0.06], [0.06, 0.08]])

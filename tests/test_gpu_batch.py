@@ -56,6 +56,25 @@ def test_batch_matches_single_bit_identical(prec):
     assert info["launches"] == 4 + 3 * len(p1) + len(p0)
 
 
+def test_batch_composite_lengths_match_single_calls():
+    """With kde_params.lengths = composite the 2-D items pad to 3 x 2^k where shorter (side
+    512: P = 768); the batch gives the bits of single calls with the same option, and the
+    oracle's estimate within the FP32 bound."""
+    wl = W.batch2d(6, seed_offset=21, n_range=(1e3, 3e4), sides=(64, 128, 256))
+    wl.append(W.mix2d_512(n=200_000, seed_offset=6))
+    items = _items(wl)
+    B = K.KdeBatch(items, n_dropped=True, prec="f32", lengths="composite")
+    B.eval()
+    torch.cuda.synchronize()
+    _assert_matches_single(B, items, prec="f32", lengths="composite")
+    assert K.kde_plan_query(wl[-1].H, wl[-1].n, (wl[-1].lo, wl[-1].hi, wl[-1].M), lengths="composite")["P"] == (768, 768)
+    for i in (0, len(wl) - 1):
+        w = wl[i]
+        f, _ = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M, method="fft" if w.M[0] > 256 else "direct")
+        got = B.densities[i].cpu().numpy()
+        assert np.max(np.abs(got - f)) <= 1e-5 * np.max(np.abs(f)), i
+
+
 def test_batch_matches_oracle():
     wl = W.batch2d(6, seed_offset=12, n_range=(500, 4000), sides=(64, 96))
     wl.append(W.mix2d_512(n=100_000, seed_offset=7))        # 512^2: P = 1024 row and column passes

@@ -348,6 +348,22 @@ def test_stored_spectrum_matches_default(prec, d, M):
         assert _rel(got.cpu().numpy(), f) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("d,M,lengths,P", [(2, (300, 257), "composite", (384, 384)),
+                                           (3, (48, 40, 36), "pow2", (64, 64, 64)),
+                                           (3, (48, 40, 36), "composite", (64, 48, 48))])
+def test_eval_length_options(prec, d, M, lengths, P):
+    """kde_params.lengths (3 x 2^k also in 2-D, or 2^k only) changes the padded lengths and
+    not the estimate beyond rounding."""
+    w = W.small_mixture(600 + d, d, 40_000, M, ratio=(1.0, 20.0))
+    g = (w.lo, w.hi, w.M)
+    assert K.kde_plan_query(w.H, w.n, g, lengths=lengths)["P"] == P
+    got = K.kde_eval(_dev(w.X), w.H, g, prec=prec, lengths=lengths)[0]
+    torch.cuda.synchronize()
+    f, _ = O.kde_binned(w.X, w.H, w.lo, w.hi, w.M)
+    assert _rel(got.cpu().numpy(), f) <= TOL[prec]
+
+
 @pytest.fixture(scope="module")
 def ref2d512():
     w = W.mix2d_512()
