@@ -109,8 +109,9 @@ typedef struct kde_params {
     int32_t lengths;          /* padded FFT lengths P_k (kde_plan.P): 0 (default) 2^j, or in 3-D
                                  and 4-D 3 x 2^j when shorter; 1: 3 x 2^j also in 2-D (pays in
                                  batches of 2-D problems, whose launches hold many lines; single
-                                 2-D problems are faster with 0); 2: 2^j only. Any value gives
-                                 the estimate of Eq. (7) up to rounding */
+                                 2-D problems are faster with 0); 2: 2^j only; other values:
+                                 KDE_ERR_ARG. Any value gives the estimate of Eq. (7) up to
+                                 rounding */
     int32_t trace_capacity;   /* optional per-kernel timing: number of events in
                                  trace_events, used in pairs */
     hipEvent_t* trace_events; /* if non-NULL: the i-th pass of the call (one kernel; the two
