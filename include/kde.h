@@ -325,7 +325,8 @@ typedef struct kde_batch_info {
     int32_t launches;         /* kernel launches per kde_batch_eval */
     size_t ws_bytes;          /* device workspace kde_batch_bind needs */
     int32_t tile[KDE_MAX_D];  /* binning tile in use (the autotuner may change it) */
-    int32_t narrow_mask;      /* bit log2(P): strided-axis passes of length P use 4 lines
+    int32_t narrow_mask;      /* bit ceil(log2 P) (3 x 2^j lengths share the bit of the next
+                                 power of two): strided-axis passes of length P use 4 lines
                                  per workgroup (else the widest shape) */
 } kde_batch_info;
 

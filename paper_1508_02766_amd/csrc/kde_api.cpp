@@ -699,7 +699,7 @@ Pass row_c2r_pass(const Plan& pl, int P, const void* in, int64_t nrows, int64_t 
 }
 
 // nmask < 0: workgroup shape chosen at launch from its size; else bit
-// log2(P) of nmask selects the narrow shape for length P.
+// ceil(log2 P) of nmask selects the narrow shape for length P.
 Pass cols_pass(const Plan& pl, int P, int mode, const kde::ColArgs& a, int nmask, int order, const char* name) {
     int lg = 0;
     while ((1 << lg) < P) ++lg;
@@ -1146,7 +1146,7 @@ struct kde_batch {
     kde_params prm{};
     bool has_prm = false;
     int tile[kde::kMaxD] = {};     // binning tile of the current configuration (0: default)
-    int narrow_mask = 0;           // bit log2(P): narrow strided passes of length P
+    int narrow_mask = 0;           // bit ceil(log2 P): narrow strided passes of length P
     std::vector<Plan> plans;
     std::vector<size_t> inst_off;  // per item: offset of its eval workspace in ws
     std::vector<char> internal;    // per item: density and dot live in the workspace (LSCV batches)
